@@ -1,0 +1,750 @@
+// bssn_oracle.cpp -- CPU reference of the BSSN right-hand side and RK4 step.
+//
+// TEST INFRASTRUCTURE ONLY.  This is the plain, slow, FP64 oracle that the HIP
+// library is checked against.  Only the test suite, the smoke check and the
+// benchmark's CPU-baseline leg load it; the library never links or calls it,
+// and it shares no source, header or table with the library.
+//
+// What it computes (Chemora, arXiv:1307.6488): the paper's showcase is the
+// McLachlan BSSN evolution code -- the Einstein equations in BSSN form with
+// high-order finite differences (section "Scientific Motivation"), 8th-order
+// partially upwinded stencils needing 5 ghost zones and a Runge-Kutta time
+// integrator (section "Binary Black Hole Simulations", timer table: RHS
+// derivatives / advection / evaluations, boundary condition, time-integrator
+// copy).  The paper cites but does not print the equations; they are taken
+// here from the formulation it cites (Nakamura 1987; Shibata & Nakamura 1995;
+// Baumgarte & Shapiro 1998; Alcubierre et al. 1999/2003), in the chi variant
+// with 1+log slicing and the advective Gamma-driver shift used by moving-
+// puncture codes, plus Kreiss-Oliger dissipation (Kreiss & Oliger 1973).
+//
+// Style: every operator is a direct transcription of its definition, tensor
+// sums are explicit loops over 3x3 arrays, nothing is fused or reordered for
+// speed.  The scalar type is a template parameter so the same code, run on a
+// counting scalar, reports the exact number of floating-point operations per
+// grid point (+, -, *, /; no FMA).  Build: g++ -O2 -ffp-contract=off.
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+extern "C" {
+
+typedef struct {
+  int32_t fd_order;   // 4 or 8
+  int32_t ghost;      // ghost width of the arrays
+  int32_t upwind;     // 1: lopsided advection stencils, 0: centred
+  int32_t ko_radius;  // Kreiss-Oliger radius r, 0 = off
+  double eps_diss;    // Kreiss-Oliger strength
+  int32_t lapse;      // 0 1+log, 1 harmonic, 2 frozen
+  int32_t shift;      // 0 Gamma-driver, 1 frozen
+  double eta;         // Gamma-driver damping
+  int32_t bc;         // 0 static ghosts, 1 periodic
+  int32_t nthreads;   // OpenMP threads (<= 0: runtime default)
+} oracle_params;
+
+typedef struct {
+  int32_t n[3];       // interior extents
+  int32_t ghost;
+  int64_t sy, sz, sf; // element strides (x stride 1)
+  double h;           // grid spacing
+} oracle_grid;
+
+}  // extern "C"
+
+namespace {
+
+enum {
+  CHI = 0, GT = 1, TRK = 7, AT = 8, XT = 14, ALPHA = 17, BETA = 18, BDRV = 21, NGF = 24
+};
+const int SYM[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+// pairs (a,b) of the 6 packed second-derivative slots
+const int PAIR[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+
+// ---------------------------------------------------------------------------
+// counting scalar
+// ---------------------------------------------------------------------------
+struct Counted {
+  double v;
+  static long long nadd, nmul, ndiv;
+  Counted() : v(0.0) {}
+  Counted(double x) : v(x) {}
+};
+long long Counted::nadd = 0, Counted::nmul = 0, Counted::ndiv = 0;
+inline Counted operator+(Counted a, Counted b) { ++Counted::nadd; return Counted(a.v + b.v); }
+inline Counted operator-(Counted a, Counted b) { ++Counted::nadd; return Counted(a.v - b.v); }
+inline Counted operator*(Counted a, Counted b) { ++Counted::nmul; return Counted(a.v * b.v); }
+inline Counted operator/(Counted a, Counted b) { ++Counted::ndiv; return Counted(a.v / b.v); }
+inline Counted operator-(Counted a) { return Counted(-a.v); }
+inline bool nonneg(Counted a) { return a.v >= 0.0; }
+inline bool nonneg(double a) { return a >= 0.0; }
+
+// ---------------------------------------------------------------------------
+// finite-difference weights.  Centred weights are the classical 4th/8th-order
+// ones (Fornberg 1988); the lopsided (partially upwinded) ones use offsets
+// -1..3 (order 4) and -3..5 (order 8) for a non-negative advecting velocity.
+// Every operator is applied to differences u_{+k} - u_0 so that a constant
+// field gives exactly zero.
+// ---------------------------------------------------------------------------
+struct Weights {
+  int order;
+  int nc;          // number of centred offsets (order/2)
+  double c1[4];    // first derivative, offsets 1..nc (antisymmetric)
+  double c2[4];    // second derivative, offsets 1..nc (symmetric)
+  int up_lo, up_hi;
+  double up[9];    // lopsided weights for offsets up_lo..up_hi (entry for 0 unused)
+};
+
+Weights make_weights(int order) {
+  Weights w;
+  std::memset(&w, 0, sizeof w);
+  w.order = order;
+  w.nc = order / 2;
+  if (order == 4) {
+    w.c1[0] = 2.0 / 3.0;  w.c1[1] = -1.0 / 12.0;
+    w.c2[0] = 4.0 / 3.0;  w.c2[1] = -1.0 / 12.0;
+    w.up_lo = -1; w.up_hi = 3;
+    const double u4[5] = {-3.0 / 12.0, -10.0 / 12.0, 18.0 / 12.0, -6.0 / 12.0, 1.0 / 12.0};
+    for (int i = 0; i < 5; ++i) w.up[i] = u4[i];
+  } else {
+    w.c1[0] = 4.0 / 5.0;  w.c1[1] = -1.0 / 5.0;  w.c1[2] = 4.0 / 105.0;  w.c1[3] = -1.0 / 280.0;
+    w.c2[0] = 8.0 / 5.0;  w.c2[1] = -1.0 / 5.0;  w.c2[2] = 8.0 / 315.0;  w.c2[3] = -1.0 / 560.0;
+    w.up_lo = -3; w.up_hi = 5;
+    const double u8[9] = {-1.0 / 168.0, 1.0 / 14.0, -1.0 / 2.0, -9.0 / 20.0, 5.0 / 4.0,
+                          -1.0 / 2.0, 1.0 / 6.0, -1.0 / 28.0, 1.0 / 280.0};
+    for (int i = 0; i < 9; ++i) w.up[i] = u8[i];
+  }
+  return w;
+}
+
+double binom(int n, int k) {
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// Pointwise operators on one grid function.  f points at the evaluation point,
+// s is the element stride along the differentiation axis.
+template <class R>
+R op_d1(const double* f, long s, const Weights& w, R inv_h) {
+  R acc = R(0.0);
+  for (int k = 1; k <= w.nc; ++k) acc = acc + R(w.c1[k - 1]) * (R(f[k * s]) - R(f[-k * s]));
+  return acc * inv_h;
+}
+
+template <class R>
+R op_d2(const double* f, long s, const Weights& w, R inv_h2) {
+  R acc = R(0.0);
+  const R c = R(f[0]);
+  for (int k = 1; k <= w.nc; ++k)
+    acc = acc + R(w.c2[k - 1]) * ((R(f[k * s]) - c) + (R(f[-k * s]) - c));
+  return acc * inv_h2;
+}
+
+// mixed derivative d_a d_b: outer first derivative (stride sa) of inner first
+// derivatives (stride sb), the inner differences formed at each outer offset.
+template <class R>
+R op_d11(const double* f, long sa, long sb, const Weights& w, R inv_h) {
+  R acc = R(0.0);
+  for (int k = 1; k <= w.nc; ++k) {
+    R dp = op_d1<R>(f + k * sa, sb, w, inv_h);
+    R dm = op_d1<R>(f - k * sa, sb, w, inv_h);
+    acc = acc + R(w.c1[k - 1]) * (dp - dm);
+  }
+  return acc * inv_h;
+}
+
+// lopsided first derivative; positive = stencil shifted toward +axis (used
+// for a non-negative advecting velocity), else the mirror image.
+template <class R>
+R op_upwind(const double* f, long s, const Weights& w, bool positive, R inv_h) {
+  R acc = R(0.0);
+  const R c = R(f[0]);
+  for (int o = w.up_lo; o <= w.up_hi; ++o) {
+    if (o == 0) continue;
+    const double wt = w.up[o - w.up_lo];
+    if (positive)
+      acc = acc + R(wt) * (R(f[o * s]) - c);
+    else
+      acc = acc - R(wt) * (R(f[-o * s]) - c);
+  }
+  return acc * inv_h;
+}
+
+// Kreiss-Oliger dissipation along one axis with radius r:
+//   Q u = (-1)^(r+1) eps / (2^(2r) h) * sum_m (-1)^m C(2r, m) u_{i + r - m},
+// written on the symmetric differences u_{+k} + u_{-k} - 2 u_0.
+template <class R>
+R op_ko(const double* f, long s, int r, R eps_over_h) {
+  R acc = R(0.0);
+  const R c = R(f[0]);
+  const double scale = std::ldexp(1.0, -2 * r);
+  for (int k = 1; k <= r; ++k) {
+    double coef = binom(2 * r, r + k) * scale * (((k + 1) % 2 == 0) ? 1.0 : -1.0);
+    acc = acc + R(coef) * ((R(f[k * s]) - c) + (R(f[-k * s]) - c));
+  }
+  return acc * eps_over_h;
+}
+
+// ---------------------------------------------------------------------------
+// pointwise right-hand side.  Inputs: the 24 values, first derivatives
+// d1[f][k] = d_k u_f, second derivatives d2[f][slot] (slot as in PAIR),
+// advection terms adv[f] = beta^k D_k u_f and dissipation diss[f].
+// ---------------------------------------------------------------------------
+struct Opts {
+  int lapse, shift;
+  double eta;
+};
+
+template <class R>
+struct Geometry {
+  R gt[3][3], gtu[3][3];       // conformal metric and inverse
+  R Gl[3][3][3];               // Gt_{k,ij}  (first index lowered)
+  R Gu[3][3][3];               // Gt^k_{ij}
+  R Xtd[3];                    // Gt^k computed from the metric
+  R Ric[3][3];                 // physical Ricci tensor R_ij
+};
+
+// steps 1-5: inverse metric, Christoffels, Ricci tensor
+template <class R>
+void geometry(const R u[NGF], const R d1[NGF][3], const R d2[NGF][6], Geometry<R>& G) {
+  const R half = R(0.5);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) G.gt[i][j] = u[GT + SYM[i][j]];
+
+  // inverse by cofactors / determinant (no unit-determinant assumption)
+  const R(&g)[3][3] = G.gt;
+  R cof[3][3];
+  cof[0][0] = g[1][1] * g[2][2] - g[1][2] * g[2][1];
+  cof[0][1] = g[0][2] * g[2][1] - g[0][1] * g[2][2];
+  cof[0][2] = g[0][1] * g[1][2] - g[0][2] * g[1][1];
+  cof[1][1] = g[0][0] * g[2][2] - g[0][2] * g[2][0];
+  cof[1][2] = g[0][2] * g[1][0] - g[0][0] * g[1][2];
+  cof[2][2] = g[0][0] * g[1][1] - g[0][1] * g[1][0];
+  // expansion along the first row; the adjugate of a symmetric matrix is symmetric
+  R det = g[0][0] * cof[0][0] + g[0][1] * cof[0][1] + g[0][2] * cof[0][2];
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j) {
+      G.gtu[i][j] = cof[i][j] / det;
+      G.gtu[j][i] = G.gtu[i][j];
+    }
+
+  // dg[m][a][b] = d_m gt_ab
+  R dg[3][3][3];
+  for (int m = 0; m < 3; ++m)
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) dg[m][a][b] = d1[GT + SYM[a][b]][m];
+
+  // Gt_{k,ij} = 1/2 (d_j gt_ki + d_i gt_kj - d_k gt_ij)
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < 3; ++i)
+      for (int j = i; j < 3; ++j) {
+        G.Gl[k][i][j] = half * (dg[j][k][i] + dg[i][k][j] - dg[k][i][j]);
+        G.Gl[k][j][i] = G.Gl[k][i][j];
+      }
+  // Gt^k_{ij} = gtu^{kl} Gt_{l,ij}
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < 3; ++i)
+      for (int j = i; j < 3; ++j) {
+        R s = R(0.0);
+        for (int l = 0; l < 3; ++l) s = s + G.gtu[k][l] * G.Gl[l][i][j];
+        G.Gu[k][i][j] = s;
+        G.Gu[k][j][i] = s;
+      }
+  // Gt^k computed: gtu^{ij} Gt^k_{ij}
+  for (int k = 0; k < 3; ++k) {
+    R s = R(0.0);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) s = s + G.gtu[i][j] * G.Gu[k][i][j];
+    G.Xtd[k] = s;
+  }
+
+  // conformal Ricci tensor
+  R Rt[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j) {
+      R s = R(0.0);
+      // -1/2 gtu^{lm} d_l d_m gt_ij
+      for (int l = 0; l < 3; ++l)
+        for (int m = 0; m < 3; ++m) s = s - half * G.gtu[l][m] * d2[GT + SYM[i][j]][SYM[l][m]];
+      // +1/2 (gt_ki d_j Gt^k + gt_kj d_i Gt^k), Gt^k the evolved variable
+      for (int k = 0; k < 3; ++k)
+        s = s + half * (G.gt[k][i] * d1[XT + k][j] + G.gt[k][j] * d1[XT + k][i]);
+      // +1/2 Gtd^k (Gt_{i,jk} + Gt_{j,ik})
+      for (int k = 0; k < 3; ++k) s = s + half * G.Xtd[k] * (G.Gl[i][j][k] + G.Gl[j][i][k]);
+      // + gtu^{lm} (Gt^k_li Gt_{j,km} + Gt^k_lj Gt_{i,km} + Gt^k_im Gt_{k,lj})
+      for (int l = 0; l < 3; ++l)
+        for (int m = 0; m < 3; ++m)
+          for (int k = 0; k < 3; ++k)
+            s = s + G.gtu[l][m] * (G.Gu[k][l][i] * G.Gl[j][k][m] + G.Gu[k][l][j] * G.Gl[i][k][m] +
+                                   G.Gu[k][i][m] * G.Gl[k][l][j]);
+      Rt[i][j] = s;
+    }
+
+  // conformal-factor part of the Ricci tensor
+  const R chi = u[CHI];
+  R cddchi[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j) {
+      R s = d2[CHI][SYM[i][j]];
+      for (int k = 0; k < 3; ++k) s = s - G.Gu[k][i][j] * d1[CHI][k];
+      cddchi[i][j] = s;
+      cddchi[j][i] = s;
+    }
+  R trc = R(0.0), dchi2 = R(0.0);
+  for (int l = 0; l < 3; ++l)
+    for (int m = 0; m < 3; ++m) {
+      trc = trc + G.gtu[l][m] * cddchi[l][m];
+      dchi2 = dchi2 + G.gtu[l][m] * d1[CHI][l] * d1[CHI][m];
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j) {
+      R rchi = (cddchi[i][j] + G.gt[i][j] * trc) / (R(2.0) * chi) -
+               (d1[CHI][i] * d1[CHI][j] + R(3.0) * G.gt[i][j] * dchi2) / (R(4.0) * chi * chi);
+      G.Ric[i][j] = Rt[i][j] + rchi;
+      G.Ric[j][i] = G.Ric[i][j];
+    }
+}
+
+template <class R>
+void rhs_point(const Opts& P, const R u[NGF], const R d1[NGF][3], const R d2[NGF][6],
+               const R adv[NGF], const R diss[NGF], R rhs[NGF]) {
+  Geometry<R> G;
+  geometry<R>(u, d1, d2, G);
+  const R third = R(1.0 / 3.0), two3 = R(2.0 / 3.0), two = R(2.0);
+
+  const R chi = u[CHI], K = u[TRK], alpha = u[ALPHA];
+  R At[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) At[i][j] = u[AT + SYM[i][j]];
+  // db[i][k] = d_k beta^i
+  R db[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) db[i][k] = d1[BETA + i][k];
+  R divb = db[0][0] + db[1][1] + db[2][2];
+
+  // At^i_j and At^{ij}
+  R Atm[3][3], Atu[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      R s = R(0.0);
+      for (int k = 0; k < 3; ++k) s = s + G.gtu[i][k] * At[k][j];
+      Atm[i][j] = s;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j) {
+      R s = R(0.0);
+      for (int k = 0; k < 3; ++k) s = s + Atm[i][k] * G.gtu[k][j];
+      Atu[i][j] = s;
+      Atu[j][i] = s;
+    }
+  R AA = R(0.0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) AA = AA + Atm[i][j] * Atm[j][i];
+
+  // physical Christoffel symbols and D_i D_j alpha
+  R gtu_dchi[3];
+  for (int k = 0; k < 3; ++k) {
+    R s = R(0.0);
+    for (int l = 0; l < 3; ++l) s = s + G.gtu[k][l] * d1[CHI][l];
+    gtu_dchi[k] = s;
+  }
+  R DDa[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j) {
+      R s = d2[ALPHA][SYM[i][j]];
+      for (int k = 0; k < 3; ++k) {
+        R corr = G.gt[i][j] * gtu_dchi[k];
+        if (k == i) corr = corr - d1[CHI][j];
+        if (k == j) corr = corr - d1[CHI][i];
+        // Gamma^k_ij = Gt^k_ij + corr / (2 chi)
+        R Gam = G.Gu[k][i][j] + corr / (two * chi);
+        s = s - Gam * d1[ALPHA][k];
+      }
+      DDa[i][j] = s;
+      DDa[j][i] = s;
+    }
+  R LapA = R(0.0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) LapA = LapA + G.gtu[i][j] * DDa[i][j];
+  LapA = chi * LapA;
+
+  // trace-free part of -D_i D_j alpha + alpha R_ij
+  R X[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j) {
+      X[i][j] = alpha * G.Ric[i][j] - DDa[i][j];
+      X[j][i] = X[i][j];
+    }
+  R trX = R(0.0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) trX = trX + G.gtu[i][j] * X[i][j];
+
+  // chi
+  rhs[CHI] = adv[CHI] + two3 * chi * (alpha * K - divb);
+  // gt_ij and At_ij
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j) {
+      const int s = SYM[i][j];
+      R lie_g = R(0.0), lie_a = R(0.0), AtAt = R(0.0);
+      for (int k = 0; k < 3; ++k) {
+        lie_g = lie_g + G.gt[i][k] * db[k][j] + G.gt[j][k] * db[k][i];
+        lie_a = lie_a + At[i][k] * db[k][j] + At[j][k] * db[k][i];
+        AtAt = AtAt + At[i][k] * Atm[k][j];
+      }
+      rhs[GT + s] = adv[GT + s] - two * alpha * At[i][j] + lie_g - two3 * G.gt[i][j] * divb;
+      R XTF = X[i][j] - third * G.gt[i][j] * trX;
+      rhs[AT + s] = adv[AT + s] + chi * XTF + alpha * (K * At[i][j] - two * AtAt) + lie_a -
+                    two3 * At[i][j] * divb;
+    }
+  // K
+  rhs[TRK] = adv[TRK] - LapA + alpha * (AA + third * K * K);
+
+  // Gt^i (without advection first; the Gamma-driver reuses it)
+  R Xt_src[3];
+  for (int i = 0; i < 3; ++i) {
+    R s = R(0.0);
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) s = s + G.gtu[j][k] * d2[BETA + i][SYM[j][k]];
+    R ddiv = R(0.0);  // gtu^{ij} d_j d_k beta^k
+    for (int j = 0; j < 3; ++j) {
+      R dj_div = R(0.0);
+      for (int k = 0; k < 3; ++k) dj_div = dj_div + d2[BETA + k][SYM[j][k]];
+      ddiv = ddiv + G.gtu[i][j] * dj_div;
+    }
+    s = s + third * ddiv;
+    for (int j = 0; j < 3; ++j) s = s - G.Xtd[j] * db[i][j];
+    s = s + two3 * G.Xtd[i] * divb;
+    R t = R(0.0);
+    for (int j = 0; j < 3; ++j) s = s - two * Atu[i][j] * d1[ALPHA][j];
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) t = t + G.Gu[i][j][k] * Atu[j][k];
+    R tchi = R(0.0), tK = R(0.0);
+    for (int j = 0; j < 3; ++j) {
+      tchi = tchi + Atu[i][j] * d1[CHI][j];
+      tK = tK + G.gtu[i][j] * d1[TRK][j];
+    }
+    t = t - R(1.5) * tchi / chi - two3 * tK;
+    s = s + two * alpha * t;
+    Xt_src[i] = s;
+    rhs[XT + i] = adv[XT + i] + s;
+  }
+
+  // lapse
+  if (P.lapse == 0)
+    rhs[ALPHA] = adv[ALPHA] - two * alpha * K;
+  else if (P.lapse == 1)
+    rhs[ALPHA] = adv[ALPHA] - alpha * alpha * K;
+  else
+    rhs[ALPHA] = R(0.0);
+  // shift
+  for (int i = 0; i < 3; ++i) {
+    if (P.shift == 0) {
+      rhs[BETA + i] = adv[BETA + i] + R(0.75) * u[BDRV + i];
+      rhs[BDRV + i] = adv[BDRV + i] + Xt_src[i] - R(P.eta) * u[BDRV + i];
+    } else {
+      rhs[BETA + i] = R(0.0);
+      rhs[BDRV + i] = R(0.0);
+    }
+  }
+  // dissipation on every evolved variable
+  for (int f = 0; f < NGF; ++f) {
+    if (f == ALPHA && P.lapse == 2) continue;
+    if ((f >= BETA) && P.shift == 1) continue;
+    rhs[f] = rhs[f] + diss[f];
+  }
+}
+
+// Hamiltonian constraint H = chi gtu^{ij} R_ij + 2/3 K^2 - At^i_j At^j_i
+template <class R>
+R ham_point(const R u[NGF], const R d1[NGF][3], const R d2[NGF][6]) {
+  Geometry<R> G;
+  geometry<R>(u, d1, d2, G);
+  R trR = R(0.0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) trR = trR + G.gtu[i][j] * G.Ric[i][j];
+  R Atm[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      R s = R(0.0);
+      for (int k = 0; k < 3; ++k) s = s + G.gtu[i][k] * u[AT + SYM[k][j]];
+      Atm[i][j] = s;
+    }
+  R AA = R(0.0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) AA = AA + Atm[i][j] * Atm[j][i];
+  return u[CHI] * trR + R(2.0 / 3.0) * u[TRK] * u[TRK] - AA;
+}
+
+// which GFs need first / second derivatives
+bool needs_d1(int f) { return !((f >= AT && f < AT + 6) || f >= BDRV); }
+bool needs_d2(int f) { return f == CHI || (f >= GT && f < GT + 6) || f == ALPHA || (f >= BETA && f < BETA + 3); }
+
+// ---------------------------------------------------------------------------
+// grid-point gather: every stencil the right-hand side needs at one point
+// ---------------------------------------------------------------------------
+template <class R>
+struct Point {
+  R u[NGF], d1[NGF][3], d2[NGF][6], adv[NGF], diss[NGF];
+};
+
+template <class R>
+void gather(const oracle_params& P, const oracle_grid& g, const Weights& w, const double* u, long idx,
+            bool want_rhs_terms, Point<R>& pt) {
+  const long st[3] = {1, g.sy, g.sz};
+  const R inv_h = R(1.0 / g.h), inv_h2 = R(1.0 / (g.h * g.h));
+  for (int f = 0; f < NGF; ++f) {
+    const double* p = u + f * g.sf + idx;
+    pt.u[f] = R(p[0]);
+    for (int k = 0; k < 3; ++k) pt.d1[f][k] = R(0.0);
+    for (int s = 0; s < 6; ++s) pt.d2[f][s] = R(0.0);
+    if (needs_d1(f) || (want_rhs_terms && !P.upwind))
+      for (int k = 0; k < 3; ++k) pt.d1[f][k] = op_d1<R>(p, st[k], w, inv_h);
+    if (needs_d2(f))
+      for (int s = 0; s < 6; ++s) {
+        const int a = PAIR[s][0], b = PAIR[s][1];
+        pt.d2[f][s] = (a == b) ? op_d2<R>(p, st[a], w, inv_h2) : op_d11<R>(p, st[a], st[b], w, inv_h);
+      }
+  }
+  if (!want_rhs_terms) return;
+  const R beta[3] = {pt.u[BETA], pt.u[BETA + 1], pt.u[BETA + 2]};
+  const R eps_over_h = R(P.eps_diss / g.h);
+  for (int f = 0; f < NGF; ++f) {
+    const double* p = u + f * g.sf + idx;
+    R a = R(0.0);
+    for (int k = 0; k < 3; ++k) {
+      R dk = P.upwind ? op_upwind<R>(p, st[k], w, nonneg(beta[k]), inv_h) : pt.d1[f][k];
+      a = a + beta[k] * dk;
+    }
+    pt.adv[f] = a;
+    R d = R(0.0);
+    if (P.ko_radius > 0)
+      for (int k = 0; k < 3; ++k) d = d + op_ko<R>(p, st[k], P.ko_radius, eps_over_h);
+    pt.diss[f] = d;
+  }
+}
+
+int check(const oracle_params* P, const oracle_grid* g) {
+  if (!P || !g) return -1;
+  if (P->fd_order != 4 && P->fd_order != 8) return -1;
+  int need = P->fd_order / 2;
+  if (P->upwind) need = need > P->fd_order / 2 + 1 ? need : P->fd_order / 2 + 1;
+  if (P->ko_radius > need) need = P->ko_radius;
+  if (g->ghost < need || g->h <= 0.0) return -1;
+  for (int a = 0; a < 3; ++a)
+    if (g->n[a] < 1) return -1;
+  if (g->sy < g->n[0] + 2 * g->ghost || g->sz < g->sy * (g->n[1] + 2 * g->ghost) ||
+      g->sf < g->sz * (g->n[2] + 2 * g->ghost))
+    return -1;
+  return 0;
+}
+
+void set_threads(const oracle_params* P) {
+#ifdef _OPENMP
+  if (P->nthreads > 0) omp_set_num_threads(P->nthreads);
+#endif
+}
+
+long at(const oracle_grid& g, int i, int j, int k) {
+  return (long)(k + g.ghost) * g.sz + (long)(j + g.ghost) * g.sy + (i + g.ghost);
+}
+
+void rhs_grid(const oracle_params& P, const oracle_grid& g, const double* u, double* rhs) {
+  const Weights w = make_weights(P.fd_order);
+  const Opts o = {P.lapse, P.shift, P.eta};
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k < g.n[2]; ++k) {
+    Point<double> pt;
+    double r[NGF];
+    for (int j = 0; j < g.n[1]; ++j)
+      for (int i = 0; i < g.n[0]; ++i) {
+        const long idx = at(g, i, j, k);
+        gather<double>(P, g, w, u, idx, true, pt);
+        rhs_point<double>(o, pt.u, pt.d1, pt.d2, pt.adv, pt.diss, r);
+        for (int f = 0; f < NGF; ++f) rhs[f * g.sf + idx] = r[f];
+      }
+  }
+}
+
+// periodic images into every ghost point (edges and corners included)
+void fill_periodic(const oracle_grid& g, double* u) {
+  const int G = g.ghost;
+#pragma omp parallel for schedule(static)
+  for (int k = -G; k < g.n[2] + G; ++k)
+    for (int j = -G; j < g.n[1] + G; ++j)
+      for (int i = -G; i < g.n[0] + G; ++i) {
+        const bool inside = i >= 0 && i < g.n[0] && j >= 0 && j < g.n[1] && k >= 0 && k < g.n[2];
+        if (inside) continue;
+        const int ii = ((i % g.n[0]) + g.n[0]) % g.n[0];
+        const int jj = ((j % g.n[1]) + g.n[1]) % g.n[1];
+        const int kk = ((k % g.n[2]) + g.n[2]) % g.n[2];
+        for (int f = 0; f < NGF; ++f) u[f * g.sf + at(g, i, j, k)] = u[f * g.sf + at(g, ii, jj, kk)];
+      }
+}
+
+// out = base + c * k on interior points
+void axpy_interior(const oracle_grid& g, const double* base, double c, const double* k, double* out) {
+#pragma omp parallel for schedule(static)
+  for (int kz = 0; kz < g.n[2]; ++kz)
+    for (int f = 0; f < NGF; ++f)
+      for (int j = 0; j < g.n[1]; ++j)
+        for (int i = 0; i < g.n[0]; ++i) {
+          const long idx = f * g.sf + at(g, i, j, kz);
+          out[idx] = base[idx] + c * k[idx];
+        }
+}
+
+}  // namespace
+
+extern "C" {
+
+int oracle_required_ghost(int order, int upwind, int ko_radius) {
+  int need = order / 2;
+  if (upwind && order / 2 + 1 > need) need = order / 2 + 1;
+  return ko_radius > need ? ko_radius : need;
+}
+
+// Right-hand side at every interior point; ghost entries of rhs are untouched.
+int oracle_rhs(const oracle_params* P, const oracle_grid* g, const double* u, double* rhs) {
+  if (check(P, g) || !u || !rhs) return -1;
+  set_threads(P);
+  rhs_grid(*P, *g, u, rhs);
+  return 0;
+}
+
+// nsteps classic RK4 steps, u advanced in place.  Stage inputs take their
+// ghosts from u (static) or from periodic images (periodic).
+int oracle_rk4(const oracle_params* P, const oracle_grid* g, double dt, int nsteps, double* u) {
+  if (check(P, g) || !u || !(dt > 0.0) || nsteps < 0) return -1;
+  set_threads(P);
+  const size_t N = (size_t)g->sf * NGF;
+  std::vector<double> k1(N, 0.0), k2(N, 0.0), k3(N, 0.0), k4(N, 0.0), s(u, u + N);
+  for (int step = 0; step < nsteps; ++step) {
+    rhs_grid(*P, *g, u, k1.data());
+    std::memcpy(s.data(), u, N * sizeof(double));   // ghosts of the stage input
+    axpy_interior(*g, u, 0.5 * dt, k1.data(), s.data());
+    if (P->bc == 1) fill_periodic(*g, s.data());
+    rhs_grid(*P, *g, s.data(), k2.data());
+    axpy_interior(*g, u, 0.5 * dt, k2.data(), s.data());
+    if (P->bc == 1) fill_periodic(*g, s.data());
+    rhs_grid(*P, *g, s.data(), k3.data());
+    axpy_interior(*g, u, dt, k3.data(), s.data());
+    if (P->bc == 1) fill_periodic(*g, s.data());
+    rhs_grid(*P, *g, s.data(), k4.data());
+    const oracle_grid& G = *g;
+#pragma omp parallel for schedule(static)
+    for (int kz = 0; kz < G.n[2]; ++kz)
+      for (int f = 0; f < NGF; ++f)
+        for (int j = 0; j < G.n[1]; ++j)
+          for (int i = 0; i < G.n[0]; ++i) {
+            const long idx = f * G.sf + at(G, i, j, kz);
+            u[idx] = u[idx] + (dt / 6.0) * (k1[idx] + 2.0 * k2[idx] + 2.0 * k3[idx] + k4[idx]);
+          }
+    if (P->bc == 1) fill_periodic(*g, u);
+  }
+  return 0;
+}
+
+int oracle_fill_periodic(const oracle_grid* g, double* u) {
+  if (!g || !u) return -1;
+  fill_periodic(*g, u);
+  return 0;
+}
+
+// Hamiltonian constraint at interior points into H (one GF with the grid's
+// strides; ghost entries untouched).
+int oracle_hamiltonian(const oracle_params* P, const oracle_grid* g, const double* u, double* H) {
+  if (check(P, g) || !u || !H) return -1;
+  set_threads(P);
+  const Weights w = make_weights(P->fd_order);
+  const oracle_grid G = *g;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k < G.n[2]; ++k) {
+    Point<double> pt;
+    for (int j = 0; j < G.n[1]; ++j)
+      for (int i = 0; i < G.n[0]; ++i) {
+        const long idx = at(G, i, j, k);
+        gather<double>(*P, G, w, u, idx, false, pt);
+        H[idx] = ham_point<double>(pt.u, pt.d1, pt.d2);
+      }
+  }
+  return 0;
+}
+
+// Pointwise algebra with caller-supplied derivatives (d1: 24x3, d2: 24x6 in
+// slot order xx xy xz yy yz zz, adv and diss: 24).
+int oracle_rhs_point(const oracle_params* P, const double* u, const double* d1, const double* d2,
+                     const double* adv, const double* diss, double* rhs) {
+  if (!P || !u || !d1 || !d2 || !adv || !diss || !rhs) return -1;
+  const Opts o = {P->lapse, P->shift, P->eta};
+  double D1[NGF][3], D2[NGF][6];
+  std::memcpy(D1, d1, sizeof D1);
+  std::memcpy(D2, d2, sizeof D2);
+  rhs_point<double>(o, u, D1, D2, adv, diss, rhs);
+  return 0;
+}
+
+int oracle_ham_point(const double* u, const double* d1, const double* d2, double* H) {
+  if (!u || !d1 || !d2 || !H) return -1;
+  double D1[NGF][3], D2[NGF][6];
+  std::memcpy(D1, d1, sizeof D1);
+  std::memcpy(D2, d2, sizeof D2);
+  *H = ham_point<double>(u, D1, D2);
+  return 0;
+}
+
+// One operator on one grid function at every interior point (for pinning the
+// stencils): op 0 = D1(axis a), 1 = D2(axis a), 2 = D_a D_b, 3 = lopsided
+// (+), 4 = lopsided (-), 5 = Kreiss-Oliger(axis a, radius r, eps).
+int oracle_apply_op(int op, int a, int b, int order, int r, double eps, const oracle_grid* g,
+                    const double* f, double* out) {
+  if (!g || !f || !out || (order != 4 && order != 8) || a < 0 || a > 2 || b < 0 || b > 2) return -1;
+  const Weights w = make_weights(order);
+  const oracle_grid G = *g;
+  const long st[3] = {1, G.sy, G.sz};
+  const double inv_h = 1.0 / G.h;
+  for (int k = 0; k < G.n[2]; ++k)
+    for (int j = 0; j < G.n[1]; ++j)
+      for (int i = 0; i < G.n[0]; ++i) {
+        const long idx = at(G, i, j, k);
+        const double* p = f + idx;
+        double v = 0.0;
+        switch (op) {
+          case 0: v = op_d1<double>(p, st[a], w, inv_h); break;
+          case 1: v = op_d2<double>(p, st[a], w, inv_h * inv_h); break;
+          case 2: v = op_d11<double>(p, st[a], st[b], w, inv_h); break;
+          case 3: v = op_upwind<double>(p, st[a], w, true, inv_h); break;
+          case 4: v = op_upwind<double>(p, st[a], w, false, inv_h); break;
+          case 5: v = op_ko<double>(p, st[a], r, eps / G.h); break;
+          default: return -1;
+        }
+        out[idx] = v;
+      }
+  return 0;
+}
+
+// Exact operation count of the right-hand side at one interior point
+// (counts[0] = additions/subtractions, [1] = multiplications, [2] = divisions),
+// counted by running the same code on a counting scalar.  Constants 1/h,
+// 1/h^2, eps/h are per-grid and not counted.
+int oracle_count_rhs_flops(const oracle_params* P, const oracle_grid* g, const double* u, int i, int j,
+                           int k, long long* counts) {
+  if (check(P, g) || !u || !counts) return -1;
+  const Weights w = make_weights(P->fd_order);
+  const Opts o = {P->lapse, P->shift, P->eta};
+  Point<Counted> pt;
+  Counted r[NGF];
+  Counted::nadd = Counted::nmul = Counted::ndiv = 0;
+  gather<Counted>(*P, *g, w, u, at(*g, i, j, k), true, pt);
+  rhs_point<Counted>(o, pt.u, pt.d1, pt.d2, pt.adv, pt.diss, r);
+  counts[0] = Counted::nadd;
+  counts[1] = Counted::nmul;
+  counts[2] = Counted::ndiv;
+  return 0;
+}
+
+}  // extern "C"
