@@ -1,0 +1,146 @@
+/* chemora.h -- C ABI of the MI355X (gfx950) BSSN right-hand-side library.
+ *
+ * The library evaluates the right-hand side of the BSSN form of the Einstein
+ * equations with high-order finite differences on a Cartesian patch, and
+ * advances a patch by classic fourth-order Runge-Kutta steps (Chemora,
+ * arXiv:1307.6488: the McLachlan BSSN evolution of section "Binary Black Hole
+ * Simulations" -- derivative, advection and evaluation kernels, boundary
+ * condition and time-integrator update -- and the per-point "numerical
+ * kernel over a local grid section with ghost zones filled outside the
+ * kernel" model of section "CaKernel Programming Abstractions").
+ *
+ * Conventions shared by every call
+ *  - Every entry point returns a chemora_status (0 = OK, < 0 = error) and
+ *    never aborts.  On error chemora_last_error() returns a thread-local,
+ *    NUL-terminated message owned by the library (valid until the next call
+ *    on the same thread).
+ *  - All argument checks run on the host before any HIP call; a call that
+ *    returns CHEMORA_EINVAL has enqueued no GPU work.
+ *  - Device pointers are plain HIP device addresses (e.g. a torch tensor's
+ *    data_ptr()); the caller owns and keeps them alive until the work has
+ *    completed on `stream`.  `stream` is a hipStream_t passed as void*
+ *    (NULL = the default stream).  Work is enqueued asynchronously; there is
+ *    no host synchronisation inside these calls.  Device faults surface at
+ *    the caller's next synchronisation.
+ *  - CHEMORA_EDEVICE reports a failed HIP launch/runtime call.
+ *
+ * State layout (one patch): 24 grid functions (GFs), FP64, structure of
+ * arrays.  Element (f, i, j, k) -- GF f, stored point (i, j, k) counted
+ * from the first ghost point -- sits at u[f*sf + k*sz + j*sy + i].  Each axis
+ * stores n[a] interior points plus `ghost` points on both sides; interior
+ * point (0,0,0) is stored at (ghost, ghost, ghost) and sits at `origin`,
+ * spacing h in all three directions.  Requirements:
+ *     sy >= n[0] + 2g,  sz >= sy*(n[1] + 2g),  sf >= sz*(n[2] + 2g),
+ *     sf*24 < 2^31 is NOT required (64-bit offsets), every pointer 8-byte
+ *     aligned.  Row padding (sy > n[0]+2g) and the 3-D ghost corners are
+ *     never read.
+ * GF order: 0 chi | 1-6 gt_xx gt_xy gt_xz gt_yy gt_yz gt_zz | 7 K |
+ *           8-13 At_xx..At_zz | 14-16 Gt^x Gt^y Gt^z | 17 alpha |
+ *           18-20 beta^x beta^y beta^z | 21-23 B^x B^y B^z.
+ */
+#ifndef CHEMORA_H
+#define CHEMORA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CHEMORA_OK = 0,
+  CHEMORA_EINVAL = -1,        /* invalid argument (nothing enqueued)          */
+  CHEMORA_EDEVICE = -2,       /* HIP runtime / launch failure                  */
+  CHEMORA_ENOMEM = -3,        /* library-side allocation failed (plans only)   */
+  CHEMORA_EUNSUPPORTED = -4,  /* valid but not built (e.g. order/precision)    */
+  CHEMORA_ENOTFINITE = -5     /* chemora_check_finite found NaN/Inf            */
+} chemora_status;
+
+enum { CHEMORA_NGF = 24 };
+enum { CHEMORA_LAPSE_ONE_PLUS_LOG = 0, CHEMORA_LAPSE_HARMONIC = 1, CHEMORA_LAPSE_FROZEN = 2 };
+enum { CHEMORA_SHIFT_GAMMA_DRIVER = 0, CHEMORA_SHIFT_FROZEN = 1 };
+enum { CHEMORA_BC_STATIC = 0, CHEMORA_BC_PERIODIC = 1 };
+enum { CHEMORA_PREC_FP64 = 0, CHEMORA_PREC_SPLIT = 1 };
+
+/* Discretisation and gauge parameters (the kernel "descriptor": stencil
+ * extent, parameters).  */
+typedef struct chemora_params {
+  int32_t fd_order;   /* 4 or 8: centred first/second/mixed derivatives      */
+  int32_t ghost;      /* g >= chemora_required_ghost(fd_order, upwind, ko)   */
+  int32_t upwind;     /* 1: lopsided advection stencils (offsets -1..3 at
+                         order 4, -3..5 at order 8, mirrored for beta < 0);
+                         0: centred advection                               */
+  int32_t ko_radius;  /* Kreiss-Oliger radius r (0 = off), r <= g           */
+  double eps_diss;    /* Kreiss-Oliger strength eps >= 0                     */
+  int32_t lapse;      /* CHEMORA_LAPSE_*                                     */
+  int32_t shift;      /* CHEMORA_SHIFT_*                                     */
+  double eta;         /* Gamma-driver damping                                */
+  int32_t bc;         /* CHEMORA_BC_*: ghost treatment inside rk4_step       */
+  int32_t precision;  /* CHEMORA_PREC_FP64 (CHEMORA_PREC_SPLIT: EUNSUPPORTED
+                         until built)                                       */
+  double chi_split;   /* split precision: FP64 chi terms where min chi < it  */
+} chemora_params;
+
+/* One Cartesian patch (a grid section with its ghost zones). */
+typedef struct chemora_patch {
+  int32_t n[3];       /* interior points nx, ny, nz (>= 1; >= ghost when the
+                         boundary is periodic)                              */
+  int32_t reserved;   /* must be 0                                            */
+  int64_t sy, sz, sf; /* element strides of y, z and the GF index            */
+  double h;           /* grid spacing (> 0)                                   */
+  double origin[3];   /* coordinates of interior point (0,0,0) (metadata)    */
+  double *u;          /* device pointer: 24 GFs, caller-owned                */
+} chemora_patch;
+
+/* Ghost width that one right-hand-side evaluation reads:
+ * max(order/2, order/2+1 if upwind, ko_radius).  Returns < 0 for an
+ * unsupported order. */
+int chemora_required_ghost(int fd_order, int upwind, int ko_radius);
+
+/* Right-hand side of all 24 BSSN equations at every interior point
+ * (moving-puncture BSSN with 1+log / harmonic / frozen lapse and the
+ * advective Gamma-driver shift, Kreiss-Oliger dissipation added to every
+ * evolved variable).  `rhs` has the patch's layout and strides; only its
+ * interior entries are written.  `rhs` must not overlap the patch state. */
+int chemora_bssn_rhs(const chemora_params *params, const chemora_patch *patch, double *rhs,
+                     void *stream);
+
+/* Number of doubles of caller-provided scratch rk4_step needs: 3*24*sf
+ * (two stage buffers and the RK accumulator). */
+size_t chemora_rk4_scratch_elems(const chemora_patch *patch);
+
+/* One classic RK4 step of size dt > 0 applied to patch->u in place.
+ * BC static: ghost points of u are left untouched and are the ghosts of every
+ * stage.  BC periodic: ghosts of every stage input and of the result are
+ * refilled with periodic images of the interior.  `scratch` is a device
+ * buffer of at least chemora_rk4_scratch_elems(patch) doubles that must not
+ * overlap u; its content on entry is ignored and on return is unspecified. */
+int chemora_rk4_step(const chemora_params *params, const chemora_patch *patch, double dt,
+                     double *scratch, void *stream);
+
+/* Stage s (1..4) of the step chemora_rk4_step performs, for callers that
+ * interleave their own work between stages or time them one by one.
+ * Calling s = 1, 2, 3, 4 in this order with the same dt and scratch is the
+ * same computation as one chemora_rk4_step (bitwise); any other order is
+ * undefined.  Stage 1 also prepares the stage buffers' ghosts (static BC). */
+int chemora_rk4_stage(const chemora_params *params, const chemora_patch *patch, int stage, double dt,
+                      double *scratch, void *stream);
+
+/* Counts NaN/Inf in the interior of all 24 GFs (ghost width from params),
+ * waits for `stream` and stores the count in *bad_count (host pointer).
+ * Returns CHEMORA_ENOTFINITE when the count is nonzero. */
+int chemora_check_finite(const chemora_params *params, const chemora_patch *patch, int64_t *bad_count,
+                         void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *chemora_last_error(void);
+
+/* ABI version of this header (major*100 + minor). */
+int chemora_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHEMORA_H */

@@ -1,0 +1,186 @@
+"""ctypes binding of libchemora.so (the gfx950 BSSN library).
+
+Argument marshalling only: every step of the right-hand side and of the RK4
+step runs in the library's HIP kernels.  The functions carry the C names and
+take the same arguments (structs by value are built from Python objects).
+The library must be built (``python -m paper_1307_6488_amd.build``);
+importing this module without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchemora.so")
+
+OK, EINVAL, EDEVICE, ENOMEM, EUNSUPPORTED, ENOTFINITE = 0, -1, -2, -3, -4, -5
+NGF = 24
+
+# Every symbol include/chemora.h declares.
+EXPORTS = (
+    "chemora_required_ghost", "chemora_bssn_rhs", "chemora_rk4_scratch_elems", "chemora_rk4_step",
+    "chemora_rk4_stage", "chemora_check_finite", "chemora_last_error", "chemora_abi_version",
+)
+
+
+class chemora_params(ctypes.Structure):
+    _fields_ = [("fd_order", ctypes.c_int32), ("ghost", ctypes.c_int32), ("upwind", ctypes.c_int32),
+                ("ko_radius", ctypes.c_int32), ("eps_diss", ctypes.c_double), ("lapse", ctypes.c_int32),
+                ("shift", ctypes.c_int32), ("eta", ctypes.c_double), ("bc", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("chi_split", ctypes.c_double)]
+
+
+class chemora_patch(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32), ("sy", ctypes.c_int64),
+                ("sz", ctypes.c_int64), ("sf", ctypes.c_int64), ("h", ctypes.c_double),
+                ("origin", ctypes.c_double * 3), ("u", ctypes.c_void_p)]
+
+
+class ChemoraError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"chemora error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_1307_6488_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P, X = ctypes.POINTER(chemora_params), ctypes.POINTER(chemora_patch)
+        L.chemora_required_ghost.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.chemora_required_ghost.restype = ctypes.c_int
+        L.chemora_bssn_rhs.argtypes = [P, X, ctypes.c_void_p, ctypes.c_void_p]
+        L.chemora_bssn_rhs.restype = ctypes.c_int
+        L.chemora_rk4_scratch_elems.argtypes = [X]
+        L.chemora_rk4_scratch_elems.restype = ctypes.c_size_t
+        L.chemora_rk4_step.argtypes = [P, X, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+        L.chemora_rk4_step.restype = ctypes.c_int
+        L.chemora_rk4_stage.argtypes = [P, X, ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+        L.chemora_rk4_stage.restype = ctypes.c_int
+        L.chemora_check_finite.argtypes = [P, X, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
+        L.chemora_check_finite.restype = ctypes.c_int
+        L.chemora_last_error.argtypes = []
+        L.chemora_last_error.restype = ctypes.c_char_p
+        L.chemora_abi_version.argtypes = []
+        L.chemora_abi_version.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().chemora_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc != OK:
+        raise ChemoraError(rc, last_error())
+    return rc
+
+
+def make_params(p) -> chemora_params:
+    """From an object with the chemora_params field names (e.g. inputs.Params)."""
+    return chemora_params(p.fd_order, p.ghost, p.upwind, p.ko_radius, p.eps_diss, p.lapse, p.shift, p.eta,
+                          p.bc, getattr(p, "precision", 0), getattr(p, "chi_split", 0.1))
+
+
+def make_patch(grid, u_ptr: int) -> chemora_patch:
+    """From an object with n, h, origin, sy, sz, sf (e.g. inputs.Grid) and a
+    device address."""
+    return chemora_patch((ctypes.c_int32 * 3)(*grid.n), 0, grid.sy, grid.sz, grid.sf, grid.h,
+                         (ctypes.c_double * 3)(*grid.origin), ctypes.c_void_p(u_ptr))
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)      # torch.cuda.Stream
+
+
+# --- the C entry points, same names -------------------------------------------------
+
+def chemora_required_ghost(fd_order: int, upwind: int, ko_radius: int) -> int:
+    return lib().chemora_required_ghost(fd_order, upwind, ko_radius)
+
+
+def chemora_bssn_rhs(params: chemora_params, patch: chemora_patch, rhs_ptr: int, stream=None) -> int:
+    return _check(lib().chemora_bssn_rhs(ctypes.byref(params), ctypes.byref(patch), ctypes.c_void_p(rhs_ptr),
+                                         _stream(stream)))
+
+
+def chemora_rk4_scratch_elems(patch: chemora_patch) -> int:
+    return int(lib().chemora_rk4_scratch_elems(ctypes.byref(patch)))
+
+
+def chemora_rk4_step(params: chemora_params, patch: chemora_patch, dt: float, scratch_ptr: int,
+                     stream=None) -> int:
+    return _check(lib().chemora_rk4_step(ctypes.byref(params), ctypes.byref(patch), dt,
+                                         ctypes.c_void_p(scratch_ptr), _stream(stream)))
+
+
+def chemora_rk4_stage(params: chemora_params, patch: chemora_patch, stage: int, dt: float, scratch_ptr: int,
+                      stream=None) -> int:
+    return _check(lib().chemora_rk4_stage(ctypes.byref(params), ctypes.byref(patch), stage, dt,
+                                          ctypes.c_void_p(scratch_ptr), _stream(stream)))
+
+
+def chemora_check_finite(params: chemora_params, patch: chemora_patch, stream=None) -> int:
+    """Number of non-finite interior values (0 when all are finite)."""
+    n = ctypes.c_int64(0)
+    rc = lib().chemora_check_finite(ctypes.byref(params), ctypes.byref(patch), ctypes.byref(n), _stream(stream))
+    if rc not in (OK, ENOTFINITE):
+        raise ChemoraError(rc, last_error())
+    return int(n.value)
+
+
+def chemora_abi_version() -> int:
+    return lib().chemora_abi_version()
+
+
+# --- torch conveniences (device memory and streams only) ----------------------------
+
+class Patch:
+    """A device-resident patch: torch tensor of the state plus the C structs."""
+
+    def __init__(self, params, grid, state, device="cuda"):
+        import torch
+        self.params_py, self.grid = params, grid
+        self.params = make_params(params)
+        if isinstance(state, torch.Tensor):
+            self.u = state
+        else:
+            self.u = torch.from_numpy(state).to(device)
+        assert self.u.dtype == torch.float64 and self.u.is_contiguous()
+        assert tuple(self.u.shape) == tuple(grid.shape)
+        self.patch = make_patch(grid, self.u.data_ptr())
+        self._scratch = None
+
+    def scratch(self):
+        import torch
+        if self._scratch is None:
+            n = chemora_rk4_scratch_elems(self.patch)
+            self._scratch = torch.empty(n, dtype=torch.float64, device=self.u.device)
+        return self._scratch
+
+    def rhs(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.full_like(self.u, float("nan"))
+        chemora_bssn_rhs(self.params, self.patch, out.data_ptr(), stream or torch.cuda.current_stream())
+        return out
+
+    def rk4_step(self, dt: float, nsteps: int = 1, stream=None):
+        import torch
+        s = stream or torch.cuda.current_stream()
+        sc = self.scratch().data_ptr()
+        for _ in range(nsteps):
+            chemora_rk4_step(self.params, self.patch, dt, sc, s)
+        return self.u

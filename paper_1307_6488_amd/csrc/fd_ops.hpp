@@ -1,0 +1,115 @@
+// fd_ops.hpp -- finite-difference operators for the gfx950 BSSN kernels.
+//
+// Every operator is written on differences of grid values (u_{+k} - u_{-k} or
+// u_{+k} - u_0) with integer weights over a common denominator, and the
+// 1/(D h) (or 1/(D h^2)) factor applied once at the end.  Constant data
+// therefore gives exactly zero, and each derivative costs one multiply by a
+// precomputed scale.  Weights:
+//   order 4  D1: (8 d1 - d2) / 12h                      d_k = u_k - u_-k
+//            D2: (16 s1 - s2) / 12h^2                   s_k = u_k + u_-k - 2u_0
+//            lopsided (beta >= 0, offsets -1..3):
+//                (-3 e_-1 + 18 e_1 - 6 e_2 + e_3) / 12h e_o = u_o - u_0
+//   order 8  D1: (672 d1 - 168 d2 + 32 d3 - 3 d4) / 840h
+//            D2: (8064 s1 - 1008 s2 + 128 s3 - 9 s4) / 5040h^2
+//            lopsided (offsets -3..5):
+//                (-5 e_-3 + 60 e_-2 - 420 e_-1 + 1050 e_1 - 420 e_2
+//                 + 140 e_3 - 30 e_4 + 3 e_5) / 840h
+//   Kreiss-Oliger radius r (Kreiss & Oliger 1973), dissipative sign, per axis:
+//            r=2: (4 s1 - s2) * 2^-4 eps/h
+//            r=3: (15 s1 - 6 s2 + s3) * 2^-6 eps/h
+//            r=5: (210 s1 - 120 s2 + 45 s3 - 10 s4 + s5) * 2^-10 eps/h
+// For beta < 0 the lopsided stencil is mirrored and negated.
+// The mixed derivative D_a D_b is the outer D1 along a of inner D1's along b,
+// both unscaled, divided by (12h)^2 or (840h)^2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chemora {
+
+template <int ORDER>
+struct Stencil;
+
+template <>
+struct Stencil<4> {
+  static constexpr int R = 2;            // centred reach
+  static constexpr double D1 = 12.0;     // denominators
+  static constexpr double D2 = 12.0;
+  static constexpr double DU = 12.0;
+  template <class F>
+  __device__ static inline double first(F&& at) {
+    return 8.0 * (at(1) - at(-1)) - (at(2) - at(-2));
+  }
+  template <class F>
+  __device__ static inline double second(F&& at) {
+    const double c = at(0);
+    return 16.0 * ((at(1) - c) + (at(-1) - c)) - ((at(2) - c) + (at(-2) - c));
+  }
+  // lopsided toward +axis; s = +1 or -1 mirrors the offsets, the caller
+  // multiplies the result by s
+  template <class F>
+  __device__ static inline double lopsided(F&& at, int s) {
+    const double c = at(0);
+    return -3.0 * (at(-s) - c) + 18.0 * (at(s) - c) - 6.0 * (at(2 * s) - c) + (at(3 * s) - c);
+  }
+};
+
+template <>
+struct Stencil<8> {
+  static constexpr int R = 4;
+  static constexpr double D1 = 840.0;
+  static constexpr double D2 = 5040.0;
+  static constexpr double DU = 840.0;
+  template <class F>
+  __device__ static inline double first(F&& at) {
+    return 672.0 * (at(1) - at(-1)) - 168.0 * (at(2) - at(-2)) + 32.0 * (at(3) - at(-3)) -
+           3.0 * (at(4) - at(-4));
+  }
+  template <class F>
+  __device__ static inline double second(F&& at) {
+    const double c = at(0);
+    return 8064.0 * ((at(1) - c) + (at(-1) - c)) - 1008.0 * ((at(2) - c) + (at(-2) - c)) +
+           128.0 * ((at(3) - c) + (at(-3) - c)) - 9.0 * ((at(4) - c) + (at(-4) - c));
+  }
+  template <class F>
+  __device__ static inline double lopsided(F&& at, int s) {
+    const double c = at(0);
+    return -5.0 * (at(-3 * s) - c) + 60.0 * (at(-2 * s) - c) - 420.0 * (at(-s) - c) +
+           1050.0 * (at(s) - c) - 420.0 * (at(2 * s) - c) + 140.0 * (at(3 * s) - c) -
+           30.0 * (at(4 * s) - c) + 3.0 * (at(5 * s) - c);
+  }
+};
+
+// Kreiss-Oliger term along one axis: the weighted sum of the symmetric
+// differences s_k, accumulated from k = 1 upward and scaled by
+// scale = 2^(-2r) eps / h.  It is a 2r-th difference that cancels by many
+// orders of magnitude on smooth data, so it is evaluated without FMA
+// contraction in this fixed order: the result is then reproducible to the
+// bit across compilers and independent of how the rest is scheduled.
+template <class F>
+__device__ inline double ko_axis(F&& at, int r, double scale) {
+#pragma clang fp contract(off)
+  const double c = at(0);
+  auto s = [&](int k) { return (at(k) - c) + (at(-k) - c); };
+  double acc;
+  if (r == 2) {
+    acc = 4.0 * s(1);
+    acc = acc - 1.0 * s(2);
+  } else if (r == 3) {
+    acc = 15.0 * s(1);
+    acc = acc - 6.0 * s(2);
+    acc = acc + 1.0 * s(3);
+  } else if (r == 5) {
+    acc = 210.0 * s(1);
+    acc = acc - 120.0 * s(2);
+    acc = acc + 45.0 * s(3);
+    acc = acc - 10.0 * s(4);
+    acc = acc + 1.0 * s(5);
+  } else {
+    return 0.0;
+  }
+  return acc * scale;
+}
+
+}  // namespace chemora

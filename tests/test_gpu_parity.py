@@ -1,0 +1,231 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Error metric per grid function f (max-norm normalised, interior points):
+    err_f = max |x_f - x_f^oracle| / max |x_f^oracle|
+and for a function the oracle gives as exactly zero, |x_f| <= 1e-14 times the
+largest magnitude over all functions.  Bars: 1e-12 after one right-hand side
+or one RK4 step, 1e-10 after 100 RK4 steps.  The GPU is free to contract to
+FMA and to reorder sums; bitwise checks only compare the GPU with itself
+(translation, determinism) or exact zeros.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1307_6488_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_1307_6488_amd import chemora
+    chemora.lib()
+    return torch
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gf_errors(got, ref, grid):
+    s = (slice(None),) + grid.interior()
+    a, b = got[s], ref[s]
+    scale = np.max(np.abs(b), axis=(1, 2, 3))
+    diff = np.max(np.abs(a - b), axis=(1, 2, 3))
+    big = float(np.max(scale))
+    out = np.where(scale > 0, diff / np.where(scale > 0, scale, 1.0), diff / max(big, 1e-300) * 1e-2)
+    return out
+
+
+def assert_parity(got, ref, grid, tol, what):
+    e = gf_errors(got, ref, grid)
+    worst = int(np.argmax(e))
+    say(f"{what}: max err {e[worst]:.3e} ({I.GF_NAMES[worst]}); per GF: "
+        + " ".join(f"{v:.1e}" for v in e))
+    assert np.all(np.isfinite(got[(slice(None),) + grid.interior()])), what
+    assert e[worst] <= tol, (what, dict(zip(I.GF_NAMES, e.tolist())))
+
+
+def gpu_rhs(torch, params, grid, u, fill=np.nan):
+    from paper_1307_6488_amd.chemora import Patch
+    P = Patch(params, grid, u)
+    out = torch.full_like(P.u, fill)
+    P.rhs(out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def gpu_rk4(torch, params, grid, u, dt, nsteps):
+    from paper_1307_6488_amd.chemora import Patch
+    P = Patch(params, grid, u)
+    P.rk4_step(dt, nsteps)
+    torch.cuda.synchronize()
+    return P.u.cpu().numpy()
+
+
+def bl_grid(n, ghost, h=1.0 / 8.0):
+    return I.centred_grid(n, ghost, h)
+
+
+CASES_RHS = [
+    # (name, params, grid, state maker)
+    ("sinusoid-32^3-o4-centred", lambda: I.workload(1)),
+    ("bl-ragged-o4-upwind", lambda: I.Workload("bl", I.workload(2).params, bl_grid((70, 37, 19), 3),
+                                               None, 1 / 32, 1)),
+    ("bl-pert-ragged-o8-upwind", lambda: I.Workload("blp", I.workload(3).params, bl_grid((45, 20, 13), 5),
+                                                    None, 1 / 32, 1)),
+]
+
+
+def _state(w):
+    if w.make_state is not None:
+        return w.make_state()
+    u = I.brill_lindquist(w.grid)
+    if w.params.fd_order == 8:
+        I.add_sinusoids(u, w.grid, np.random.default_rng(1310), 1e-4, [I.GT + s for s in range(6)] + [I.TRK],
+                        periodic_ghosts=False)
+    return u
+
+
+@pytest.mark.parametrize("name,mk", CASES_RHS, ids=[c[0] for c in CASES_RHS])
+def test_rhs_parity(torch_cuda, name, mk):
+    w = mk()
+    u = _state(w)
+    say(f"rhs parity {name} n={w.grid.n} order={w.params.fd_order}")
+    got = gpu_rhs(torch_cuda, w.params, w.grid, u)
+    ref = oracle.rhs(w.params, w.grid, u, nthreads=NTHREADS)
+    assert_parity(got, ref, w.grid, 1e-12, f"rhs {name}")
+
+
+@pytest.mark.parametrize("index", [2, 3])
+def test_rhs_parity_full_size(torch_cuda, index):
+    """Full-size grids (128^3 order 4, 192^3 order 8) in the benchmark's
+    launch configuration, compared at every interior point."""
+    w = I.workload(index)
+    u = w.make_state()
+    say(f"full-size rhs parity workload {index} n={w.grid.n}")
+    got = gpu_rhs(torch_cuda, w.params, w.grid, u)
+    ref = oracle.rhs(w.params, w.grid, u, nthreads=NTHREADS)
+    assert_parity(got, ref, w.grid, 1e-12, f"rhs full {index}")
+
+
+def test_rhs_leaves_ghosts_and_ignores_poisoned_points(torch_cuda):
+    w = I.workload(2, n_override=20)
+    u = w.make_state()
+    I.poison_padding(u, w.grid)
+    I.poison_corners(u, w.grid)
+    got = gpu_rhs(torch_cuda, w.params, w.grid, u, fill=7.0)
+    inner = (slice(None),) + w.grid.interior()
+    assert np.all(np.isfinite(got[inner]))
+    mask = np.ones(w.grid.shape, dtype=bool)
+    mask[inner] = False
+    assert np.all(got[mask] == 7.0)
+    ref = oracle.rhs(w.params, w.grid, u, nthreads=NTHREADS)
+    assert_parity(got, ref, w.grid, 1e-12, "rhs poisoned")
+
+
+@pytest.mark.parametrize("index", [1, 2, 3])
+def test_flat_space_is_exactly_zero(torch_cuda, index):
+    w = I.workload(index, n_override=16)
+    u = I.flat(w.grid)
+    got = gpu_rhs(torch_cuda, w.params, w.grid, u)
+    assert np.all(got[(slice(None),) + w.grid.interior()] == 0.0)
+    after = gpu_rk4(torch_cuda, w.params, w.grid, u, w.dt, 3)
+    assert np.array_equal(after[:, :, :, : w.grid.ext[0]], u[:, :, :, : w.grid.ext[0]])
+
+
+def test_periodic_translation_is_bitwise(torch_cuda):
+    w = I.workload(1, n_override=24)
+    u = w.make_state()
+    g, gr = w.grid.ghost, w.grid
+    inner = u[(slice(None),) + gr.interior()]
+    r1 = gpu_rhs(torch_cuda, w.params, gr, u)[(slice(None),) + gr.interior()]
+    for ax, shift in ((3, 1), (2, 5), (1, -3)):
+        rolled = np.roll(inner, -shift, axis=ax)
+        ext = rolled
+        for a in (1, 2, 3):
+            n = rolled.shape[a]
+            ext = np.take(ext, np.arange(-g, n + g) % n, axis=a)
+        u2 = I.alloc_state(gr)
+        u2[:, :, :, : gr.ext[0]] = ext
+        r2 = gpu_rhs(torch_cuda, w.params, gr, u2)[(slice(None),) + gr.interior()]
+        assert np.array_equal(np.roll(r1, -shift, axis=ax), r2), (ax, shift)
+
+
+def test_determinism(torch_cuda):
+    w = I.workload(2, n_override=40)
+    u = w.make_state()
+    a = gpu_rhs(torch_cuda, w.params, w.grid, u)
+    b = gpu_rhs(torch_cuda, w.params, w.grid, u)
+    assert np.array_equal(a, b, equal_nan=True)
+    x = gpu_rk4(torch_cuda, w.params, w.grid, u, w.dt, 2)
+    y = gpu_rk4(torch_cuda, w.params, w.grid, u, w.dt, 2)
+    assert np.array_equal(x, y, equal_nan=True)
+
+
+def test_rk4_one_step_periodic(torch_cuda):
+    w = I.workload(1)
+    u = w.make_state()
+    got = gpu_rk4(torch_cuda, w.params, w.grid, u, w.dt, 1)
+    ref = oracle.rk4(w.params, w.grid, u, w.dt, 1, nthreads=NTHREADS)
+    assert_parity(got, ref, w.grid, 1e-12, "rk4 1 step periodic")
+    # ghosts hold the periodic images of the interior, bitwise
+    g, n = w.grid.ghost, w.grid.n
+    core = got[(slice(None),) + w.grid.interior()]
+    ext = core
+    for a in (1, 2, 3):
+        ext = np.take(ext, np.arange(-g, n[3 - a] + g) % n[3 - a], axis=a)
+    assert np.array_equal(got[:, :, :, : w.grid.ext[0]], ext)
+
+
+def test_rk4_100_steps_brill_lindquist(torch_cuda):
+    w = I.workload(2, n_override=24)
+    u = w.make_state()
+    say("rk4 100 steps BL 24^3")
+    got = gpu_rk4(torch_cuda, w.params, w.grid, u, w.dt, 100)
+    ref = oracle.rk4(w.params, w.grid, u, w.dt, 100, nthreads=NTHREADS)
+    assert_parity(got, ref, w.grid, 1e-10, "rk4 100 steps BL")
+    mask = np.ones(w.grid.shape, dtype=bool)
+    mask[(slice(None),) + w.grid.interior()] = False
+    mask[:, :, :, w.grid.ext[0]:] = False
+    assert np.array_equal(got[mask], u[mask])        # static ghosts untouched
+
+
+def test_rk4_order8_steps(torch_cuda):
+    w = I.workload(3, n_override=18)
+    u = w.make_state()
+    say("rk4 20 steps order 8 18^3")
+    got = gpu_rk4(torch_cuda, w.params, w.grid, u, w.dt, 20)
+    ref = oracle.rk4(w.params, w.grid, u, w.dt, 20, nthreads=NTHREADS)
+    assert_parity(got, ref, w.grid, 1e-10, "rk4 20 steps order 8")
+
+
+def test_gauge_wave_harmonic_periodic(torch_cuda):
+    grid = I.gauge_wave_grid(32, 3)
+    u = I.gauge_wave(grid, A=0.1)
+    p = I.Params(fd_order=4, ghost=3, upwind=1, ko_radius=3, eps_diss=0.1, lapse=1, shift=1,
+                 bc=I.BC_PERIODIC)
+    dt = 0.25 * grid.h
+    got = gpu_rk4(torch_cuda, p, grid, u, dt, 16)
+    ref = oracle.rk4(p, grid, u, dt, 16, nthreads=NTHREADS)
+    assert_parity(got, ref, grid, 1e-12, "gauge wave 16 steps")
+
+
+def test_check_finite(torch_cuda):
+    from paper_1307_6488_amd import chemora as C
+    w = I.workload(2, n_override=12)
+    u = w.make_state()
+    P = C.Patch(w.params, w.grid, u)
+    assert C.chemora_check_finite(P.params, P.patch) == 0
+    P.u[5, w.grid.ghost + 3, w.grid.ghost + 2, w.grid.ghost + 1] = float("nan")
+    P.u[0, w.grid.ghost, w.grid.ghost, w.grid.ghost] = float("inf")
+    P.u[0, 0, 0, 0] = float("nan")                     # a ghost: not counted
+    assert C.chemora_check_finite(P.params, P.patch) == 2
