@@ -33,14 +33,14 @@
 namespace chemora {
 
 // packed symmetric index: xx xy xz yy yz zz
-__device__ constexpr int S(int i, int j) {
+__device__ __forceinline__ constexpr int S(int i, int j) {
   return (i == 0) ? j : (j == 0 ? i : (i == 1 ? (j == 1 ? 3 : 4) : (j == 1 ? 4 : 5)));
 }
 // weight of a packed slot in a full double sum over (i, j)
-__device__ constexpr double W(int s) { return (s == 1 || s == 2 || s == 4) ? 2.0 : 1.0; }
+__device__ __forceinline__ constexpr double W(int s) { return (s == 1 || s == 2 || s == 4) ? 2.0 : 1.0; }
 // row/column of packed slot
-__device__ constexpr int SI(int s) { return s < 3 ? 0 : (s < 5 ? 1 : 2); }
-__device__ constexpr int SJ(int s) { return s < 3 ? s : (s < 5 ? s - 2 : 2); }
+__device__ __forceinline__ constexpr int SI(int s) { return s < 3 ? 0 : (s < 5 ? 1 : 2); }
+__device__ __forceinline__ constexpr int SJ(int s) { return s < 3 ? s : (s < 5 ? s - 2 : 2); }
 
 enum : int {
   gCHI = 0, gGT = 1, gK = 7, gAT = 8, gXT = 14, gALPHA = 17, gBETA = 18, gB = 21
@@ -255,7 +255,7 @@ __device__ inline void bssn_algebra(const PointIn& p, const Gauge& gauge, double
 }
 
 // whether GF f evolves (a frozen gauge variable gets no advection/dissipation)
-__device__ inline bool evolves(int f, const Gauge& gauge) {
+__device__ __forceinline__ bool evolves(int f, const Gauge& gauge) {
   if (f == gALPHA) return gauge.lapse != 2;
   if (f >= gBETA) return gauge.shift == 0;
   return true;

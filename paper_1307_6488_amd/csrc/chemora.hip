@@ -123,8 +123,14 @@ int validate(const chemora_params* P, const chemora_patch* X) {
   if (X->sy < X->n[0] + g2) return fail(CHEMORA_EINVAL, "sy %lld < nx + 2g", (long long)X->sy);
   if (X->sz < X->sy * (X->n[1] + g2)) return fail(CHEMORA_EINVAL, "sz %lld < sy*(ny + 2g)", (long long)X->sz);
   if (X->sf < X->sz * (X->n[2] + g2)) return fail(CHEMORA_EINVAL, "sf %lld < sz*(nz + 2g)", (long long)X->sf);
-  if (X->sz > INT32_MAX || X->n[0] + g2 > 65535 * 64 || X->n[1] + g2 > 65535 || X->n[2] + g2 > 65535)
+  const int64_t tiles = (int64_t)((X->n[0] + 63) / 64) * ((X->n[1] + 3) / 4) * X->n[2];
+  if (X->sz > INT32_MAX || tiles > INT32_MAX || X->n[1] + g2 > 65535 || X->n[2] + g2 > 65535)
     return fail(CHEMORA_EINVAL, "patch too large for the launch geometry");
+  if (((uint64_t)CHEMORA_NGF * (uint64_t)X->sf + 8) * 8 > 0xFFFFFFFFull)
+    return fail(CHEMORA_EUNSUPPORTED, "patch state of %lld bytes exceeds 4 GiB; split it into patches",
+                (long long)((uint64_t)CHEMORA_NGF * X->sf * 8));
+  if (P->fd_order == 4 && P->ko_radius > 3)
+    return fail(CHEMORA_EUNSUPPORTED, "order 4 supports ko_radius <= 3");
   if (!(X->h > 0.0) || !std::isfinite(X->h)) return fail(CHEMORA_EINVAL, "h must be finite and > 0");
   if (!X->u) return fail(CHEMORA_EINVAL, "patch.u is NULL");
   if (((uintptr_t)X->u) % 8) return fail(CHEMORA_EINVAL, "patch.u not 8-byte aligned");
@@ -178,6 +184,8 @@ chemora::StageArgs base_args(const chemora_params* P, const chemora_patch* X) {
   a.gauge.lapse = P->lapse;
   a.gauge.shift = P->shift;
   a.gauge.eta = P->eta;
+  a.tiles_x = (X->n[0] + chemora::TILE_X - 1) / chemora::TILE_X;
+  a.tiles_y = (X->n[1] + chemora::TILE_Y - 1) / chemora::TILE_Y;
   return a;
 }
 

@@ -7,8 +7,8 @@ namespace chemora {
 namespace {
 template <bool UPWIND, int MODE>
 void launch(const StageArgs& a, hipStream_t s) {
-  dim3 block(64, 4, 1);
-  dim3 grid((a.geo.nx + 63) / 64, (a.geo.ny + 3) / 4, a.geo.nz);
+  dim3 block(TILE_X, TILE_Y, 1);
+  dim3 grid(a.tiles_x * a.tiles_y * a.geo.nz, 1, 1);
   hipLaunchKernelGGL((stage_kernel<8, UPWIND, MODE>), grid, block, 0, s, a);
 }
 
