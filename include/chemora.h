@@ -127,6 +127,37 @@ int chemora_rk4_step(const chemora_params *params, const chemora_patch *patch, d
 int chemora_rk4_stage(const chemora_params *params, const chemora_patch *patch, int stage, double dt,
                       double *scratch, void *stream);
 
+/* ---- batched form: many patches advanced together ------------------------
+ * A plan records a list of patches (each with its own spacing h, extents and
+ * strides; all share params) and their RK4 scratch buffers.  One RK4 step of
+ * every patch is captured once into a HIP graph: per RK stage a single
+ * persistent launch covers the tiles of all patches.  Patch p advances with
+ * its own time step dt_p = courant * h_p.  Patches are independent (each
+ * keeps its own ghosts); no data moves between patches. */
+typedef struct chemora_plan chemora_plan;   /* opaque, library-owned */
+
+/* Creates a plan.  patches[p].u and scratch[p] (chemora_rk4_scratch_elems
+ * doubles) must stay allocated, and scratch must not be modified by the
+ * caller, until chemora_plan_destroy.  With static ghosts the stage buffers'
+ * ghosts are copied from u once, here, on `stream`.  Validation as for
+ * chemora_rk4_step, per patch (EINVAL / EUNSUPPORTED before any HIP call);
+ * courant must be finite and > 0; npatch >= 1.  tune_cache_path is reserved
+ * (may be NULL).  Device tables and the graph are allocated here (ENOMEM or
+ * EDEVICE on failure, nothing leaked). */
+int chemora_plan_create(const chemora_params *params, const chemora_patch *patches, double *const *scratch,
+                        int32_t npatch, double courant, const char *tune_cache_path, void *stream,
+                        chemora_plan **out);
+
+/* Advances every patch of the plan by nsteps RK4 steps (nsteps >= 0), by
+ * replaying the captured graph on `stream`. */
+int chemora_batch_step(chemora_plan *plan, int32_t nsteps, void *stream);
+
+/* Total interior points of the plan's patches (0 for NULL). */
+int64_t chemora_plan_points(const chemora_plan *plan);
+
+/* Releases the plan (waits for its own work to finish).  NULL is a no-op. */
+int chemora_plan_destroy(chemora_plan *plan);
+
 /* Counts NaN/Inf in the interior of all 24 GFs (ghost width from params),
  * waits for `stream` and stores the count in *bad_count (host pointer).
  * Returns CHEMORA_ENOTFINITE when the count is nonzero. */

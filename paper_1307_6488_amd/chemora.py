@@ -22,6 +22,7 @@ NGF = 24
 EXPORTS = (
     "chemora_required_ghost", "chemora_bssn_rhs", "chemora_rk4_scratch_elems", "chemora_rk4_step",
     "chemora_rk4_stage", "chemora_check_finite", "chemora_last_error", "chemora_abi_version",
+    "chemora_plan_create", "chemora_batch_step", "chemora_plan_points", "chemora_plan_destroy",
 )
 
 
@@ -68,6 +69,15 @@ def lib() -> ctypes.CDLL:
         L.chemora_check_finite.restype = ctypes.c_int
         L.chemora_last_error.argtypes = []
         L.chemora_last_error.restype = ctypes.c_char_p
+        L.chemora_plan_create.argtypes = [P, X, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_double,
+                                          ctypes.c_char_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+        L.chemora_plan_create.restype = ctypes.c_int
+        L.chemora_batch_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+        L.chemora_batch_step.restype = ctypes.c_int
+        L.chemora_plan_points.argtypes = [ctypes.c_void_p]
+        L.chemora_plan_points.restype = ctypes.c_int64
+        L.chemora_plan_destroy.argtypes = [ctypes.c_void_p]
+        L.chemora_plan_destroy.restype = ctypes.c_int
         L.chemora_abi_version.argtypes = []
         L.chemora_abi_version.restype = ctypes.c_int
         _lib = L
@@ -141,6 +151,32 @@ def chemora_check_finite(params: chemora_params, patch: chemora_patch, stream=No
     return int(n.value)
 
 
+def chemora_plan_create(params: chemora_params, patches, scratch_ptrs, courant: float, tune_cache_path=None,
+                        stream=None) -> int:
+    """Returns the opaque plan handle (an int).  patches: sequence of
+    chemora_patch; scratch_ptrs: device addresses, one per patch."""
+    n = len(patches)
+    arr = (chemora_patch * n)(*patches)
+    sc = (ctypes.c_void_p * n)(*[ctypes.c_void_p(p) for p in scratch_ptrs])
+    out = ctypes.c_void_p(0)
+    path = tune_cache_path.encode() if tune_cache_path else None
+    _check(lib().chemora_plan_create(ctypes.byref(params), arr, sc, n, courant, path, _stream(stream),
+                                     ctypes.byref(out)))
+    return out.value
+
+
+def chemora_batch_step(plan: int, nsteps: int, stream=None) -> int:
+    return _check(lib().chemora_batch_step(ctypes.c_void_p(plan), nsteps, _stream(stream)))
+
+
+def chemora_plan_points(plan: int) -> int:
+    return int(lib().chemora_plan_points(ctypes.c_void_p(plan)))
+
+
+def chemora_plan_destroy(plan: int) -> int:
+    return _check(lib().chemora_plan_destroy(ctypes.c_void_p(plan)))
+
+
 def chemora_abi_version() -> int:
     return lib().chemora_abi_version()
 
@@ -184,3 +220,33 @@ class Patch:
         for _ in range(nsteps):
             chemora_rk4_step(self.params, self.patch, dt, sc, s)
         return self.u
+
+
+class Batch:
+    """Several device-resident patches advanced together through a plan."""
+
+    def __init__(self, params, grids, states, courant: float, device="cuda"):
+        import torch
+        self.patches = [Patch(params, g, s, device=device) for g, s in zip(grids, states)]
+        self.params = make_params(params)
+        scr = [p.scratch().data_ptr() for p in self.patches]
+        self.plan = chemora_plan_create(self.params, [p.patch for p in self.patches], scr, courant, None,
+                                        torch.cuda.current_stream())
+
+    def step(self, nsteps: int = 1, stream=None):
+        import torch
+        chemora_batch_step(self.plan, nsteps, stream or torch.cuda.current_stream())
+
+    def points(self) -> int:
+        return chemora_plan_points(self.plan)
+
+    def close(self):
+        if self.plan:
+            chemora_plan_destroy(self.plan)
+            self.plan = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

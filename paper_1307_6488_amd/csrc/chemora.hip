@@ -16,10 +16,13 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
+#include <new>
 #include <string>
+#include <vector>
 
 #include "chemora.h"
-#include "stage_kernel.hpp"
+#include "stage_common.hpp"
 
 namespace chemora {
 
@@ -162,12 +165,25 @@ chemora::Scales make_scales(const chemora_params* P, double h) {
   return s;
 }
 
-template <int MODE>
+// single-patch form: one work-group per tile
 void dispatch_stage(const chemora_params* P, const chemora::StageArgs& a, hipStream_t s) {
+  chemora::BatchTable none;
+  std::memset(&none, 0, sizeof none);
+  const int tiles = a.tiles_x * a.tiles_y * a.geo.nz;
   if (P->fd_order == 4)
-    chemora::launch_stage_o4(MODE, P->upwind != 0, a, s);
+    chemora::launch_stage_o4(P->upwind != 0, P->ko_radius, a, none, tiles, s);
   else
-    chemora::launch_stage_o8(MODE, P->upwind != 0, a, s);
+    chemora::launch_stage_o8(P->upwind != 0, P->ko_radius, a, none, tiles, s);
+}
+
+// batched form: a persistent grid over the plan's tile list
+void dispatch_batch(const chemora_params* P, const chemora::BatchTable& bt, int grid, hipStream_t s) {
+  chemora::StageArgs none;
+  std::memset(&none, 0, sizeof none);
+  if (P->fd_order == 4)
+    chemora::launch_stage_o4(P->upwind != 0, P->ko_radius, none, bt, grid, s);
+  else
+    chemora::launch_stage_o8(P->upwind != 0, P->ko_radius, none, bt, grid, s);
 }
 
 int check_launch(const char* what) {
@@ -226,7 +242,8 @@ int chemora_bssn_rhs(const chemora_params* params, const chemora_patch* patch, d
   chemora::StageArgs a = base_args(params, patch);
   a.in = patch->u;
   a.out = rhs;
-  dispatch_stage<chemora::MODE_RHS>(params, a, (hipStream_t)stream);
+  a.mode = chemora::MODE_RHS;
+  dispatch_stage(params, a, (hipStream_t)stream);
   return check_launch("bssn_rhs");
 }
 
@@ -266,22 +283,26 @@ int rk4_stage(const chemora_params* params, const chemora_patch* patch, int stag
     case 1:
       if (!periodic) launch_ghosts(false, a.geo, u, SA, SB, s);
       a.in = u; a.out = SA; a.cy = dt / 6.0; a.cs = 0.5 * dt;
-      dispatch_stage<chemora::MODE_STAGE1>(params, a, s);
+      a.mode = chemora::MODE_STAGE1;
+      dispatch_stage(params, a, s);
       written = SA;
       break;
     case 2:
       a.in = SA; a.out = SB; a.cy = dt / 3.0; a.cs = 0.5 * dt;
-      dispatch_stage<chemora::MODE_STAGE23>(params, a, s);
+      a.mode = chemora::MODE_STAGE23;
+      dispatch_stage(params, a, s);
       written = SB;
       break;
     case 3:
       a.in = SB; a.out = SA; a.cy = dt / 3.0; a.cs = dt;
-      dispatch_stage<chemora::MODE_STAGE23>(params, a, s);
+      a.mode = chemora::MODE_STAGE23;
+      dispatch_stage(params, a, s);
       written = SA;
       break;
     case 4:
       a.in = SA; a.un = nullptr; a.out = u; a.cy = dt / 6.0; a.cs = 0.0;
-      dispatch_stage<chemora::MODE_STAGE4>(params, a, s);
+      a.mode = chemora::MODE_STAGE4;
+      dispatch_stage(params, a, s);
       written = u;
       break;
     default:
@@ -338,6 +359,191 @@ int chemora_check_finite(const chemora_params* params, const chemora_patch* patc
   if (e != hipSuccess) return fail(CHEMORA_EDEVICE, "check_finite: %s", hipGetErrorString(e));
   *bad_count = (int64_t)h;
   return h ? fail(CHEMORA_ENOTFINITE, "%llu non-finite interior values", h) : CHEMORA_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// plans (batched form)
+// ---------------------------------------------------------------------------
+struct chemora_plan {
+  chemora_params params;
+  int npatch = 0;
+  int64_t points = 0;
+  int ntiles = 0;
+  int grid = 0;                                   // persistent work-groups per launch
+  chemora::StageArgs* d_args = nullptr;           // 4 stage tables of npatch entries
+  int* d_tile_start = nullptr;
+  hipStream_t capture = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void plan_free(chemora_plan* pl) {
+  if (!pl) return;
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->capture) {
+    (void)hipStreamSynchronize(pl->capture);
+    (void)hipStreamDestroy(pl->capture);
+  }
+  if (pl->d_args) (void)hipFree(pl->d_args);
+  if (pl->d_tile_start) (void)hipFree(pl->d_tile_start);
+  delete pl;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chemora_plan_create(const chemora_params* params, const chemora_patch* patches, double* const* scratch,
+                        int32_t npatch, double courant, const char* tune_cache_path, void* stream,
+                        chemora_plan** out) {
+  (void)tune_cache_path;
+  g_error.clear();
+  if (!out) return fail(CHEMORA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!patches || !scratch) return fail(CHEMORA_EINVAL, "patches or scratch is NULL");
+  if (npatch < 1) return fail(CHEMORA_EINVAL, "npatch %d < 1", npatch);
+  if (!(courant > 0.0) || !std::isfinite(courant)) return fail(CHEMORA_EINVAL, "courant must be finite and > 0");
+  int rc;
+  int64_t tiles = 0, points = 0;
+  for (int p = 0; p < npatch; ++p) {
+    if ((rc = rk4_checks(params, &patches[p], courant * patches[p].h, scratch[p]))) {
+      const std::string m = g_error;
+      return fail(rc, "patch %d: %s", p, m.c_str());
+    }
+    const chemora::StageArgs a = base_args(params, &patches[p]);
+    tiles += (int64_t)a.tiles_x * a.tiles_y * a.geo.nz;
+    points += (int64_t)patches[p].n[0] * patches[p].n[1] * patches[p].n[2];
+  }
+  if (tiles > INT32_MAX) return fail(CHEMORA_EINVAL, "too many tiles in the plan");
+
+  chemora_plan* pl = new (std::nothrow) chemora_plan;
+  if (!pl) return fail(CHEMORA_ENOMEM, "host allocation failed");
+  pl->params = *params;
+  pl->npatch = npatch;
+  pl->points = points;
+  pl->ntiles = (int)tiles;
+
+  // per-stage argument tables and tile offsets (host side first)
+  std::vector<chemora::StageArgs> args(4 * (size_t)npatch);
+  std::vector<int> start(npatch + 1, 0);
+  for (int p = 0; p < npatch; ++p) {
+    const chemora_patch* X = &patches[p];
+    const double dt = courant * X->h;
+    const size_t state = (size_t)CHEMORA_NGF * X->sf;
+    double* u = X->u;
+    double* SA = scratch[p];
+    double* SB = scratch[p] + state;
+    double* Y = scratch[p] + 2 * state;
+    chemora::StageArgs a = base_args(params, X);
+    start[p + 1] = start[p] + a.tiles_x * a.tiles_y * a.geo.nz;
+    a.un = u;
+    a.y = Y;
+    chemora::StageArgs s1 = a, s2 = a, s3 = a, s4 = a;
+    s1.in = u;  s1.out = SA; s1.cy = dt / 6.0; s1.cs = 0.5 * dt; s1.mode = chemora::MODE_STAGE1;
+    s2.in = SA; s2.out = SB; s2.cy = dt / 3.0; s2.cs = 0.5 * dt; s2.mode = chemora::MODE_STAGE23;
+    s3.in = SB; s3.out = SA; s3.cy = dt / 3.0; s3.cs = dt;       s3.mode = chemora::MODE_STAGE23;
+    s4.in = SA; s4.out = u;  s4.cy = dt / 6.0; s4.cs = 0.0;      s4.mode = chemora::MODE_STAGE4; s4.un = nullptr;
+    args[0 * npatch + p] = s1;
+    args[1 * npatch + p] = s2;
+    args[2 * npatch + p] = s3;
+    args[3 * npatch + p] = s4;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMalloc((void**)&pl->d_args, args.size() * sizeof(chemora::StageArgs));
+  if (e == hipSuccess) e = hipMalloc((void**)&pl->d_tile_start, start.size() * sizeof(int));
+  if (e != hipSuccess) {
+    plan_free(pl);
+    (void)hipGetLastError();
+    return fail(CHEMORA_ENOMEM, "device allocation of plan tables failed");
+  }
+  e = hipMemcpyAsync(pl->d_args, args.data(), args.size() * sizeof(chemora::StageArgs), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(pl->d_tile_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  // static ghosts of the stage buffers, once
+  if (e == hipSuccess && params->bc == CHEMORA_BC_STATIC) {
+    for (int p = 0; p < npatch && e == hipSuccess; ++p) {
+      const size_t state = (size_t)CHEMORA_NGF * patches[p].sf;
+      launch_ghosts(false, make_geo(params, &patches[p]), patches[p].u, scratch[p], scratch[p] + state, s);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // tables and ghosts in place before capture
+  if (e != hipSuccess) {
+    plan_free(pl);
+    return fail(CHEMORA_EDEVICE, "plan setup: %s", hipGetErrorString(e));
+  }
+
+  // persistent grid: one 256-thread work-group per compute unit (the stage
+  // kernel runs one wave per SIMD: 64 KB-140 KB of LDS and ~390 registers)
+  int dev = 0, cus = 0;
+  if ((e = hipGetDevice(&dev)) == hipSuccess)
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess || cus <= 0) {
+    plan_free(pl);
+    return fail(CHEMORA_EDEVICE, "device query failed");
+  }
+  pl->grid = std::max(1, std::min(pl->ntiles, cus));
+
+  // capture one RK4 step
+  e = hipStreamCreateWithFlags(&pl->capture, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(pl->capture, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    plan_free(pl);
+    return fail(CHEMORA_EDEVICE, "graph capture start: %s", hipGetErrorString(e));
+  }
+  const bool periodic = params->bc == CHEMORA_BC_PERIODIC;
+  for (int st = 0; st < 4; ++st) {
+    chemora::BatchTable bt;
+    bt.args = pl->d_args + st * npatch;
+    bt.tile_start = pl->d_tile_start;
+    bt.npatch = npatch;
+    bt.ntiles = pl->ntiles;
+    dispatch_batch(params, bt, pl->grid, pl->capture);
+    if (periodic)
+      for (int p = 0; p < npatch; ++p) {
+        const double* wr = args[st * npatch + p].out;
+        launch_ghosts(true, make_geo(params, &patches[p]), nullptr, const_cast<double*>(wr), nullptr, pl->capture);
+      }
+  }
+  hipError_t le = hipGetLastError();
+  e = hipStreamEndCapture(pl->capture, &pl->graph);
+  if (le != hipSuccess || e != hipSuccess) {
+    plan_free(pl);
+    return fail(CHEMORA_EDEVICE, "graph capture: %s", hipGetErrorString(le != hipSuccess ? le : e));
+  }
+  e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    plan_free(pl);
+    return fail(CHEMORA_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+  }
+  *out = pl;
+  return CHEMORA_OK;
+}
+
+int chemora_batch_step(chemora_plan* plan, int32_t nsteps, void* stream) {
+  g_error.clear();
+  if (!plan) return fail(CHEMORA_EINVAL, "plan is NULL");
+  if (nsteps < 0) return fail(CHEMORA_EINVAL, "nsteps %d < 0", nsteps);
+  for (int n = 0; n < nsteps; ++n) {
+    hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(CHEMORA_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+  }
+  return CHEMORA_OK;
+}
+
+int64_t chemora_plan_points(const chemora_plan* plan) { return plan ? plan->points : 0; }
+
+int chemora_plan_destroy(chemora_plan* plan) {
+  g_error.clear();
+  if (!plan) return CHEMORA_OK;
+  const hipError_t e = hipDeviceSynchronize();
+  plan_free(plan);
+  return e == hipSuccess ? CHEMORA_OK : fail(CHEMORA_EDEVICE, "plan destroy: %s", hipGetErrorString(e));
 }
 
 }  // extern "C"

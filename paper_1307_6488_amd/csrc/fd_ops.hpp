@@ -38,18 +38,18 @@ struct Stencil<4> {
   static constexpr double D2 = 12.0;
   static constexpr double DU = 12.0;
   template <class F>
-  __device__ static inline double first(F&& at) {
+  __device__ static __forceinline__ double first(F&& at) {
     return 8.0 * (at(1) - at(-1)) - (at(2) - at(-2));
   }
   template <class F>
-  __device__ static inline double second(F&& at) {
+  __device__ static __forceinline__ double second(F&& at) {
     const double c = at(0);
     return 16.0 * ((at(1) - c) + (at(-1) - c)) - ((at(2) - c) + (at(-2) - c));
   }
   // lopsided toward +axis; s = +1 or -1 mirrors the offsets, the caller
   // multiplies the result by s
   template <class F>
-  __device__ static inline double lopsided(F&& at, int s) {
+  __device__ static __forceinline__ double lopsided(F&& at, int s) {
     const double c = at(0);
     return -3.0 * (at(-s) - c) + 18.0 * (at(s) - c) - 6.0 * (at(2 * s) - c) + (at(3 * s) - c);
   }
@@ -62,18 +62,18 @@ struct Stencil<8> {
   static constexpr double D2 = 5040.0;
   static constexpr double DU = 840.0;
   template <class F>
-  __device__ static inline double first(F&& at) {
+  __device__ static __forceinline__ double first(F&& at) {
     return 672.0 * (at(1) - at(-1)) - 168.0 * (at(2) - at(-2)) + 32.0 * (at(3) - at(-3)) -
            3.0 * (at(4) - at(-4));
   }
   template <class F>
-  __device__ static inline double second(F&& at) {
+  __device__ static __forceinline__ double second(F&& at) {
     const double c = at(0);
     return 8064.0 * ((at(1) - c) + (at(-1) - c)) - 1008.0 * ((at(2) - c) + (at(-2) - c)) +
            128.0 * ((at(3) - c) + (at(-3) - c)) - 9.0 * ((at(4) - c) + (at(-4) - c));
   }
   template <class F>
-  __device__ static inline double lopsided(F&& at, int s) {
+  __device__ static __forceinline__ double lopsided(F&& at, int s) {
     const double c = at(0);
     return -5.0 * (at(-3 * s) - c) + 60.0 * (at(-2 * s) - c) - 420.0 * (at(-s) - c) +
            1050.0 * (at(s) - c) - 420.0 * (at(2 * s) - c) + 140.0 * (at(3 * s) - c) -
@@ -86,21 +86,22 @@ struct Stencil<8> {
 // scale = 2^(-2r) eps / h.  It is a 2r-th difference that cancels by many
 // orders of magnitude on smooth data, so it is evaluated without FMA
 // contraction in this fixed order: the result is then reproducible to the
-// bit across compilers and independent of how the rest is scheduled.
-template <class F>
-__device__ inline double ko_axis(F&& at, int r, double scale) {
+// bit across compilers and independent of how the rest is scheduled.  Radii
+// above RMAX (the reach of the caller's staged neighbourhood) are not built.
+template <int RMAX, class F>
+__device__ __forceinline__ double ko_axis(F&& at, int r, double scale) {
 #pragma clang fp contract(off)
   const double c = at(0);
   auto s = [&](int k) { return (at(k) - c) + (at(-k) - c); };
   double acc;
-  if (r == 2) {
+  if (RMAX >= 2 && r == 2) {
     acc = 4.0 * s(1);
     acc = acc - 1.0 * s(2);
-  } else if (r == 3) {
+  } else if (RMAX >= 3 && r == 3) {
     acc = 15.0 * s(1);
     acc = acc - 6.0 * s(2);
     acc = acc + 1.0 * s(3);
-  } else if (r == 5) {
+  } else if (RMAX >= 5 && r == 5) {
     acc = 210.0 * s(1);
     acc = acc - 120.0 * s(2);
     acc = acc + 45.0 * s(3);

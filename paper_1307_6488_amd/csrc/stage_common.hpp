@@ -1,0 +1,142 @@
+// stage_common.hpp -- launch arguments, index conventions and buffer-resource
+// helpers shared by the RK-stage kernel (stage_kernel.hpp) and the host ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chemora {
+
+// ---- grid-function numbering and symmetric-tensor packing ----------------
+// packed symmetric index: xx xy xz yy yz zz
+__device__ __forceinline__ constexpr int S(int i, int j) {
+  return (i == 0) ? j : (j == 0 ? i : (i == 1 ? (j == 1 ? 3 : 4) : (j == 1 ? 4 : 5)));
+}
+// weight of a packed slot in a full double sum over (i, j)
+__device__ __forceinline__ constexpr double W(int s) { return (s == 1 || s == 2 || s == 4) ? 2.0 : 1.0; }
+// row / column of a packed slot
+__device__ __forceinline__ constexpr int SI(int s) { return s < 3 ? 0 : (s < 5 ? 1 : 2); }
+__device__ __forceinline__ constexpr int SJ(int s) { return s < 3 ? s : (s < 5 ? s - 2 : 2); }
+
+// storage order of the 24 grid functions (the chemora.h GF layout)
+enum : int { gCHI = 0, gGT = 1, gK = 7, gAT = 8, gXT = 14, gALPHA = 17, gBETA = 18, gB = 21 };
+
+struct Gauge {
+  int lapse;   // 0 1+log, 1 harmonic, 2 frozen
+  int shift;   // 0 Gamma-driver, 1 frozen
+  double eta;
+};
+
+// ---- launch arguments ----------------------------------------------------
+// Geometry of a patch (all strides in elements).
+struct Geo {
+  int nx, ny, nz, g;
+  int64_t sy, sz, sf;
+};
+
+struct Scales {
+  double d1;    // 1 / (D1 h)
+  double d2;    // 1 / (D2 h^2)
+  double d11;   // 1 / (D1 h)^2
+  double up;    // 1 / (DU h)
+  double ko;    // 2^(-2r) * (eps / h)
+  int ko_r;
+};
+
+// What the kernel does with the right-hand side k it computed:
+//   RHS     out = k
+//   STAGE1  y = u + cy k,   out = u + cs k      (u = in = un)
+//   STAGE23 y += cy k,      out = un + cs k
+//   STAGE4  out = y + cy k
+enum Mode : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE23 = 2, MODE_STAGE4 = 4 };
+
+struct StageArgs {
+  const double* __restrict__ in;   // stencil input of this stage
+  const double* __restrict__ un;   // u_n (stages 1-3)
+  double* __restrict__ y;          // RK accumulator
+  double* __restrict__ out;        // rhs (MODE_RHS), next stage input, or u (stage 4)
+  Geo geo;
+  Scales sc;
+  Gauge gauge;
+  double cy;                       // weight of k in the accumulator update
+  double cs;                       // weight of k in the next stage input
+  int tiles_x, tiles_y;            // tile grid (TILE_X x TILE_Y points per tile)
+  int mode;                        // a Mode
+};
+
+// Batched form: all tiles of all patches of a plan.  ntiles == 0 selects the
+// single-patch form (the StageArgs kernel argument, one tile per work-group).
+struct BatchTable {
+  const StageArgs* args;     // one per patch (device memory)
+  const int* tile_start;     // prefix sums of tiles per patch, npatch + 1 entries
+  int npatch;
+  int ntiles;
+};
+
+constexpr int TILE_X = 64;
+constexpr int TILE_Y = 4;
+constexpr int NXCD = 8;
+
+// ---- device helpers ------------------------------------------------------
+// Materialises a value in registers at this point.  Without it the compiler
+// sinks the arithmetic of an accumulator to its last use near the end of the
+// kernel while the stencil reads feeding it stay early (stores intervene),
+// which keeps every tap live across the kernel.
+__device__ __forceinline__ void keep(double& x) { asm volatile("" : "+v"(x)); }
+template <int N>
+__device__ __forceinline__ void keep(double (&x)[N]) {
+#pragma unroll
+  for (int n = 0; n < N; ++n) keep(x[n]);
+}
+template <int N, int M>
+__device__ __forceinline__ void keep(double (&x)[N][M]) {
+#pragma unroll
+  for (int n = 0; n < N; ++n) keep(x[n]);
+}
+
+// Raw buffer access (gfx9 descriptor word 3 = 0x00020000).  Each state
+// buffer (24 GFs) is one buffer resource whose base sits XB elements before
+// the array, and an access is
+//   base + voffset (per lane) + soffset (uniform: GF, plane, tile) + imm,
+// so per-point offsets stay in one register and GF / plane offsets are
+// scalar arithmetic.  Offsets are 32-bit: the host rejects patches whose
+// 24-GF state exceeds 4 GiB.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+constexpr int XB = 8;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t state_rsrc(const double* base, int64_t sf) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(base - XB), (short)0, (int)((24 * sf + XB) * 8), 0x00020000);
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)voff, (int)soff, 0);
+}
+
+// Work-groups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Remap the hardware block id so that each XCD receives a contiguous
+// range of tiles (neighbours share halos in that XCD's L2).
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
+  const int full = (nblocks / NXCD) * NXCD;
+  if (bid >= full) return bid;
+  return (bid % NXCD) * (nblocks / NXCD) + bid / NXCD;
+}
+
+// patch of global tile t (binary search over the prefix sums)
+__device__ __forceinline__ int batch_patch(const BatchTable& bt, int t) {
+  int lo = 0, hi = bt.npatch - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bt.tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---- host-side launchers, one per order (stage_o4.hip / stage_o8.hip) ----
+// Single-patch form: bt.ntiles == 0, grid = tiles of a.  Batched form: a is
+// unused, grid = persistent work-groups striding over bt's tiles.
+void launch_stage_o4(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s);
+void launch_stage_o8(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s);
+
+}  // namespace chemora

@@ -1,206 +1,280 @@
-// stage_kernel.hpp -- the fused RK-stage kernel (stencils + BSSN algebra +
-// advection + dissipation + RK4 stage combination), one work-item per
-// interior point.  Instantiated per finite-difference order in
-// stage_o4.hip / stage_o8.hip.
+// stage_kernel.hpp -- the fused RK-stage kernel for gfx950: stencils, BSSN
+// algebra, upwinded advection, Kreiss-Oliger dissipation and the RK4 stage
+// combination in one pass over the grid, instantiated per finite-difference
+// order in stage_o4.hip / stage_o8.hip.
 //
-// The paper's McLachlan kernels spill badly ("fat kernels", section "Fat
-// Kernel Detection") because every derivative is formed before the
-// algebra.  Here the right-hand side is evaluated grid function by grid
-// function in dependency order
-//     beta -> gt -> chi -> Gt -> alpha -> K -> At -> (Gt, B)
-// so each stencil result is consumed as soon as it is formed: second
-// derivatives are contracted at once into the Ricci, D_i D_j alpha and
-// Gt-source accumulators, and each variable's right-hand side is finished
-// and passed through the RK epilogue (loads of u_n / the accumulator,
-// stores) as soon as its inputs are complete.  Only the first derivatives of
-// beta, chi, alpha, K and the Christoffel symbols stay live.
+// Equations (section "Scientific Motivation": the BSSN form of the Einstein
+// equations; section "Binary Black Hole Simulations": the McLachlan kernels),
+// in the chi form with 1+log / harmonic / frozen slicing and the advective
+// Gamma-driver shift (eta damping, 3/4 coupling):
+//   d0 chi   = 2/3 chi (alpha K - div beta)
+//   d0 gt_ij = -2 alpha At_ij + gt_ik d_j b^k + gt_jk d_i b^k - 2/3 gt_ij div beta
+//   d0 K     = -D^2 alpha + alpha (At_ij At^ij + K^2/3)
+//   d0 At_ij = chi [-D_i D_j alpha + alpha R_ij]^TF + alpha (K At_ij - 2 At_ik At^k_j)
+//              + At_ik d_j b^k + At_jk d_i b^k - 2/3 At_ij div beta
+//   d0 Gt^i  = gt^jk d_j d_k b^i + 1/3 gt^ij d_j d_k b^k - Gd^j d_j b^i
+//              + 2/3 Gd^i div beta - 2 At^ij d_j alpha
+//              + 2 alpha (Gt^i_jk At^jk - 3/(2chi) At^ij d_j chi - 2/3 gt^ij d_j K)
+//   d0 alpha = -2 alpha K (1+log) | -alpha^2 K (harmonic) ;  d0 beta^i = 3/4 B^i
+//   d0 B^i   = d0 Gt^i - eta B^i
+// with d0 = d_t - beta^k d_k, Gd^i = gt^jk Gt^i_jk from the metric, and
+//   R_ij  = -1/2 gt^lm d_l d_m gt_ij + gt_k(i d_j) Gt^k + Gd^k Gt_(ij)k
+//           + gt^lm (2 Gt^k_l(i Gt_j)km + Gt^k_im Gt_klj)
+//           + [D~_i D~_j chi + gt_ij D~^2 chi] / (2 chi)
+//           - [d_i chi d_j chi + 3 gt_ij |d chi|^2] / (4 chi^2).
+// Each variable's right-hand side is (algebra + advection) + dissipation.
+//
+// Work decomposition.  A work-group (4 waves) owns a 64 x 4 tile of one
+// z-plane, one work-item per point.  The paper's kernels spill because every
+// derivative is formed before the algebra (section "Fat Kernel Detection");
+// here the right-hand side is evaluated grid function by grid function in
+// dependency order
+//     beta(3) gt(6) chi alpha Gt(3) K At(6) B(3)
+// and every stencil result is consumed at once: second derivatives are
+// contracted straight into the Ricci, D_i D_j alpha and Gt-source
+// accumulators, and each variable's right-hand side goes through the RK
+// epilogue (loads of u_n / the accumulator, stores) as soon as its inputs are
+// complete.
+//
+// Staging.  Each grid function's stencil neighbourhood is copied into LDS by
+// direct global->LDS loads (buffer_load_dwordx4 ... lds: lane l moves two
+// doubles to LDS bytes [16 l, 16 l + 16) of the instruction's 1 KiB chunk), no
+// registers involved, double-buffered: the next grid function's chunks are in
+// flight while the work-items evaluate the current one's stencils from LDS
+// with compile-time offsets.  Every lane's global offset for each of its
+// wave's chunks is computed once per tile, so issuing a grid function costs
+// one instruction per chunk.  One barrier per grid function.
+//
+// LDS layout per staged grid function (pitch P = 64 + 2R doubles):
+//   plane dz = 0            rows y in [-R,  3+R]   (x and y stencils, xy mixed)
+//   planes 1 <= |dz| <= RM  rows y in [-RM, 3+RM]  (xz / yz mixed, z stencils)
+//   planes RM < |dz| <= R   rows y in [0, 3]       (z stencils only)
+// with R the axis reach (upwind, Kreiss-Oliger) and RM = ORDER/2 the mixed
+// reach; planes are ordered dz = 0, +1, -1, +2, -2, ...
 #pragma once
 
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
-#include "bssn_algebra.hpp"
 #include "fd_ops.hpp"
+#include "stage_common.hpp"
 
 namespace chemora {
 
-// Geometry of a launch (all offsets in elements).
-struct Geo {
-  int nx, ny, nz, g;
-  int64_t sy, sz, sf;
+template <int R, int RM>
+struct LdsLayout {
+  static constexpr int TX = TILE_X, TY = TILE_Y;
+  static constexpr int P = TX + 2 * R;
+  static constexpr int ROWS0 = TY + 2 * R, ROWS1 = TY + 2 * RM, ROWS2 = TY;
+  static constexpr int SIZE = P * (ROWS0 + 2 * RM * ROWS1 + 2 * (R - RM) * ROWS2);
+  static constexpr int CHUNK = 128;                          // doubles per LDS-DMA instruction
+  static constexpr int NCHUNK = (SIZE + CHUNK - 1) / CHUNK;
+  static constexpr int SIZEP = NCHUNK * CHUNK;               // buffer size incl. padding
+  static constexpr int CPW = (NCHUNK + 3) / 4;               // chunks per wave
+  static_assert(P % 2 == 0, "a lane's pair of doubles must not straddle rows");
+
+  // first row (y = -yhalo) of plane dz, in doubles
+  __host__ __device__ static constexpr int plane(int dz) {
+    const int a = dz < 0 ? -dz : dz;
+    if (a == 0) return 0;
+    if (a <= RM) return P * (ROWS0 + ((dz > 0 ? 2 * a - 1 : 2 * a) - 1) * ROWS1);
+    return P * (ROWS0 + 2 * RM * ROWS1 + ((dz > 0 ? 2 * (a - RM) - 1 : 2 * (a - RM)) - 1) * ROWS2);
+  }
+  __host__ __device__ static constexpr int yhalo(int dz) {
+    const int a = dz < 0 ? -dz : dz;
+    return a == 0 ? R : (a <= RM ? RM : 0);
+  }
+  // offset (doubles) of tap (dx, dy, dz) from the work-item's anchor ty*P + tx
+  __host__ __device__ static constexpr int off(int dx, int dy, int dz) {
+    return plane(dz) + (dy + yhalo(dz)) * P + (dx + R);
+  }
+  // inverse of off(): the tile-relative point (x, y, dz) stored at LDS double
+  // idx; the padding past SIZE maps to the anchor (0, 0, 0)
+  __host__ __device__ static constexpr void decode(int idx, int& x, int& y, int& dz) {
+    if (idx >= SIZE) {
+      x = 0; y = 0; dz = 0;
+      return;
+    }
+    const int row = idx / P;
+    x = idx - row * P - R;
+    if (row < ROWS0) {
+      dz = 0;
+      y = row - R;
+      return;
+    }
+    int r = row - ROWS0;
+    int a, q;
+    if (r < 2 * RM * ROWS1) {
+      q = r / ROWS1;
+      y = r - q * ROWS1 - RM;
+      a = q / 2 + 1;
+    } else {
+      r -= 2 * RM * ROWS1;
+      q = r / ROWS2;
+      y = r - q * ROWS2;
+      a = RM + q / 2 + 1;
+    }
+    dz = (q & 1) ? -a : a;
+  }
 };
 
-struct Scales {
-  double d1;    // 1 / (D1 h)
-  double d2;    // 1 / (D2 h^2)
-  double d11;   // 1 / (D1 h)^2
-  double up;    // 1 / (DU h)
-  double ko;    // 2^(-2r) * (eps / h)
-  int ko_r;
-};
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
-enum Mode : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE23 = 2, MODE_STAGE4 = 4 };
-
-struct StageArgs {
-  const double* __restrict__ in;   // stencil input of this stage
-  const double* __restrict__ un;   // u_n (stages 1-3)
-  double* __restrict__ y;          // RK accumulator
-  double* __restrict__ out;        // rhs (MODE_RHS), next stage input, or u (stage 4)
-  Geo geo;
-  Scales sc;
-  Gauge gauge;
-  double cy;                       // weight of k in the accumulator update
-  double cs;                       // weight of k in the next stage input
-  int tiles_x, tiles_y;            // tile grid (64 x 4 points per tile)
-};
-
-// Keeps the scheduler from hoisting the next phase's loads above this point
-// (which would make every stencil value live at once and spill).
-#ifndef CHEMORA_NO_PHASE
-#define CHEMORA_PHASE() __builtin_amdgcn_sched_barrier(0)
-#else
-#define CHEMORA_PHASE()
-#endif
-
-// Materialises a value in registers at this point.  Without it the compiler
-// sinks the arithmetic of an accumulator to its last use near the end of the
-// kernel while the stencil loads feeding it stay early (stores intervene),
-// which keeps every loaded tap live across the kernel.
-__device__ inline void keep(double& x) { asm volatile("" : "+v"(x)); }
-template <int N>
-__device__ inline void keep(double (&x)[N]) {
-#pragma unroll
-  for (int n = 0; n < N; ++n) keep(x[n]);
-}
-template <int N, int M>
-__device__ inline void keep(double (&x)[N][M]) {
-#pragma unroll
-  for (int n = 0; n < N; ++n) keep(x[n]);
-}
-
-#ifndef CHEMORA_WAVES_PER_EU
-#define CHEMORA_WAVES_PER_EU 2
-#endif
-
-constexpr int TILE_X = 64;
-constexpr int TILE_Y = 4;
-constexpr int NXCD = 8;
-
-// Raw buffer access (gfx9 descriptor word 3 = 0x00020000).  Each state
-// buffer (24 GFs) is one buffer resource whose base sits XB elements before
-// the array, and an access is
-//   base + voffset (per lane: the point) + soffset (uniform: GF, y/z offsets)
-//        + imm ((XB + dx) * 8, a compile-time immediate),
-// so the ~1000 stencil taps of a point share a single address register and
-// every y/z/GF offset is scalar arithmetic.  Offsets are 32-bit: the host
-// rejects patches whose 24-GF state exceeds 4 GiB.
-typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
-constexpr int XB = 8;
-
-__device__ inline __amdgpu_buffer_rsrc_t state_rsrc(const double* base, int64_t sf) {
-  return __builtin_amdgcn_make_buffer_rsrc((void*)(base - XB), (short)0, (int)((24 * sf + XB) * 8), 0x00020000);
-}
-__device__ inline double bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-}
-__device__ inline void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)voff, (int)soff, 0);
-}
-
-// Work-groups are dispatched round-robin over the 8 XCDs (each with its own
-// L2).  Remap the hardware block id so that each XCD receives a contiguous
-// range of tiles (neighbours share halos in that XCD's L2).
-__device__ inline int xcd_tile(int bid, int nblocks) {
-  const int full = (nblocks / NXCD) * NXCD;
-  if (bid >= full) return bid;
-  return (bid % NXCD) * (nblocks / NXCD) + bid / NXCD;
-}
-
-template <int ORDER, bool UPWIND, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CHEMORA_WAVES_PER_EU))) void stage_kernel(StageArgs a) {
+// One tile t of a patch (x-tiles fastest, then y, then z), staged through
+// the two LDS buffers buf0 / buf1 (LdsLayout::SIZEP doubles each).  Every
+// work-item of the work-group must call it (it synchronises); it ends with a
+// barrier, so the buffers may be reused right after.
+template <int ORDER, bool UPWIND, int R>
+__device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* buf0, double* buf1) {
   using St = Stencil<ORDER>;
+  constexpr int RM = ORDER / 2;
+  using L = LdsLayout<R, RM>;
   const Geo G = a.geo;
-  const int nblocks = a.tiles_x * a.tiles_y * G.nz;
-  const int t = xcd_tile(blockIdx.x, nblocks);
-  const int tx = t % a.tiles_x;
-  const int ty = (t / a.tiles_x) % a.tiles_y;
+  const int txi = t % a.tiles_x;
+  const int tyi = (t / a.tiles_x) % a.tiles_y;
   const int k = t / (a.tiles_x * a.tiles_y);
-  const int i = tx * TILE_X + threadIdx.x;
-  const int j = ty * TILE_Y + threadIdx.y;
-  if (i >= G.nx || j >= G.ny) return;
-  // byte offsets: lane part (the point, x and y), uniform part (GF, z plane,
-  // y/z stencil offsets), immediate (x stencil offset)
+  // threadIdx.y is the wave index: uniform across the wave, so keep it (and
+  // everything the staging derives from it) in scalar registers
+  const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  const int i0 = txi * TILE_X, j0 = tyi * TILE_Y;
+  const bool valid = (i0 + lane < G.nx) && (j0 + wave < G.ny);
+  // pointwise accesses of work-items outside the interior use a clamped point
+  const int ic = min(i0 + lane, G.nx - 1), jc = min(j0 + wave, G.ny - 1);
+
+  // byte offsets are unsigned 32-bit (the host limits a state to 4 GiB)
   const unsigned sy = (unsigned)G.sy, sz = (unsigned)G.sz, sf = (unsigned)G.sf, gg = (unsigned)G.g;
-  const unsigned vb = (j * sy + i + gg) * 8u;
-  const unsigned zb = k * sz;
   const __amdgpu_buffer_rsrc_t rin = state_rsrc(a.in, G.sf);
-  auto soff = [&](int f, int dy, int dz) { return (f * sf + zb + (gg + dz) * sz + (gg + dy) * sy) * 8u; };
-  auto tap = [&](int f, int dx, int dy, int dz) { return bload(rin, vb + (XB + dx) * 8, soff(f, dy, dz)); };
-  auto along = [&](int f, int ax, int o) {
-    return ax == 0 ? tap(f, o, 0, 0) : (ax == 1 ? tap(f, 0, o, 0) : tap(f, 0, 0, o));
+  const unsigned vpt = (jc * sy + ic + gg) * 8u + XB * 8u;       // the point (pointwise accesses)
+  const unsigned spt = ((k + gg) * sz + gg * sy) * 8u;          // its z plane / ghost offset
+  auto val = [&](int f) __attribute__((always_inline)) { return bload(rin, vpt, spt + f * sf * 8u); };
+
+  // ---- staging offsets of this tile.  Lane l of wave w moves LDS doubles
+  // [c*128 + 2l, c*128 + 2l + 1] of chunks c = w, w+4, ...  Points outside
+  // the patch's stored box (rows / columns of a ragged tile past the ghost
+  // zone) are clamped into it: their LDS values are never read by a valid
+  // work-item.  A pair whose first double is the last stored column of the
+  // box is moved as one double through a register (bit q of `lone`), so no
+  // access leaves the box.  voff is biased by (R sz + R sy + R) so that it
+  // stays non-negative.
+  const int xmax = G.nx - 1 + R - i0;       // last tile-relative column inside the box
+  const int ymax = G.ny - 1 + R - j0;       // last tile-relative row inside the box
+  const unsigned bias = (unsigned)R * (sz + sy + 1u);
+  unsigned voff[L::CPW];
+  unsigned lone = 0;
+#pragma unroll
+  for (int q = 0; q < L::CPW; ++q) {
+    int x, y, dz;
+    L::decode((wave + 4 * q) * L::CHUNK + 2 * lane, x, y, dz);
+    y = min(y, ymax);
+    if (x == xmax) lone |= 1u << q;
+    if (x > xmax) x = xmax - 1;
+    voff[q] = (unsigned)(dz * (int)sz + y * (int)sy + x + (int)bias) * 8u;
+  }
+  const unsigned tile_base = ((k + gg) * sz + (j0 + gg) * sy + i0 + gg + XB) * 8u - bias * 8u;
+  auto issue = [&](int f, double* dst) __attribute__((always_inline)) {
+    const unsigned so = tile_base + f * sf * 8u;
+#pragma unroll
+    for (int q = 0; q < L::CPW; ++q) {
+      const int c = wave + 4 * q;
+      if (L::CPW * 4 != L::NCHUNK && c >= L::NCHUNK) break;   // wave-uniform
+      double* chunk = dst + c * L::CHUNK;
+      if (!((lone >> q) & 1u))
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr_t)chunk, 16, voff[q], so, 0, 0);
+      else
+        chunk[2 * lane] = bload(rin, voff[q], so);
+    }
   };
-  auto val = [&](int f) { return tap(f, 0, 0, 0); };
-  auto D1 = [&](int f, int ax) {
-    return St::first([&](int o) { return along(f, ax, o); }) * a.sc.d1;
+  auto sync = [&]() __attribute__((always_inline)) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
   };
-  auto D2 = [&](int f, int slot) {
+
+  const int anchor = wave * L::P + lane;
+  // stencil access into the buffer of the current phase
+  auto make_ops = [&](const double* cur) __attribute__((always_inline)) {
+    auto tap = [=](int dx, int dy, int dz) __attribute__((always_inline)) { return cur[anchor + L::off(dx, dy, dz)]; };
+    return tap;
+  };
+  const double bet[3] = {val(gBETA), val(gBETA + 1), val(gBETA + 2)};
+  auto D1 = [&](auto tap, int ax) __attribute__((always_inline)) {
+    return St::first([&](int o) { return ax == 0 ? tap(o, 0, 0) : (ax == 1 ? tap(0, o, 0) : tap(0, 0, o)); }) *
+           a.sc.d1;
+  };
+  auto D2 = [&](auto tap, int slot) __attribute__((always_inline)) {
     const int ai = SI(slot), bj = SJ(slot);
-    if (ai == bj) return St::second([&](int o) { return along(f, ai, o); }) * a.sc.d2;
+    auto along = [&](int o) __attribute__((always_inline)) { return ai == 0 ? tap(o, 0, 0) : (ai == 1 ? tap(0, o, 0) : tap(0, 0, o)); };
+    if (ai == bj) return St::second(along) * a.sc.d2;
     const double v = St::first([&](int oa) {
       return St::first([&](int ob) {
         int d[3] = {0, 0, 0};
         d[ai] = oa;
         d[bj] = ob;
-        return tap(f, d[0], d[1], d[2]);
+        return tap(d[0], d[1], d[2]);
       });
     });
     return v * a.sc.d11;
   };
-  const double bet[3] = {val(gBETA), val(gBETA + 1), val(gBETA + 2)};
-  // advection + dissipation of GF f; rhs = (algebra + adv) + diss
-  auto finish = [&](int f, double alg) {
+  // advection + dissipation of the staged GF; rhs = (algebra + adv) + diss
+  auto finish = [&](auto tap, double alg) __attribute__((always_inline)) {
     double adv = 0.0, diss = 0.0;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
+      auto along = [&](int o) __attribute__((always_inline)) { return ax == 0 ? tap(o, 0, 0) : (ax == 1 ? tap(0, o, 0) : tap(0, 0, o)); };
       double d;
       if (UPWIND) {
-        const int sg = bet[ax] >= 0.0 ? 1 : -1;
-        d = (double)sg * St::lopsided([&](int o) { return along(f, ax, o); }, sg) * a.sc.up;
+        // both lopsided stencils from the same taps, then select by the sign of beta
+        const double dp = St::lopsided(along, 1);
+        const double dm = -St::lopsided([&](int o) { return along(-o); }, 1);
+        d = (bet[ax] >= 0.0 ? dp : dm) * a.sc.up;
       } else {
-        d = St::first([&](int o) { return along(f, ax, o); }) * a.sc.d1;
+        d = St::first(along) * a.sc.d1;
       }
       adv += bet[ax] * d;
       if (a.sc.ko_r > 0) {
-        const double qd = ko_axis([&](int o) { return along(f, ax, o); }, a.sc.ko_r, a.sc.ko);
+        const double qd = ko_axis<R>(along, a.sc.ko_r, a.sc.ko);
         diss = (ax == 0) ? qd : diss + qd;
       }
     }
     return (alg + adv) + diss;
   };
-  // RK epilogue of GF f with right-hand side kf (pointwise buffers)
-  const unsigned vo = vb + XB * 8u;
-  auto emit = [&](int f, double kf) {
-    const unsigned so = soff(f, 0, 0);
-    if (MODE == MODE_RHS) {
-      bstore(state_rsrc(a.out, G.sf), vo, so, kf);
-    } else if (MODE == MODE_STAGE1) {
+  const int mode = a.mode;
+  auto emit = [&](int f, double kf) __attribute__((always_inline)) {
+    if (!valid) return;
+    const unsigned so = spt + f * sf * 8u;
+    if (mode == MODE_RHS) {
+      bstore(state_rsrc(a.out, G.sf), vpt, so, kf);
+    } else if (mode == MODE_STAGE1) {
       const double u0 = val(f);
-      bstore(state_rsrc(a.y, G.sf), vo, so, u0 + a.cy * kf);
-      bstore(state_rsrc(a.out, G.sf), vo, so, u0 + a.cs * kf);
-    } else if (MODE == MODE_STAGE23) {
-      const double y0 = bload(state_rsrc(a.y, G.sf), vo, so);
-      const double u0 = bload(state_rsrc(a.un, G.sf), vo, so);
-      bstore(state_rsrc(a.y, G.sf), vo, so, y0 + a.cy * kf);
-      bstore(state_rsrc(a.out, G.sf), vo, so, u0 + a.cs * kf);
+      bstore(state_rsrc(a.y, G.sf), vpt, so, u0 + a.cy * kf);
+      bstore(state_rsrc(a.out, G.sf), vpt, so, u0 + a.cs * kf);
+    } else if (mode == MODE_STAGE23) {
+      const double y0 = bload(state_rsrc(a.y, G.sf), vpt, so);
+      const double u0 = bload(state_rsrc(a.un, G.sf), vpt, so);
+      bstore(state_rsrc(a.y, G.sf), vpt, so, y0 + a.cy * kf);
+      bstore(state_rsrc(a.out, G.sf), vpt, so, u0 + a.cs * kf);
     } else {
-      const double y0 = bload(state_rsrc(a.y, G.sf), vo, so);
-      bstore(state_rsrc(a.out, G.sf), vo, so, y0 + a.cy * kf);
+      const double y0 = bload(state_rsrc(a.y, G.sf), vpt, so);
+      bstore(state_rsrc(a.out, G.sf), vpt, so, y0 + a.cy * kf);
     }
   };
-  const Gauge& gauge = a.gauge;
-  const double alpha = val(gALPHA), chi = val(gCHI), K = val(gK);
 
-  // conformal metric and its inverse (point values only)
+  // staging sequence: 24 phases (B only with the Gamma-driver shift)
+  const Gauge& gauge = a.gauge;
+  const bool driver = gauge.shift == 0;
+  auto seq_gf = [&](int p) __attribute__((always_inline)) -> int {
+    if (p < 3) return gBETA + p;
+    if (p < 9) return gGT + (p - 3);
+    if (p == 9) return gCHI;
+    if (p == 10) return gALPHA;
+    if (p < 14) return gXT + (p - 11);
+    if (p == 14) return gK;
+    if (p < 21) return gAT + (p - 15);
+    return gB + (p - 21);
+  };
+  const int nphase = driver ? 24 : 21;
+  // phase p computes from buffer p&1 after issuing phase p+1 into the other
+  auto begin = [&](int p) __attribute__((always_inline)) {
+    if (p + 1 < nphase) issue(seq_gf(p + 1), ((p + 1) & 1) ? buf1 : buf0);
+  };
+
+  const double alpha = val(gALPHA), chi = val(gCHI), K = val(gK);
   double g[6], gu[6];
 #pragma unroll
   for (int s = 0; s < 6; ++s) g[s] = val(gGT + s);
@@ -215,63 +289,80 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CHEMORA_WAV
     gu[0] = c00 * idet; gu[1] = c01 * idet; gu[2] = c02 * idet;
     gu[3] = c11 * idet; gu[4] = c12 * idet; gu[5] = c22 * idet;
   }
+  // traceless extrinsic curvature, raised (point values only)
+  double A[6], Au[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) A[s] = val(gAT + s);
+  {
+    double Am[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj)
+        Am[i][jj] = gu[S(i, 0)] * A[S(0, jj)] + gu[S(i, 1)] * A[S(1, jj)] + gu[S(i, 2)] * A[S(2, jj)];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int i = SI(s), jj = SJ(s);
+      Au[s] = Am[i][0] * gu[S(0, jj)] + Am[i][1] * gu[S(1, jj)] + Am[i][2] * gu[S(2, jj)];
+    }
+  }
 
-  CHEMORA_PHASE();
-  // ---- shift: d beta kept; d d beta contracted into the Gt source
-  double db[3][3];          // db[i][k] = d_k beta^i
+  issue(seq_gf(0), buf0);
+  sync();
+
+  // ---- shift (phases 0-2)
+  double db[3][3];
   double xts[3] = {0.0, 0.0, 0.0};
-  double ddiv[3] = {0.0, 0.0, 0.0};   // d_j d_k beta^k
+  double ddiv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    CHEMORA_PHASE();
+    begin(c);
+    auto tap = make_ops((c & 1) ? buf1 : buf0);
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) db[c][ax] = D1(gBETA + c, ax);
+    for (int ax = 0; ax < 3; ++ax) db[c][ax] = D1(tap, ax);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-      const double dd = D2(gBETA + c, q);
+      const double dd = D2(tap, q);
       xts[c] += W(q) * gu[q] * dd;
       const int qi = SI(q), qj = SJ(q);
       if (qj == c) ddiv[qi] += dd;
       if (qi == c && qi != qj) ddiv[qj] += dd;
     }
+    emit(gBETA + c, driver ? finish(tap, 0.75 * val(gB + c)) : 0.0);
+    keep(db[c]);
+    keep(xts);
+    keep(ddiv);
+    sync();
   }
-  keep(db);
-  keep(xts);
-  keep(ddiv);
-  CHEMORA_PHASE();
   const double divb = db[0][0] + db[1][1] + db[2][2];
-  if (gauge.shift == 0) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) emit(gBETA + c, finish(gBETA + c, 0.75 * val(gB + c)));
-  } else {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) emit(gBETA + c, 0.0);
-  }
 
-  CHEMORA_PHASE();
-  // ---- conformal metric: Christoffels, the d d gt part of the Ricci tensor
+  // ---- conformal metric (phases 3-8)
   double Ric[6];
-  double Gl[3][6];          // Gt_{k,ij}
+  double Gu[3][6];
+  double Gd[3];
   {
     double dg[6][3];
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-      CHEMORA_PHASE();
+      const int p = 3 + s;
+      begin(p);
+      auto tap = make_ops((p & 1) ? buf1 : buf0);
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) dg[s][ax] = D1(gGT + s, ax);
+      for (int ax = 0; ax < 3; ++ax) dg[s][ax] = D1(tap, ax);
       double r = 0.0;
 #pragma unroll
-      for (int q = 0; q < 6; ++q) r += W(q) * gu[q] * D2(gGT + s, q);
+      for (int q = 0; q < 6; ++q) r += W(q) * gu[q] * D2(tap, q);
       Ric[s] = -0.5 * r;
-      keep(Ric[s]);
-      keep(dg[s]);
       const int i = SI(s), jj = SJ(s);
       double lie = 0.0;
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) lie += g[S(i, kk)] * db[kk][jj] + g[S(jj, kk)] * db[kk][i];
-      const double At_s = val(gAT + s);
-      emit(gGT + s, finish(gGT + s, -2.0 * alpha * At_s + lie - (2.0 / 3.0) * g[s] * divb));
+      emit(gGT + s, finish(tap, -2.0 * alpha * A[s] + lie - (2.0 / 3.0) * g[s] * divb));
+      keep(Ric[s]);
+      keep(dg[s]);
+      sync();
     }
+    double Gl[3][6];
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
@@ -279,58 +370,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CHEMORA_WAV
         const int i = SI(s), jj = SJ(s);
         Gl[kk][s] = 0.5 * (dg[S(kk, i)][jj] + dg[S(kk, jj)][i] - dg[s][kk]);
       }
-  }
-  CHEMORA_PHASE();
-  double Gu[3][6];          // Gt^k_ij
-#pragma unroll
-  for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-    for (int s = 0; s < 6; ++s)
-      Gu[kk][s] = gu[S(kk, 0)] * Gl[0][s] + gu[S(kk, 1)] * Gl[1][s] + gu[S(kk, 2)] * Gl[2][s];
-  double Gd[3];
-#pragma unroll
-  for (int kk = 0; kk < 3; ++kk) {
-    double acc = 0.0;
-#pragma unroll
-    for (int s = 0; s < 6; ++s) acc += W(s) * gu[s] * Gu[kk][s];
-    Gd[kk] = acc;
-  }
-  keep(Gl);
-  keep(Gu);
-  keep(Gd);
-  // quadratic Christoffel terms of the Ricci tensor
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int i = SI(s), jj = SJ(s);
-    double r = Ric[s];
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk) r += 0.5 * Gd[kk] * (Gl[i][S(jj, kk)] + Gl[jj][S(i, kk)]);
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        // gt^lm Gt^k_li and gt^lm Gt^k_lj
-        const double gmi = gu[S(0, m)] * Gu[kk][S(0, i)] + gu[S(1, m)] * Gu[kk][S(1, i)] +
-                           gu[S(2, m)] * Gu[kk][S(2, i)];
-        const double gmj = gu[S(0, m)] * Gu[kk][S(0, jj)] + gu[S(1, m)] * Gu[kk][S(1, jj)] +
-                           gu[S(2, m)] * Gu[kk][S(2, jj)];
-        r += gmi * (Gl[jj][S(kk, m)] + Gl[kk][S(m, jj)]) + gmj * Gl[i][S(kk, m)];
-      }
-    Ric[s] = r;
+      for (int s = 0; s < 6; ++s)
+        Gu[kk][s] = gu[S(kk, 0)] * Gl[0][s] + gu[S(kk, 1)] * Gl[1][s] + gu[S(kk, 2)] * Gl[2][s];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+      double acc = 0.0;
+#pragma unroll
+      for (int s = 0; s < 6; ++s) acc += W(s) * gu[s] * Gu[kk][s];
+      Gd[kk] = acc;
+    }
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int i = SI(s), jj = SJ(s);
+      double r = Ric[s];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) r += 0.5 * Gd[kk] * (Gl[i][S(jj, kk)] + Gl[jj][S(i, kk)]);
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const double gmi = gu[S(0, m)] * Gu[kk][S(0, i)] + gu[S(1, m)] * Gu[kk][S(1, i)] +
+                             gu[S(2, m)] * Gu[kk][S(2, i)];
+          const double gmj = gu[S(0, m)] * Gu[kk][S(0, jj)] + gu[S(1, m)] * Gu[kk][S(1, jj)] +
+                             gu[S(2, m)] * Gu[kk][S(2, jj)];
+          r += gmi * (Gl[jj][S(kk, m)] + Gl[kk][S(m, jj)]) + gmj * Gl[i][S(kk, m)];
+        }
+      Ric[s] = r;
+    }
   }
+  // Gt^c_jk At^jk, the only later use of the Christoffel symbols besides chi/alpha
+  double ga[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc += W(q) * Gu[c][q] * Au[q];
+    ga[c] = acc;
+  }
+  keep(Gu);
+  keep(Gd);
+  keep(ga);
   keep(Ric);
 
-  CHEMORA_PHASE();
-  // ---- chi
+  // ---- chi (phase 9)
   double dchi[3];
-#pragma unroll
-  for (int ax = 0; ax < 3; ++ax) dchi[ax] = D1(gCHI, ax);
   const double ichi = 1.0 / chi;
   {
+    begin(9);
+    auto tap = make_ops(buf1);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) dchi[ax] = D1(tap, ax);
     double cdd[6];
 #pragma unroll
     for (int s = 0; s < 6; ++s)
-      cdd[s] = D2(gCHI, s) - (Gu[0][s] * dchi[0] + Gu[1][s] * dchi[1] + Gu[2][s] * dchi[2]);
+      cdd[s] = D2(tap, s) - (Gu[0][s] * dchi[0] + Gu[1][s] * dchi[1] + Gu[2][s] * dchi[2]);
     double trc = 0.0, dchi2 = 0.0;
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
@@ -341,40 +437,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CHEMORA_WAV
     for (int s = 0; s < 6; ++s)
       Ric[s] += 0.5 * ichi * (cdd[s] + g[s] * trc) -
                 0.25 * ichi * ichi * (dchi[SI(s)] * dchi[SJ(s)] + 3.0 * g[s] * dchi2);
-  }
-  keep(Ric);
-  keep(dchi);
-  emit(gCHI, finish(gCHI, (2.0 / 3.0) * chi * (alpha * K - divb)));
-
-  CHEMORA_PHASE();
-  // ---- evolved Gt: d Gt into the Ricci tensor; advection/dissipation kept
-  double xt_ad[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    CHEMORA_PHASE();
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const double d = D1(gXT + c, ax);
-      // +1/2 (gt_ci d_j Gt^c + gt_cj d_i Gt^c) for every (i, j) with ax in {i, j}
-#pragma unroll
-      for (int s = 0; s < 6; ++s) {
-        const int i = SI(s), jj = SJ(s);
-        if (jj == ax) Ric[s] += 0.5 * g[S(c, i)] * d;
-        if (i == ax) Ric[s] += 0.5 * g[S(c, jj)] * d;
-      }
-    }
-    xt_ad[c] = finish(gXT + c, 0.0);
-    keep(xt_ad[c]);
+    emit(gCHI, finish(tap, (2.0 / 3.0) * chi * (alpha * K - divb)));
     keep(Ric);
+    keep(dchi);
+    sync();
   }
 
-  CHEMORA_PHASE();
-  // ---- lapse: D_i D_j alpha
+  // ---- lapse (phase 10)
   double da[3];
-#pragma unroll
-  for (int ax = 0; ax < 3; ++ax) da[ax] = D1(gALPHA, ax);
   double DDa[6];
   {
+    begin(10);
+    auto tap = make_ops(buf0);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) da[ax] = D1(tap, ax);
     double gudchi_da = 0.0;
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk)
@@ -382,98 +458,159 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CHEMORA_WAV
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       const int i = SI(s), jj = SJ(s);
-      DDa[s] = D2(gALPHA, s) - (Gu[0][s] * da[0] + Gu[1][s] * da[1] + Gu[2][s] * da[2]) -
+      DDa[s] = D2(tap, s) - (Gu[0][s] * da[0] + Gu[1][s] * da[1] + Gu[2][s] * da[2]) -
                0.5 * ichi * (g[s] * gudchi_da - dchi[jj] * da[i] - dchi[i] * da[jj]);
     }
-  }
-  keep(da);
-  keep(DDa);
-  if (gauge.lapse == 2) {
-    emit(gALPHA, 0.0);
-  } else {
-    const double ra = gauge.lapse == 0 ? -2.0 * alpha * K : -alpha * alpha * K;
-    emit(gALPHA, finish(gALPHA, ra));
+    keep(da);
+    keep(DDa);
+    if (gauge.lapse == 2)
+      emit(gALPHA, 0.0);
+    else
+      emit(gALPHA, finish(tap, gauge.lapse == 0 ? -2.0 * alpha * K : -alpha * alpha * K));
+    sync();
   }
 
-  CHEMORA_PHASE();
-  // ---- traceless extrinsic curvature: mixed / raised forms
-  double A[6], Am[3][3], Au[6];
+  // ---- evolved Gt (phases 11-13)
+  double xt_ad[3];
 #pragma unroll
-  for (int s = 0; s < 6; ++s) A[s] = val(gAT + s);
+  for (int c = 0; c < 3; ++c) {
+    const int p = 11 + c;
+    begin(p);
+    auto tap = make_ops((p & 1) ? buf1 : buf0);
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+    for (int ax = 0; ax < 3; ++ax) {
+      const double d = D1(tap, ax);
 #pragma unroll
-    for (int jj = 0; jj < 3; ++jj)
-      Am[i][jj] = gu[S(i, 0)] * A[S(0, jj)] + gu[S(i, 1)] * A[S(1, jj)] + gu[S(i, 2)] * A[S(2, jj)];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int i = SI(s), jj = SJ(s);
-    Au[s] = Am[i][0] * gu[S(0, jj)] + Am[i][1] * gu[S(1, jj)] + Am[i][2] * gu[S(2, jj)];
+      for (int s = 0; s < 6; ++s) {
+        const int i = SI(s), jj = SJ(s);
+        if (jj == ax) Ric[s] += 0.5 * g[S(c, i)] * d;
+        if (i == ax) Ric[s] += 0.5 * g[S(c, jj)] * d;
+      }
+    }
+    xt_ad[c] = finish(tap, 0.0);
+    keep(xt_ad[c]);
+    keep(Ric);
+    sync();
   }
+
+  // ---- K (phase 14)
   double AA = 0.0;
+  {
+    double Am[3][3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int jj = 0; jj < 3; ++jj) AA += Am[i][jj] * Am[jj][i];
-
-  CHEMORA_PHASE();
-  // ---- K
+      for (int jj = 0; jj < 3; ++jj)
+        Am[i][jj] = gu[S(i, 0)] * A[S(0, jj)] + gu[S(i, 1)] * A[S(1, jj)] + gu[S(i, 2)] * A[S(2, jj)];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) AA += Am[i][jj] * Am[jj][i];
+  }
   double trDDa = 0.0, trRic = 0.0;
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     trDDa += W(s) * gu[s] * DDa[s];
     trRic += W(s) * gu[s] * Ric[s];
   }
-  double dK[3];
+  double xsrc[3];
+  {
+    begin(14);
+    auto tap = make_ops(buf0);
+    double dK[3];
 #pragma unroll
-  for (int ax = 0; ax < 3; ++ax) dK[ax] = D1(gK, ax);
-  keep(dK);
-  emit(gK, finish(gK, -chi * trDDa + alpha * (AA + K * K * (1.0 / 3.0))));
+    for (int ax = 0; ax < 3; ++ax) dK[ax] = D1(tap, ax);
+    emit(gK, finish(tap, -chi * trDDa + alpha * (AA + K * K * (1.0 / 3.0))));
+    // Gt source, complete now
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double r = xts[c];
+      r += (1.0 / 3.0) * (gu[S(c, 0)] * ddiv[0] + gu[S(c, 1)] * ddiv[1] + gu[S(c, 2)] * ddiv[2]);
+      r += (2.0 / 3.0) * Gd[c] * divb - (Gd[0] * db[c][0] + Gd[1] * db[c][1] + Gd[2] * db[c][2]);
+      r -= 2.0 * (Au[S(c, 0)] * da[0] + Au[S(c, 1)] * da[1] + Au[S(c, 2)] * da[2]);
+      const double adchi = Au[S(c, 0)] * dchi[0] + Au[S(c, 1)] * dchi[1] + Au[S(c, 2)] * dchi[2];
+      const double gdK = gu[S(c, 0)] * dK[0] + gu[S(c, 1)] * dK[1] + gu[S(c, 2)] * dK[2];
+      r += 2.0 * alpha * (ga[c] - 1.5 * ichi * adchi - (2.0 / 3.0) * gdK);
+      xsrc[c] = r;
+      emit(gXT + c, xt_ad[c] + r);
+    }
+    keep(xsrc);
+    sync();
+  }
 
-  CHEMORA_PHASE();
-  // ---- At
+  // ---- At (phases 15-20)
   const double trX = alpha * trRic - trDDa;
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
-    CHEMORA_PHASE();
+    const int p = 15 + s;
+    begin(p);
+    auto tap = make_ops((p & 1) ? buf1 : buf0);
     const int i = SI(s), jj = SJ(s);
     double la = 0.0, aa = 0.0;
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk) {
       la += A[S(i, kk)] * db[kk][jj] + A[S(jj, kk)] * db[kk][i];
-      aa += A[S(i, kk)] * Am[kk][jj];
+      // At_ik At^k_j = At_ik gt^kl At_lj
+      const double amkj = gu[S(kk, 0)] * A[S(0, jj)] + gu[S(kk, 1)] * A[S(1, jj)] + gu[S(kk, 2)] * A[S(2, jj)];
+      aa += A[S(i, kk)] * amkj;
     }
     const double X = alpha * Ric[s] - DDa[s];
-    emit(gAT + s, finish(gAT + s, chi * (X - (1.0 / 3.0) * g[s] * trX) + alpha * (K * A[s] - 2.0 * aa) + la -
-                                      (2.0 / 3.0) * A[s] * divb));
+    emit(gAT + s, finish(tap, chi * (X - (1.0 / 3.0) * g[s] * trX) + alpha * (K * A[s] - 2.0 * aa) + la -
+                              (2.0 / 3.0) * A[s] * divb));
+    sync();
   }
 
-  CHEMORA_PHASE();
-  // ---- Gt and the Gamma-driver B
+  // ---- Gamma-driver B (phases 21-23)
+  if (driver) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    CHEMORA_PHASE();
-    double r = xts[c];
-    r += (1.0 / 3.0) * (gu[S(c, 0)] * ddiv[0] + gu[S(c, 1)] * ddiv[1] + gu[S(c, 2)] * ddiv[2]);
-    r += (2.0 / 3.0) * Gd[c] * divb - (Gd[0] * db[c][0] + Gd[1] * db[c][1] + Gd[2] * db[c][2]);
-    r -= 2.0 * (Au[S(c, 0)] * da[0] + Au[S(c, 1)] * da[1] + Au[S(c, 2)] * da[2]);
-    double ga = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const int p = 21 + c;
+      begin(p);
+      auto tap = make_ops((p & 1) ? buf1 : buf0);
+      emit(gB + c, finish(tap, xsrc[c] - gauge.eta * val(gB + c)));
+      sync();
+    }
+  } else {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) ga += W(q) * Gu[c][q] * Au[q];
-    const double adchi = Au[S(c, 0)] * dchi[0] + Au[S(c, 1)] * dchi[1] + Au[S(c, 2)] * dchi[2];
-    const double gdK = gu[S(c, 0)] * dK[0] + gu[S(c, 1)] * dK[1] + gu[S(c, 2)] * dK[2];
-    r += 2.0 * alpha * (ga - 1.5 * ichi * adchi - (2.0 / 3.0) * gdK);
-    // r is the Gt source without advection and dissipation
-    emit(gXT + c, xt_ad[c] + r);
-    if (gauge.shift == 0)
-      emit(gB + c, finish(gB + c, r - gauge.eta * val(gB + c)));
-    else
-      emit(gB + c, 0.0);
+    for (int c = 0; c < 3; ++c) emit(gB + c, 0.0);
   }
 }
 
-// host-side launchers, one per order (defined in stage_o4.hip / stage_o8.hip)
-void launch_stage_o4(int mode, bool upwind, const StageArgs& a, hipStream_t s);
-void launch_stage_o8(int mode, bool upwind, const StageArgs& a, hipStream_t s);
+// The stage kernel.  Single-patch form (bt.ntiles == 0): one tile per
+// work-group, hardware block ids remapped so that each XCD gets a contiguous
+// range of tiles.  Batched form: a persistent grid strides over the
+// concatenated tiles of all patches of a plan; work-group b takes the
+// contiguous chunk of XCD (b mod 8), so neighbouring tiles share its L2.
+// One wave per SIMD: the double buffer takes 45-141 KB of the 160 KB LDS.
+template <int ORDER, bool UPWIND, int R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
+void stage_kernel(StageArgs a1, BatchTable bt) {
+  using L = LdsLayout<R, ORDER / 2>;
+  __shared__ double buf0[L::SIZEP];
+  __shared__ double buf1[L::SIZEP];
+  const bool batched = bt.ntiles > 0;
+  int first, last;
+  if (!batched) {
+    first = xcd_tile(blockIdx.x, gridDim.x);
+    last = first + 1;
+  } else {
+    const int G = gridDim.x;
+    const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+    const int per_xcd = (G + NXCD - 1) / NXCD;
+    const int chunk = (bt.ntiles + G - 1) / G;
+    first = (xcd * per_xcd + slot) * chunk;
+    last = min(first + chunk, bt.ntiles);
+  }
+  for (int t = first; t < last; ++t) {
+    int tt = t;
+    StageArgs a = a1;
+    if (batched) {
+      const int p = batch_patch(bt, t);
+      a = bt.args[p];
+      tt = t - bt.tile_start[p];
+    }
+    stage_tile<ORDER, UPWIND, R>(a, tt, buf0, buf1);
+  }
+}
 
 }  // namespace chemora

@@ -1,33 +1,23 @@
-// stage_o8.hip -- instances of the fused stage kernel for order-8
-// finite differences, and their launcher.
+// stage_o8.hip -- order-8 instances of the stage kernel and their launcher.
+// The staged axis reach R is 4 (centred, Kreiss-Oliger r <= 4) or 5 (upwinded, or r = 5).
 #include "stage_kernel.hpp"
 
 namespace chemora {
 
 namespace {
-template <bool UPWIND, int MODE>
-void launch(const StageArgs& a, hipStream_t s) {
-  dim3 block(TILE_X, TILE_Y, 1);
-  dim3 grid(a.tiles_x * a.tiles_y * a.geo.nz, 1, 1);
-  hipLaunchKernelGGL((stage_kernel<8, UPWIND, MODE>), grid, block, 0, s, a);
-}
-
-template <bool UPWIND>
-void by_mode(int mode, const StageArgs& a, hipStream_t s) {
-  switch (mode) {
-    case MODE_RHS: launch<UPWIND, MODE_RHS>(a, s); break;
-    case MODE_STAGE1: launch<UPWIND, MODE_STAGE1>(a, s); break;
-    case MODE_STAGE23: launch<UPWIND, MODE_STAGE23>(a, s); break;
-    default: launch<UPWIND, MODE_STAGE4>(a, s); break;
-  }
+template <bool UPWIND, int R>
+void launch(const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((stage_kernel<8, UPWIND, R>), dim3(grid), dim3(TILE_X, TILE_Y, 1), 0, s, a, bt);
 }
 }  // namespace
 
-void launch_stage_o8(int mode, bool upwind, const StageArgs& a, hipStream_t s) {
+void launch_stage_o8(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
   if (upwind)
-    by_mode<true>(mode, a, s);
+    launch<true, 5>(a, bt, grid, s);
+  else if (ko_r > 4)
+    launch<false, 5>(a, bt, grid, s);
   else
-    by_mode<false>(mode, a, s);
+    launch<false, 4>(a, bt, grid, s);
 }
 
 }  // namespace chemora

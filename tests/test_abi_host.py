@@ -133,3 +133,24 @@ def test_binding_refuses_to_run_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(C, "_lib", None)
     with pytest.raises(RuntimeError):
         C.lib()
+
+
+def test_plan_argument_checks_on_host():
+    p, g = _good()
+    P = C.make_params(p)
+    X = C.make_patch(g, FAKE)
+    out = ctypes.c_void_p(0)
+    sc = (ctypes.c_void_p * 1)(ctypes.c_void_p(FAKE + (1 << 34)))
+    arr = (C.chemora_patch * 1)(X)
+    L = C.lib()
+    assert L.chemora_plan_create(ctypes.byref(P), arr, sc, 0, 0.25, None, None, ctypes.byref(out)) == C.EINVAL
+    assert L.chemora_plan_create(ctypes.byref(P), arr, sc, 1, 0.0, None, None, ctypes.byref(out)) == C.EINVAL
+    assert L.chemora_plan_create(ctypes.byref(P), arr, sc, 1, 0.25, None, None, None) == C.EINVAL
+    bad = (C.chemora_patch * 2)(X, C.make_patch(g, 0))
+    sc2 = (ctypes.c_void_p * 2)(ctypes.c_void_p(FAKE + (1 << 34)), ctypes.c_void_p(FAKE + (1 << 35)))
+    assert L.chemora_plan_create(ctypes.byref(P), bad, sc2, 2, 0.25, None, None, ctypes.byref(out)) == C.EINVAL
+    assert "patch 1" in C.last_error()
+    assert out.value is None
+    assert L.chemora_batch_step(None, 1, None) == C.EINVAL
+    assert L.chemora_plan_destroy(None) == C.OK
+    assert L.chemora_plan_points(None) == 0

@@ -229,3 +229,95 @@ def test_check_finite(torch_cuda):
     P.u[0, w.grid.ghost, w.grid.ghost, w.grid.ghost] = float("inf")
     P.u[0, 0, 0, 0] = float("nan")                     # a ghost: not counted
     assert C.chemora_check_finite(P.params, P.patch) == 2
+
+
+def _small_patches(count=6, seed=5, off_axis=False):
+    rng = np.random.default_rng(seed)
+    grids = []
+    for p in range(count):
+        n = [int(v) for v in rng.integers(9, 40, size=3)]
+        h = 1.0 / 8.0 if p % 2 else 1.0 / 16.0
+        c = rng.uniform(-4, 4, size=3)
+        if off_axis:            # keep the patch at least ~1 M away from the punctures
+            c[1] = rng.uniform(3.5, 5.0)
+        grids.append(I.Grid(tuple(n), 3, h, tuple(float(c[a] - (n[a] - 1) * h / 2) for a in range(3))))
+    return grids
+
+
+def test_batched_plan_equals_per_patch_steps(torch_cuda):
+    """One plan over uneven patches (each its own h and dt = courant h)
+    advances every patch exactly as per-patch rk4_step calls do (bitwise:
+    the same tile code runs in both), and graph replays are deterministic."""
+    from paper_1307_6488_amd import chemora as C
+    torch = torch_cuda
+    params = I.workload(2).params
+    grids = _small_patches()
+    states = [I.brill_lindquist(g) for g in grids]
+    say("batched plan: " + " ".join(str(g.n) for g in grids))
+    courant = 0.25
+    B = C.Batch(params, grids, states, courant)
+    assert B.points() == sum(g.npoints for g in grids)
+    B.step(3)
+    torch.cuda.synchronize()
+    got = [p.u.cpu().numpy() for p in B.patches]
+    B2 = C.Batch(params, grids, states, courant)
+    B2.step(1)
+    B2.step(2)
+    torch.cuda.synchronize()
+    again = [p.u.cpu().numpy() for p in B2.patches]
+    for g, u0, a, b in zip(grids, states, got, again):
+        ref = gpu_rk4(torch, params, g, u0, courant * g.h, 3)
+        assert np.array_equal(a, ref, equal_nan=True)
+        assert np.array_equal(b, ref, equal_nan=True)
+    B.close()
+    B2.close()
+
+
+def test_batched_plan_matches_oracle(torch_cuda):
+    """Per-patch spacing and time step in the batched path against the oracle.
+    Brill-Lindquist data plus seeded 1e-4 sinusoids in every grid function, so
+    that no function starts identically zero (a function that starts at zero
+    is, after a few steps, a tiny remainder of large cancelling terms and its
+    max-norm-normalised error says nothing about the path)."""
+    from paper_1307_6488_amd import chemora as C
+    params = I.workload(2).params
+    grids = _small_patches(count=3, seed=9, off_axis=True)
+    states = []
+    for n, g in enumerate(grids):
+        u = I.brill_lindquist(g)
+        I.add_sinusoids(u, g, np.random.default_rng(40 + n), 1e-4, range(24), periodic_ghosts=False)
+        states.append(u)
+    B = C.Batch(params, grids, states, 0.25)
+    B.step(4)
+    torch_cuda.cuda.synchronize()
+    for g, u0, P in zip(grids, states, B.patches):
+        ref = oracle.rk4(params, g, u0, 0.25 * g.h, 4, nthreads=NTHREADS)
+        assert_parity(P.u.cpu().numpy(), ref, g, 1e-11, f"batched {g.n}")
+    B.close()
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.mark.parametrize("name,index", [("bl128_o4_100steps", 2), ("blpert192_o8_50steps", 3)])
+def test_full_size_evolution_against_oracle_samples(torch_cuda, name, index):
+    """Full-size multi-step evolution in the benchmark's launch configuration,
+    compared at the oracle's sampled points (tests/golden, written by
+    make_golden.py from the oracle alone), normalised per GF by the oracle's
+    max-norm over the whole grid; bar 1e-10."""
+    path = os.path.join(GOLDEN, name + ".npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{name}.npz not generated")
+    z = np.load(path)
+    w = I.workload(index)
+    steps = int(z["steps"])
+    say(f"full-size evolution {name}: {steps} steps on {w.grid.n}")
+    got = gpu_rk4(torch_cuda, w.params, w.grid, w.make_state(), float(z["dt"]), steps)
+    g = w.grid.ghost
+    idx = z["idx"]
+    samp = got[:, idx[:, 2] + g, idx[:, 1] + g, idx[:, 0] + g]
+    ref = z["samples"]
+    err = np.max(np.abs(samp - ref), axis=1) / np.maximum(z["maxabs"], 1e-300)
+    say(f"{name}: max err {err.max():.3e} ({I.GF_NAMES[int(np.argmax(err))]})")
+    assert np.all(np.isfinite(samp))
+    assert err.max() <= 1e-10, dict(zip(I.GF_NAMES, err.tolist()))
