@@ -21,6 +21,44 @@ import time
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
+# Floating-point operations of one right-hand-side evaluation per point, as
+# counted by the CPU oracle's counting scalar (+, -, *, / each one; no FMA):
+# order 4 upwind / KO r=3 and order 8 upwind / KO r=5.  The RK4 combination
+# adds 14 per grid function per step (2+2, 2+2, 2+2, 2).
+RHS_FLOPS = {4: 6931, 8: 11821}
+RK4_FLOPS = 24 * 14
+
+# HBM bytes per launch of the stage-2/3 kernel, from rocprofv3 counter runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same
+# counters read for a plain 2 GiB device copy (FETCH_SIZE reads half the
+# bytes copied: x2.0; WRITE_SIZE reads them exactly: x1.0).  They hold only
+# for the kernel sources they were taken with (hash below); otherwise the
+# bench reports traffic as null.
+MEASURED_TRAFFIC = {
+    "brill-lindquist-128^3-o4-upwind": {
+        "sources_sha256": "ad28883b6df6ea99d9b15f79d7e2217d1f9828e9e4a0c81945a2e436aee7c6ec",
+        "fetch_kib": 1.1675e6, "write_kib": 8.1106e5, "fetch_scale": 2.0, "write_scale": 1.0,
+    },
+}
+KERNEL_SOURCES = ["stage_kernel.hpp", "stage_common.hpp", "fd_ops.hpp", "stage_o4.hip"]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1307_6488_amd", "csrc")
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    m = MEASURED_TRAFFIC.get(workload)
+    if m is None or m["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024.0
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -30,6 +68,9 @@ def parse():
     ap.add_argument("--workload", type=int, default=2, choices=[2, 3])
     ap.add_argument("--n", type=int, default=0, help="override the interior edge (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (the reference "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     return ap.parse_args()
 
 
@@ -50,6 +91,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "launches": 3}), flush=True)
+        return
     w = I.workload(args.workload, n_override=args.n or None)
     u0 = w.make_state()
     npts = w.grid.npoints
@@ -94,6 +144,8 @@ def main():
     t23 = float(np.mean(stage_ms[:, 1:3])) * 1e-3
     bytes23 = 5 * 24 * 8 * npts
     achieved = bytes23 / t23 / 1e9
+    flops_update = 4 * RHS_FLOPS[w.params.fd_order] + RK4_FLOPS
+    traffic = measured_traffic(w.name)
     out = {
         "metric": "BSSN grid-point updates/s (one point advanced one full RK4 step), FP64",
         "value": value,
@@ -123,7 +175,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "kernel": "stage_kernel (RK4 stages 2/3)",
             "bytes_per_point": 960,
             "avg_launch_ms": t23 * 1e3,
@@ -131,6 +183,9 @@ def main():
         "step_roofline": {
             "algorithmic_bytes_per_update": 3072,
             "hbm_frac": value * 3072 / (HBM_PEAK_GBS * 1e9),
+            "flops_per_update": flops_update,
+            "fp64_frac": value * flops_update / (FP64_PEAK_TFLOPS * 1e12),
+            "stage23_traffic_over_algorithmic": None if traffic is None else traffic / bytes23,
         },
         "stage_ms": [float(x) for x in stage_ms.mean(axis=0)],
         "host_wall_s": wall,
@@ -140,20 +195,25 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(w, u0):
-    """The CPU oracle (plain C++, OpenMP) timed on this host: one RK4 step of
-    the same workload at full size."""
+def cpu_baseline(w, u0, min_seconds=10.0, max_steps=20):
+    """The CPU oracle (plain C++, OpenMP on every host core) timed on this
+    host: RK4 steps of the same full-size workload, repeated until at least
+    min_seconds have passed (a bounded sample of the run)."""
     root = os.path.dirname(os.path.abspath(__file__))
     if root not in sys.path:
         sys.path.insert(0, root)
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    u = u0
+    steps = 0
     t = time.perf_counter()
-    oracle.rk4(w.params, w.grid, u0, w.dt, 1, nthreads=threads)
+    while steps < max_steps and (steps == 0 or time.perf_counter() - t < min_seconds):
+        u = oracle.rk4(w.params, w.grid, u, w.dt, 1, nthreads=threads)
+        steps += 1
     dt = time.perf_counter() - t
-    return {"value": w.grid.npoints / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 RK4 step of the same {w.grid.n[0]}x{w.grid.n[1]}x{w.grid.n[2]} workload "
-                      f"({w.grid.npoints} point updates), {dt:.1f} s wall"}
+    return {"value": w.grid.npoints * steps / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} RK4 steps of the same {w.grid.n[0]}x{w.grid.n[1]}x{w.grid.n[2]} workload "
+                      f"({w.grid.npoints * steps} point updates), {dt:.1f} s wall"}
 
 
 if __name__ == "__main__":

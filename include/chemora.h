@@ -30,10 +30,12 @@
  * stores n[a] interior points plus `ghost` points on both sides; interior
  * point (0,0,0) is stored at (ghost, ghost, ghost) and sits at `origin`,
  * spacing h in all three directions.  Requirements:
- *     sy >= n[0] + 2g,  sz >= sy*(n[1] + 2g),  sf >= sz*(n[2] + 2g),
- *     sf*24 < 2^31 is NOT required (64-bit offsets), every pointer 8-byte
- *     aligned.  Row padding (sy > n[0]+2g) and the 3-D ghost corners are
- *     never read.
+ *     sy >= n[0] + 2g, and sy >= n[0] + 2g + 1 when n[0] is odd (the
+ *     stencil staging moves pairs of doubles and may read one element of
+ *     row padding), sz >= sy*(n[1] + 2g), sf >= sz*(n[2] + 2g),
+ *     24*sf*8 + 64 bytes <= 4 GiB (32-bit byte offsets), every pointer
+ *     8-byte aligned.  Row padding and the 3-D ghost corners never affect a
+ *     result (they may be read, never written; NaN there is harmless).
  * GF order: 0 chi | 1-6 gt_xx gt_xy gt_xz gt_yy gt_yz gt_zz | 7 K |
  *           8-13 At_xx..At_zz | 14-16 Gt^x Gt^y Gt^z | 17 alpha |
  *           18-20 beta^x beta^y beta^z | 21-23 B^x B^y B^z.

@@ -56,6 +56,8 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         L.oracle_rhs.argtypes = [P, G, dp, dp]
         L.oracle_rk4.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
+        L.oracle_rhs_ext.argtypes = [P, G, dp, dp]
+        L.oracle_rk4_ext.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_fill_periodic.argtypes = [G, dp]
         L.oracle_hamiltonian.argtypes = [P, G, dp, dp]
         L.oracle_rhs_point.argtypes = [P, dp, dp, dp, dp, dp, dp]
@@ -102,6 +104,27 @@ def rk4(params, grid, u: np.ndarray, dt: float, nsteps: int = 1, nthreads: int =
     v = np.ascontiguousarray(u.copy())
     _ok(lib().oracle_rk4(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), dt, nsteps,
                          _ptr(v)), "rk4")
+    return v
+
+
+def rhs_ext(params, grid, u: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """rhs() evaluated in x87 extended precision (64-bit significand), rounded
+    to FP64: the reference against which FP64 rounding error is measured."""
+    out = np.full(grid.shape, np.nan)
+    _ok(lib().oracle_rhs_ext(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), _ptr(u),
+                             _ptr(out)), "rhs_ext")
+    return out
+
+
+def ext_mantissa_bits() -> int:
+    return int(lib().oracle_ext_mant_dig())
+
+
+def rk4_ext(params, grid, u: np.ndarray, dt: float, nsteps: int = 1, nthreads: int = 0) -> np.ndarray:
+    """rk4() evaluated in x87 extended precision, rounded to FP64 at the end."""
+    v = np.ascontiguousarray(u.copy())
+    _ok(lib().oracle_rk4_ext(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), dt, nsteps,
+                             _ptr(v)), "rk4_ext")
     return v
 
 

@@ -21,8 +21,15 @@
 // sums are explicit loops over 3x3 arrays, nothing is fused or reordered for
 // speed.  The scalar type is a template parameter so the same code, run on a
 // counting scalar, reports the exact number of floating-point operations per
-// grid point (+, -, *, /; no FMA).  Build: g++ -O2 -ffp-contract=off.
+// grid point (+, -, *, /; no FMA), and, run in x87 extended precision (64-bit
+// significand), gives a reference of the same discrete scheme 11 bits more
+// accurate than FP64, against which the rounding error of any FP64
+// evaluation (this oracle's own included) can be measured.  Every rational
+// constant is formed in the scalar's own precision (the FP64 values are the
+// correctly rounded quotients, as before).  Build: g++ -O2 -ffp-contract=off.
 
+#include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -82,6 +89,7 @@ inline Counted operator/(Counted a, Counted b) { ++Counted::ndiv; return Counted
 inline Counted operator-(Counted a) { return Counted(-a.v); }
 inline bool nonneg(Counted a) { return a.v >= 0.0; }
 inline bool nonneg(double a) { return a >= 0.0; }
+inline bool nonneg(long double a) { return a >= 0.0L; }
 
 // ---------------------------------------------------------------------------
 // finite-difference weights.  Centred weights are the classical 4th/8th-order
@@ -90,36 +98,58 @@ inline bool nonneg(double a) { return a >= 0.0; }
 // Every operator is applied to differences u_{+k} - u_0 so that a constant
 // field gives exactly zero.
 // ---------------------------------------------------------------------------
-struct Weights {
-  int order;
-  int nc;          // number of centred offsets (order/2)
-  double c1[4];    // first derivative, offsets 1..nc (antisymmetric)
-  double c2[4];    // second derivative, offsets 1..nc (symmetric)
-  int up_lo, up_hi;
-  double up[9];    // lopsided weights for offsets up_lo..up_hi (entry for 0 unused)
+// Rational constants and per-grid factors in the scalar's own precision.  The
+// counting scalar takes FP64 constants without counting them.
+template <class R>
+struct Exact {
+  typedef double W;   // storage type of the stencil weights
+  static R ratio(int p, int q) { return R(double(p) / double(q)); }
+  static R quot(double a, double b) { return R(a / b); }
+  static R inv_sq(double h) { return R(1.0 / (h * h)); }
+};
+template <>
+struct Exact<long double> {
+  typedef long double W;
+  static long double ratio(int p, int q) { return (long double)p / (long double)q; }
+  static long double quot(double a, double b) { return (long double)a / (long double)b; }
+  static long double inv_sq(double h) { return 1.0L / ((long double)h * (long double)h); }
 };
 
-Weights make_weights(int order) {
-  Weights w;
+template <class W>
+struct WeightsT {
+  int order;
+  int nc;          // number of centred offsets (order/2)
+  W c1[4];         // first derivative, offsets 1..nc (antisymmetric)
+  W c2[4];         // second derivative, offsets 1..nc (symmetric)
+  int up_lo, up_hi;
+  W up[9];         // lopsided weights for offsets up_lo..up_hi (entry for 0 unused)
+};
+typedef WeightsT<double> Weights;
+
+template <class W>
+WeightsT<W> make_weights_t(int order) {
+  auto q = [](int a, int b) { return Exact<W>::ratio(a, b); };
+  WeightsT<W> w;
   std::memset(&w, 0, sizeof w);
   w.order = order;
   w.nc = order / 2;
   if (order == 4) {
-    w.c1[0] = 2.0 / 3.0;  w.c1[1] = -1.0 / 12.0;
-    w.c2[0] = 4.0 / 3.0;  w.c2[1] = -1.0 / 12.0;
+    w.c1[0] = q(2, 3);  w.c1[1] = q(-1, 12);
+    w.c2[0] = q(4, 3);  w.c2[1] = q(-1, 12);
     w.up_lo = -1; w.up_hi = 3;
-    const double u4[5] = {-3.0 / 12.0, -10.0 / 12.0, 18.0 / 12.0, -6.0 / 12.0, 1.0 / 12.0};
-    for (int i = 0; i < 5; ++i) w.up[i] = u4[i];
+    const int u4[5] = {-3, -10, 18, -6, 1};
+    for (int i = 0; i < 5; ++i) w.up[i] = q(u4[i], 12);
   } else {
-    w.c1[0] = 4.0 / 5.0;  w.c1[1] = -1.0 / 5.0;  w.c1[2] = 4.0 / 105.0;  w.c1[3] = -1.0 / 280.0;
-    w.c2[0] = 8.0 / 5.0;  w.c2[1] = -1.0 / 5.0;  w.c2[2] = 8.0 / 315.0;  w.c2[3] = -1.0 / 560.0;
+    w.c1[0] = q(4, 5);  w.c1[1] = q(-1, 5);  w.c1[2] = q(4, 105);  w.c1[3] = q(-1, 280);
+    w.c2[0] = q(8, 5);  w.c2[1] = q(-1, 5);  w.c2[2] = q(8, 315);  w.c2[3] = q(-1, 560);
     w.up_lo = -3; w.up_hi = 5;
-    const double u8[9] = {-1.0 / 168.0, 1.0 / 14.0, -1.0 / 2.0, -9.0 / 20.0, 5.0 / 4.0,
-                          -1.0 / 2.0, 1.0 / 6.0, -1.0 / 28.0, 1.0 / 280.0};
-    for (int i = 0; i < 9; ++i) w.up[i] = u8[i];
+    const int un[9] = {-1, 1, -1, -9, 5, -1, 1, -1, 1};
+    const int ud[9] = {168, 14, 2, 20, 4, 2, 6, 28, 280};
+    for (int i = 0; i < 9; ++i) w.up[i] = q(un[i], ud[i]);
   }
   return w;
 }
+Weights make_weights(int order) { return make_weights_t<double>(order); }
 
 double binom(int n, int k) {
   double r = 1.0;
@@ -129,15 +159,15 @@ double binom(int n, int k) {
 
 // Pointwise operators on one grid function.  f points at the evaluation point,
 // s is the element stride along the differentiation axis.
-template <class R>
-R op_d1(const double* f, long s, const Weights& w, R inv_h) {
+template <class R, class T, class W>
+R op_d1(const T* f, long s, const WeightsT<W>& w, R inv_h) {
   R acc = R(0.0);
   for (int k = 1; k <= w.nc; ++k) acc = acc + R(w.c1[k - 1]) * (R(f[k * s]) - R(f[-k * s]));
   return acc * inv_h;
 }
 
-template <class R>
-R op_d2(const double* f, long s, const Weights& w, R inv_h2) {
+template <class R, class T, class W>
+R op_d2(const T* f, long s, const WeightsT<W>& w, R inv_h2) {
   R acc = R(0.0);
   const R c = R(f[0]);
   for (int k = 1; k <= w.nc; ++k)
@@ -147,8 +177,8 @@ R op_d2(const double* f, long s, const Weights& w, R inv_h2) {
 
 // mixed derivative d_a d_b: outer first derivative (stride sa) of inner first
 // derivatives (stride sb), the inner differences formed at each outer offset.
-template <class R>
-R op_d11(const double* f, long sa, long sb, const Weights& w, R inv_h) {
+template <class R, class T, class W>
+R op_d11(const T* f, long sa, long sb, const WeightsT<W>& w, R inv_h) {
   R acc = R(0.0);
   for (int k = 1; k <= w.nc; ++k) {
     R dp = op_d1<R>(f + k * sa, sb, w, inv_h);
@@ -160,13 +190,13 @@ R op_d11(const double* f, long sa, long sb, const Weights& w, R inv_h) {
 
 // lopsided first derivative; positive = stencil shifted toward +axis (used
 // for a non-negative advecting velocity), else the mirror image.
-template <class R>
-R op_upwind(const double* f, long s, const Weights& w, bool positive, R inv_h) {
+template <class R, class T, class W>
+R op_upwind(const T* f, long s, const WeightsT<W>& w, bool positive, R inv_h) {
   R acc = R(0.0);
   const R c = R(f[0]);
   for (int o = w.up_lo; o <= w.up_hi; ++o) {
     if (o == 0) continue;
-    const double wt = w.up[o - w.up_lo];
+    const W wt = w.up[o - w.up_lo];
     if (positive)
       acc = acc + R(wt) * (R(f[o * s]) - c);
     else
@@ -178,8 +208,8 @@ R op_upwind(const double* f, long s, const Weights& w, bool positive, R inv_h) {
 // Kreiss-Oliger dissipation along one axis with radius r:
 //   Q u = (-1)^(r+1) eps / (2^(2r) h) * sum_m (-1)^m C(2r, m) u_{i + r - m},
 // written on the symmetric differences u_{+k} + u_{-k} - 2 u_0.
-template <class R>
-R op_ko(const double* f, long s, int r, R eps_over_h) {
+template <class R, class T>
+R op_ko(const T* f, long s, int r, R eps_over_h) {
   R acc = R(0.0);
   const R c = R(f[0]);
   const double scale = std::ldexp(1.0, -2 * r);
@@ -315,7 +345,7 @@ void rhs_point(const Opts& P, const R u[NGF], const R d1[NGF][3], const R d2[NGF
                const R adv[NGF], const R diss[NGF], R rhs[NGF]) {
   Geometry<R> G;
   geometry<R>(u, d1, d2, G);
-  const R third = R(1.0 / 3.0), two3 = R(2.0 / 3.0), two = R(2.0);
+  const R third = Exact<R>::ratio(1, 3), two3 = Exact<R>::ratio(2, 3), two = R(2.0);
 
   const R chi = u[CHI], K = u[TRK], alpha = u[ALPHA];
   R At[3][3];
@@ -477,7 +507,7 @@ R ham_point(const R u[NGF], const R d1[NGF][3], const R d2[NGF][6]) {
   R AA = R(0.0);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) AA = AA + Atm[i][j] * Atm[j][i];
-  return u[CHI] * trR + R(2.0 / 3.0) * u[TRK] * u[TRK] - AA;
+  return u[CHI] * trR + Exact<R>::ratio(2, 3) * u[TRK] * u[TRK] - AA;
 }
 
 // which GFs need first / second derivatives
@@ -492,13 +522,13 @@ struct Point {
   R u[NGF], d1[NGF][3], d2[NGF][6], adv[NGF], diss[NGF];
 };
 
-template <class R>
-void gather(const oracle_params& P, const oracle_grid& g, const Weights& w, const double* u, long idx,
-            bool want_rhs_terms, Point<R>& pt) {
+template <class R, class T>
+void gather(const oracle_params& P, const oracle_grid& g, const WeightsT<typename Exact<R>::W>& w, const T* u,
+            long idx, bool want_rhs_terms, Point<R>& pt) {
   const long st[3] = {1, g.sy, g.sz};
-  const R inv_h = R(1.0 / g.h), inv_h2 = R(1.0 / (g.h * g.h));
+  const R inv_h = Exact<R>::quot(1.0, g.h), inv_h2 = Exact<R>::inv_sq(g.h);
   for (int f = 0; f < NGF; ++f) {
-    const double* p = u + f * g.sf + idx;
+    const T* p = u + f * g.sf + idx;
     pt.u[f] = R(p[0]);
     for (int k = 0; k < 3; ++k) pt.d1[f][k] = R(0.0);
     for (int s = 0; s < 6; ++s) pt.d2[f][s] = R(0.0);
@@ -512,9 +542,9 @@ void gather(const oracle_params& P, const oracle_grid& g, const Weights& w, cons
   }
   if (!want_rhs_terms) return;
   const R beta[3] = {pt.u[BETA], pt.u[BETA + 1], pt.u[BETA + 2]};
-  const R eps_over_h = R(P.eps_diss / g.h);
+  const R eps_over_h = Exact<R>::quot(P.eps_diss, g.h);
   for (int f = 0; f < NGF; ++f) {
-    const double* p = u + f * g.sf + idx;
+    const T* p = u + f * g.sf + idx;
     R a = R(0.0);
     for (int k = 0; k < 3; ++k) {
       R dk = P.upwind ? op_upwind<R>(p, st[k], w, nonneg(beta[k]), inv_h) : pt.d1[f][k];
@@ -553,25 +583,27 @@ long at(const oracle_grid& g, int i, int j, int k) {
   return (long)(k + g.ghost) * g.sz + (long)(j + g.ghost) * g.sy + (i + g.ghost);
 }
 
-void rhs_grid(const oracle_params& P, const oracle_grid& g, const double* u, double* rhs) {
-  const Weights w = make_weights(P.fd_order);
+template <class T>
+void rhs_grid(const oracle_params& P, const oracle_grid& g, const T* u, T* rhs) {
+  const WeightsT<typename Exact<T>::W> w = make_weights_t<typename Exact<T>::W>(P.fd_order);
   const Opts o = {P.lapse, P.shift, P.eta};
 #pragma omp parallel for schedule(dynamic, 1)
   for (int k = 0; k < g.n[2]; ++k) {
-    Point<double> pt;
-    double r[NGF];
+    Point<T> pt;
+    T r[NGF];
     for (int j = 0; j < g.n[1]; ++j)
       for (int i = 0; i < g.n[0]; ++i) {
         const long idx = at(g, i, j, k);
-        gather<double>(P, g, w, u, idx, true, pt);
-        rhs_point<double>(o, pt.u, pt.d1, pt.d2, pt.adv, pt.diss, r);
+        gather<T>(P, g, w, u, idx, true, pt);
+        rhs_point<T>(o, pt.u, pt.d1, pt.d2, pt.adv, pt.diss, r);
         for (int f = 0; f < NGF; ++f) rhs[f * g.sf + idx] = r[f];
       }
   }
 }
 
 // periodic images into every ghost point (edges and corners included)
-void fill_periodic(const oracle_grid& g, double* u) {
+template <class T>
+void fill_periodic(const oracle_grid& g, T* u) {
   const int G = g.ghost;
 #pragma omp parallel for schedule(static)
   for (int k = -G; k < g.n[2] + G; ++k)
@@ -587,7 +619,8 @@ void fill_periodic(const oracle_grid& g, double* u) {
 }
 
 // out = base + c * k on interior points
-void axpy_interior(const oracle_grid& g, const double* base, double c, const double* k, double* out) {
+template <class T>
+void axpy_interior(const oracle_grid& g, const T* base, T c, const T* k, T* out) {
 #pragma omp parallel for schedule(static)
   for (int kz = 0; kz < g.n[2]; ++kz)
     for (int f = 0; f < NGF; ++f)
@@ -596,6 +629,37 @@ void axpy_interior(const oracle_grid& g, const double* base, double c, const dou
           const long idx = f * g.sf + at(g, i, j, kz);
           out[idx] = base[idx] + c * k[idx];
         }
+}
+
+// nsteps classic RK4 steps, u advanced in place.  Stage inputs take their
+// ghosts from u (static) or from periodic images (periodic).
+template <class T>
+void rk4(const oracle_params& P, const oracle_grid& g, double dt_in, int nsteps, T* u) {
+  const size_t N = (size_t)g.sf * NGF;
+  const T dt = T(dt_in), half = T(0.5), two = T(2.0), sixth = dt / T(6.0);
+  std::vector<T> k1(N, T(0.0)), k2(N, T(0.0)), k3(N, T(0.0)), k4(N, T(0.0)), s(u, u + N);
+  for (int step = 0; step < nsteps; ++step) {
+    rhs_grid<T>(P, g, u, k1.data());
+    std::copy(u, u + N, s.begin());   // ghosts of the stage input
+    axpy_interior<T>(g, u, half * dt, k1.data(), s.data());
+    if (P.bc == 1) fill_periodic<T>(g, s.data());
+    rhs_grid<T>(P, g, s.data(), k2.data());
+    axpy_interior<T>(g, u, half * dt, k2.data(), s.data());
+    if (P.bc == 1) fill_periodic<T>(g, s.data());
+    rhs_grid<T>(P, g, s.data(), k3.data());
+    axpy_interior<T>(g, u, dt, k3.data(), s.data());
+    if (P.bc == 1) fill_periodic<T>(g, s.data());
+    rhs_grid<T>(P, g, s.data(), k4.data());
+#pragma omp parallel for schedule(static)
+    for (int kz = 0; kz < g.n[2]; ++kz)
+      for (int f = 0; f < NGF; ++f)
+        for (int j = 0; j < g.n[1]; ++j)
+          for (int i = 0; i < g.n[0]; ++i) {
+            const long idx = f * g.sf + at(g, i, j, kz);
+            u[idx] = u[idx] + sixth * (k1[idx] + two * k2[idx] + two * k3[idx] + k4[idx]);
+          }
+    if (P.bc == 1) fill_periodic<T>(g, u);
+  }
 }
 
 }  // namespace
@@ -612,7 +676,7 @@ int oracle_required_ghost(int order, int upwind, int ko_radius) {
 int oracle_rhs(const oracle_params* P, const oracle_grid* g, const double* u, double* rhs) {
   if (check(P, g) || !u || !rhs) return -1;
   set_threads(P);
-  rhs_grid(*P, *g, u, rhs);
+  rhs_grid<double>(*P, *g, u, rhs);
   return 0;
 }
 
@@ -621,37 +685,44 @@ int oracle_rhs(const oracle_params* P, const oracle_grid* g, const double* u, do
 int oracle_rk4(const oracle_params* P, const oracle_grid* g, double dt, int nsteps, double* u) {
   if (check(P, g) || !u || !(dt > 0.0) || nsteps < 0) return -1;
   set_threads(P);
+  rk4<double>(*P, *g, dt, nsteps, u);
+  return 0;
+}
+
+// The same right-hand side and RK4 steps evaluated in x87 extended precision
+// (inputs and outputs FP64): the reference for measuring FP64 rounding error.
+int oracle_rhs_ext(const oracle_params* P, const oracle_grid* g, const double* u, double* rhs) {
+  if (check(P, g) || !u || !rhs) return -1;
+  set_threads(P);
   const size_t N = (size_t)g->sf * NGF;
-  std::vector<double> k1(N, 0.0), k2(N, 0.0), k3(N, 0.0), k4(N, 0.0), s(u, u + N);
-  for (int step = 0; step < nsteps; ++step) {
-    rhs_grid(*P, *g, u, k1.data());
-    std::memcpy(s.data(), u, N * sizeof(double));   // ghosts of the stage input
-    axpy_interior(*g, u, 0.5 * dt, k1.data(), s.data());
-    if (P->bc == 1) fill_periodic(*g, s.data());
-    rhs_grid(*P, *g, s.data(), k2.data());
-    axpy_interior(*g, u, 0.5 * dt, k2.data(), s.data());
-    if (P->bc == 1) fill_periodic(*g, s.data());
-    rhs_grid(*P, *g, s.data(), k3.data());
-    axpy_interior(*g, u, dt, k3.data(), s.data());
-    if (P->bc == 1) fill_periodic(*g, s.data());
-    rhs_grid(*P, *g, s.data(), k4.data());
-    const oracle_grid& G = *g;
-#pragma omp parallel for schedule(static)
-    for (int kz = 0; kz < G.n[2]; ++kz)
-      for (int f = 0; f < NGF; ++f)
-        for (int j = 0; j < G.n[1]; ++j)
-          for (int i = 0; i < G.n[0]; ++i) {
-            const long idx = f * G.sf + at(G, i, j, kz);
-            u[idx] = u[idx] + (dt / 6.0) * (k1[idx] + 2.0 * k2[idx] + 2.0 * k3[idx] + k4[idx]);
-          }
-    if (P->bc == 1) fill_periodic(*g, u);
-  }
+  std::vector<long double> U(u, u + N), K(N, 0.0L);
+  rhs_grid<long double>(*P, *g, U.data(), K.data());
+  for (int kz = 0; kz < g->n[2]; ++kz)
+    for (int f = 0; f < NGF; ++f)
+      for (int j = 0; j < g->n[1]; ++j)
+        for (int i = 0; i < g->n[0]; ++i) {
+          const long idx = f * g->sf + at(*g, i, j, kz);
+          rhs[idx] = (double)K[idx];
+        }
+  return 0;
+}
+
+// significand bits of the extended type (64 for x87)
+int oracle_ext_mant_dig(void) { return LDBL_MANT_DIG; }
+
+int oracle_rk4_ext(const oracle_params* P, const oracle_grid* g, double dt, int nsteps, double* u) {
+  if (check(P, g) || !u || !(dt > 0.0) || nsteps < 0) return -1;
+  set_threads(P);
+  const size_t N = (size_t)g->sf * NGF;
+  std::vector<long double> U(u, u + N);
+  rk4<long double>(*P, *g, dt, nsteps, U.data());
+  for (size_t i = 0; i < N; ++i) u[i] = (double)U[i];
   return 0;
 }
 
 int oracle_fill_periodic(const oracle_grid* g, double* u) {
   if (!g || !u) return -1;
-  fill_periodic(*g, u);
+  fill_periodic<double>(*g, u);
   return 0;
 }
 
@@ -668,7 +739,7 @@ int oracle_hamiltonian(const oracle_params* P, const oracle_grid* g, const doubl
     for (int j = 0; j < G.n[1]; ++j)
       for (int i = 0; i < G.n[0]; ++i) {
         const long idx = at(G, i, j, k);
-        gather<double>(*P, G, w, u, idx, false, pt);
+        gather<double, double>(*P, G, w, u, idx, false, pt);
         H[idx] = ham_point<double>(pt.u, pt.d1, pt.d2);
       }
   }
@@ -739,7 +810,7 @@ int oracle_count_rhs_flops(const oracle_params* P, const oracle_grid* g, const d
   Point<Counted> pt;
   Counted r[NGF];
   Counted::nadd = Counted::nmul = Counted::ndiv = 0;
-  gather<Counted>(*P, *g, w, u, at(*g, i, j, k), true, pt);
+  gather<Counted, double>(*P, *g, w, u, at(*g, i, j, k), true, pt);
   rhs_point<Counted>(o, pt.u, pt.d1, pt.d2, pt.adv, pt.diss, r);
   counts[0] = Counted::nadd;
   counts[1] = Counted::nmul;

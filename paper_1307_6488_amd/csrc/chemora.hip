@@ -124,6 +124,9 @@ int validate(const chemora_params* P, const chemora_patch* X) {
   if (X->reserved != 0) return fail(CHEMORA_EINVAL, "patch.reserved must be 0");
   const int64_t g2 = 2 * (int64_t)P->ghost;
   if (X->sy < X->n[0] + g2) return fail(CHEMORA_EINVAL, "sy %lld < nx + 2g", (long long)X->sy);
+  if ((X->n[0] & 1) && X->sy < X->n[0] + g2 + 1)
+    return fail(CHEMORA_EINVAL, "sy %lld: odd nx needs one element of row padding (sy >= nx + 2g + 1)",
+                (long long)X->sy);
   if (X->sz < X->sy * (X->n[1] + g2)) return fail(CHEMORA_EINVAL, "sz %lld < sy*(ny + 2g)", (long long)X->sz);
   if (X->sf < X->sz * (X->n[2] + g2)) return fail(CHEMORA_EINVAL, "sf %lld < sz*(nz + 2g)", (long long)X->sf);
   const int64_t tiles = (int64_t)((X->n[0] + 63) / 64) * ((X->n[1] + 3) / 4) * X->n[2];
@@ -240,7 +243,7 @@ int chemora_bssn_rhs(const chemora_params* params, const chemora_patch* patch, d
   const size_t bytes = (size_t)CHEMORA_NGF * patch->sf * sizeof(double);
   if (overlap(rhs, bytes, patch->u, bytes)) return fail(CHEMORA_EINVAL, "rhs overlaps patch.u");
   chemora::StageArgs a = base_args(params, patch);
-  a.in = patch->u;
+  a.in = a.un = a.yin = patch->u;
   a.out = rhs;
   a.mode = chemora::MODE_RHS;
   dispatch_stage(params, a, (hipStream_t)stream);
@@ -263,12 +266,36 @@ int rk4_checks(const chemora_params* params, const chemora_patch* patch, double 
   return CHEMORA_OK;
 }
 
-// One RK4 stage.  Buffers: u = u_n (overwritten by stage 4), SA/SB stage
-// inputs, Y accumulator.
+// Arguments of RK4 stage `stage` (1-4).  Buffers: u = u_n (overwritten by
+// stage 4), SA/SB stage inputs, Y accumulator.
 //   1: Y = u + dt/6 k1(u),  SA = u + dt/2 k1      3: Y += dt/3 k3(SB), SA = u + dt k3
 //   2: Y += dt/3 k2(SA),    SB = u + dt/2 k2      4: u = Y + dt/6 k4(SA)
+// Returns the buffer the stage writes.
+double* stage_args(chemora::StageArgs& a, int stage, double dt, double* u, double* SA, double* SB, double* Y) {
+  a.y = Y;
+  switch (stage) {
+    case 1:
+      a.in = u; a.un = u; a.yin = u; a.out = SA; a.cy = dt / 6.0; a.cs = 0.5 * dt;
+      a.mode = chemora::MODE_STAGE1;
+      return SA;
+    case 2:
+      a.in = SA; a.un = u; a.yin = Y; a.out = SB; a.cy = dt / 3.0; a.cs = 0.5 * dt;
+      a.mode = chemora::MODE_STAGE23;
+      return SB;
+    case 3:
+      a.in = SB; a.un = u; a.yin = Y; a.out = SA; a.cy = dt / 3.0; a.cs = dt;
+      a.mode = chemora::MODE_STAGE23;
+      return SA;
+    default:
+      a.in = SA; a.un = Y; a.yin = Y; a.out = u; a.cy = dt / 6.0; a.cs = 0.0;
+      a.mode = chemora::MODE_STAGE4;
+      return u;
+  }
+}
+
 int rk4_stage(const chemora_params* params, const chemora_patch* patch, int stage, double dt, double* scratch,
               hipStream_t s) {
+  if (stage < 1 || stage > 4) return fail(CHEMORA_EINVAL, "stage %d not in 1..4", stage);
   const size_t state = (size_t)CHEMORA_NGF * patch->sf;
   double* u = patch->u;
   double* SA = scratch;
@@ -276,38 +303,9 @@ int rk4_stage(const chemora_params* params, const chemora_patch* patch, int stag
   double* Y = scratch + 2 * state;
   const bool periodic = params->bc == CHEMORA_BC_PERIODIC;
   chemora::StageArgs a = base_args(params, patch);
-  a.un = u;
-  a.y = Y;
-  double* written = nullptr;
-  switch (stage) {
-    case 1:
-      if (!periodic) launch_ghosts(false, a.geo, u, SA, SB, s);
-      a.in = u; a.out = SA; a.cy = dt / 6.0; a.cs = 0.5 * dt;
-      a.mode = chemora::MODE_STAGE1;
-      dispatch_stage(params, a, s);
-      written = SA;
-      break;
-    case 2:
-      a.in = SA; a.out = SB; a.cy = dt / 3.0; a.cs = 0.5 * dt;
-      a.mode = chemora::MODE_STAGE23;
-      dispatch_stage(params, a, s);
-      written = SB;
-      break;
-    case 3:
-      a.in = SB; a.out = SA; a.cy = dt / 3.0; a.cs = dt;
-      a.mode = chemora::MODE_STAGE23;
-      dispatch_stage(params, a, s);
-      written = SA;
-      break;
-    case 4:
-      a.in = SA; a.un = nullptr; a.out = u; a.cy = dt / 6.0; a.cs = 0.0;
-      a.mode = chemora::MODE_STAGE4;
-      dispatch_stage(params, a, s);
-      written = u;
-      break;
-    default:
-      return fail(CHEMORA_EINVAL, "stage %d not in 1..4", stage);
-  }
+  if (stage == 1 && !periodic) launch_ghosts(false, a.geo, u, SA, SB, s);
+  double* written = stage_args(a, stage, dt, u, SA, SB, Y);
+  dispatch_stage(params, a, s);
   if (periodic) launch_ghosts(true, a.geo, nullptr, written, nullptr, s);
   return check_launch("rk4 stage");
 }
@@ -441,17 +439,11 @@ int chemora_plan_create(const chemora_params* params, const chemora_patch* patch
     double* Y = scratch[p] + 2 * state;
     chemora::StageArgs a = base_args(params, X);
     start[p + 1] = start[p] + a.tiles_x * a.tiles_y * a.geo.nz;
-    a.un = u;
-    a.y = Y;
-    chemora::StageArgs s1 = a, s2 = a, s3 = a, s4 = a;
-    s1.in = u;  s1.out = SA; s1.cy = dt / 6.0; s1.cs = 0.5 * dt; s1.mode = chemora::MODE_STAGE1;
-    s2.in = SA; s2.out = SB; s2.cy = dt / 3.0; s2.cs = 0.5 * dt; s2.mode = chemora::MODE_STAGE23;
-    s3.in = SB; s3.out = SA; s3.cy = dt / 3.0; s3.cs = dt;       s3.mode = chemora::MODE_STAGE23;
-    s4.in = SA; s4.out = u;  s4.cy = dt / 6.0; s4.cs = 0.0;      s4.mode = chemora::MODE_STAGE4; s4.un = nullptr;
-    args[0 * npatch + p] = s1;
-    args[1 * npatch + p] = s2;
-    args[2 * npatch + p] = s3;
-    args[3 * npatch + p] = s4;
+    for (int st = 0; st < 4; ++st) {
+      chemora::StageArgs sa = a;
+      stage_args(sa, st + 1, dt, u, SA, SB, Y);
+      args[st * npatch + p] = sa;
+    }
   }
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMalloc((void**)&pl->d_args, args.size() * sizeof(chemora::StageArgs));

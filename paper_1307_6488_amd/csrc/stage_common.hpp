@@ -43,18 +43,23 @@ struct Scales {
   int ko_r;
 };
 
-// What the kernel does with the right-hand side k it computed:
+// What the kernel does with the right-hand side k it computed, with
+// Y = yin[point] and U = un[point] read at every point in every mode:
 //   RHS     out = k
-//   STAGE1  y = u + cy k,   out = u + cs k      (u = in = un)
-//   STAGE23 y += cy k,      out = un + cs k
-//   STAGE4  out = y + cy k
+//   STAGE1  y = Y + cy k,   out = U + cs k      (yin = un = u_n)
+//   STAGE23 y = Y + cy k,   out = U + cs k      (yin = y, un = u_n)
+//   STAGE4  out = Y + cy k                      (yin = accumulator)
+// Pointers a mode does not need are set to an array the stage reads anyway
+// (in / u_n / the accumulator), so the unconditional reads cost no HBM
+// traffic and keep the kernel free of mode-dependent loads.
 enum Mode : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE23 = 2, MODE_STAGE4 = 4 };
 
 struct StageArgs {
   const double* __restrict__ in;   // stencil input of this stage
-  const double* __restrict__ un;   // u_n (stages 1-3)
-  double* __restrict__ y;          // RK accumulator
-  double* __restrict__ out;        // rhs (MODE_RHS), next stage input, or u (stage 4)
+  const double* un;                // U operand (see Mode)
+  const double* yin;               // Y operand (see Mode)
+  double* y;                       // RK accumulator written by stages 1-3
+  double* out;                     // rhs (MODE_RHS), next stage input, or u (stage 4)
   Geo geo;
   Scales sc;
   Gauge gauge;
@@ -123,12 +128,30 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
   return (bid % NXCD) * (nblocks / NXCD) + bid / NXCD;
 }
 
+// Values loaded from the plan tables are the same in every lane, but the
+// compiler cannot prove it (the kernel also writes global memory), and a
+// buffer descriptor held in vector registers turns every access into a
+// waterfall loop.  Broadcasting lane 0 puts them in scalar registers.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ StageArgs uniform_args(const StageArgs* p) {
+  constexpr int N = (int)(sizeof(StageArgs) / 4);
+  static_assert(sizeof(StageArgs) % 4 == 0, "StageArgs is a whole number of words");
+  int w[N];
+  __builtin_memcpy(w, p, sizeof(StageArgs));
+#pragma unroll
+  for (int i = 0; i < N; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  StageArgs a;
+  __builtin_memcpy(&a, w, sizeof(StageArgs));
+  return a;
+}
+
 // patch of global tile t (binary search over the prefix sums)
 __device__ __forceinline__ int batch_patch(const BatchTable& bt, int t) {
   int lo = 0, hi = bt.npatch - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (bt.tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+    if (uniform(bt.tile_start[mid]) <= t) lo = mid; else hi = mid - 1;
   }
   return lo;
 }

@@ -117,19 +117,56 @@ struct LdsLayout {
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
-// One tile t of a patch (x-tiles fastest, then y, then z), staged through
-// the two LDS buffers buf0 / buf1 (LdsLayout::SIZEP doubles each).  Every
+// s_waitcnt vmcnt(N) lgkmcnt(0) (gfx9 encoding: vmcnt bits 3:0 and 15:14,
+// expcnt 6:4 left at its maximum, lgkmcnt 11:8)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
+
+// Work-group barrier for LDS hand-over.  __syncthreads() adds work-group
+// scope release / acquire fences, which on gfx9 wait for every outstanding
+// vector-memory operation -- the staging loads of later phases included.
+// The LDS data a barrier hands over is already complete (wait_staged waits
+// for this wave's staging loads and, lgkmcnt(0), its LDS accesses), so only
+// the compiler must be kept from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Wait until this wave's staging loads of the next phase have landed in LDS
+// while the loads of the m phases issued after it (C chunks each at least)
+// may stay in flight.  Vector-memory loads complete in issue order, so at
+// most m*C outstanding operations imply the older loads are done; stores and
+// extra loads issued in between only make the wait longer.  m is
+// wave-uniform; NB - 2 is the most phases in flight behind the next one.
+template <int NB, int C>
+__device__ __forceinline__ void wait_staged(int m) {
+  if (NB >= 5 && m >= 3) wait_vm<3 * C>();
+  else if (NB >= 4 && m >= 2) wait_vm<2 * C>();
+  else if (NB >= 3 && m >= 1) wait_vm<C>();
+  else wait_vm<0>();
+}
+
+// One tile t of a patch, staged through the NB LDS buffers bufs[]
+// (LdsLayout::SIZEP doubles each): grid function p of the sequence goes to
+// bufs[p % NB], issued NB - 1 phases before it is used.  Tiles are numbered
+// x fastest, then z, then y, so that the work-groups in flight on one XCD
+// cover a block that is deep in z and share their z halos in its L2.  Every
 // work-item of the work-group must call it (it synchronises); it ends with a
 // barrier, so the buffers may be reused right after.
-template <int ORDER, bool UPWIND, int R>
-__device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* buf0, double* buf1) {
+template <int ORDER, bool UPWIND, int R, int NB>
+__device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* const (&bufs)[NB]) {
   using St = Stencil<ORDER>;
   constexpr int RM = ORDER / 2;
   using L = LdsLayout<R, RM>;
   const Geo G = a.geo;
   const int txi = t % a.tiles_x;
-  const int tyi = (t / a.tiles_x) % a.tiles_y;
-  const int k = t / (a.tiles_x * a.tiles_y);
+  const int k = (t / a.tiles_x) % G.nz;
+  const int tyi = t / (a.tiles_x * G.nz);
   // threadIdx.y is the wave index: uniform across the wave, so keep it (and
   // everything the staging derives from it) in scalar registers
   const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
@@ -149,21 +186,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
   // [c*128 + 2l, c*128 + 2l + 1] of chunks c = w, w+4, ...  Points outside
   // the patch's stored box (rows / columns of a ragged tile past the ghost
   // zone) are clamped into it: their LDS values are never read by a valid
-  // work-item.  A pair whose first double is the last stored column of the
-  // box is moved as one double through a register (bit q of `lone`), so no
-  // access leaves the box.  voff is biased by (R sz + R sy + R) so that it
-  // stays non-negative.
+  // work-item.  A pair whose first column is the last one of the box (odd nx
+  // only) reads one element of row padding, which the host guarantees
+  // (sy >= nx + 2g + 1 for odd nx), so no access leaves its row.  voff is
+  // biased by (R sz + R sy + R) so that it stays non-negative.
   const int xmax = G.nx - 1 + R - i0;       // last tile-relative column inside the box
   const int ymax = G.ny - 1 + R - j0;       // last tile-relative row inside the box
   const unsigned bias = (unsigned)R * (sz + sy + 1u);
   unsigned voff[L::CPW];
-  unsigned lone = 0;
 #pragma unroll
   for (int q = 0; q < L::CPW; ++q) {
     int x, y, dz;
     L::decode((wave + 4 * q) * L::CHUNK + 2 * lane, x, y, dz);
     y = min(y, ymax);
-    if (x == xmax) lone |= 1u << q;
     if (x > xmax) x = xmax - 1;
     voff[q] = (unsigned)(dz * (int)sz + y * (int)sy + x + (int)bias) * 8u;
   }
@@ -174,16 +209,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
     for (int q = 0; q < L::CPW; ++q) {
       const int c = wave + 4 * q;
       if (L::CPW * 4 != L::NCHUNK && c >= L::NCHUNK) break;   // wave-uniform
-      double* chunk = dst + c * L::CHUNK;
-      if (!((lone >> q) & 1u))
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr_t)chunk, 16, voff[q], so, 0, 0);
-      else
-        chunk[2 * lane] = bload(rin, voff[q], so);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr_t)(dst + c * L::CHUNK), 16, voff[q], so, 0, 0);
     }
-  };
-  auto sync = [&]() __attribute__((always_inline)) {
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
   };
 
   const int anchor = wave * L::P + lane;
@@ -234,24 +261,29 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
     }
     return (alg + adv) + diss;
   };
+  // RK epilogue.  Its operands (u_n / accumulator values at the point) are
+  // loaded by epi_load() before the phase issues its staging loads: loads
+  // complete in issue order, so a load issued after them would make its use
+  // wait for every staging load in flight.
   const int mode = a.mode;
-  auto emit = [&](int f, double kf) __attribute__((always_inline)) {
+  struct Epi {
+    double y, u;
+  };
+  const __amdgpu_buffer_rsrc_t ryin = state_rsrc(a.yin, G.sf), run = state_rsrc(a.un, G.sf);
+  auto epi_load = [&](int f) __attribute__((always_inline)) {
+    const unsigned so = spt + f * sf * 8u;
+    return Epi{bload(ryin, vpt, so), bload(run, vpt, so)};
+  };
+  auto emit = [&](int f, double kf, const Epi& e) __attribute__((always_inline)) {
     if (!valid) return;
     const unsigned so = spt + f * sf * 8u;
     if (mode == MODE_RHS) {
       bstore(state_rsrc(a.out, G.sf), vpt, so, kf);
-    } else if (mode == MODE_STAGE1) {
-      const double u0 = val(f);
-      bstore(state_rsrc(a.y, G.sf), vpt, so, u0 + a.cy * kf);
-      bstore(state_rsrc(a.out, G.sf), vpt, so, u0 + a.cs * kf);
-    } else if (mode == MODE_STAGE23) {
-      const double y0 = bload(state_rsrc(a.y, G.sf), vpt, so);
-      const double u0 = bload(state_rsrc(a.un, G.sf), vpt, so);
-      bstore(state_rsrc(a.y, G.sf), vpt, so, y0 + a.cy * kf);
-      bstore(state_rsrc(a.out, G.sf), vpt, so, u0 + a.cs * kf);
+    } else if (mode == MODE_STAGE4) {
+      bstore(state_rsrc(a.out, G.sf), vpt, so, e.y + a.cy * kf);
     } else {
-      const double y0 = bload(state_rsrc(a.y, G.sf), vpt, so);
-      bstore(state_rsrc(a.out, G.sf), vpt, so, y0 + a.cy * kf);
+      bstore(state_rsrc(a.y, G.sf), vpt, so, e.y + a.cy * kf);
+      bstore(state_rsrc(a.out, G.sf), vpt, so, e.u + a.cs * kf);
     }
   };
 
@@ -269,9 +301,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
     return gB + (p - 21);
   };
   const int nphase = driver ? 24 : 21;
-  // phase p computes from buffer p&1 after issuing phase p+1 into the other
+  // phase p computes from bufs[p % NB] after issuing phase p + NB - 1 into the
+  // buffer phase p - 1 used; at its end the next phase's buffer must be
+  // complete in every wave (own loads waited for, then the barrier)
+  // The scheduling barrier keeps the phase's pointwise loads (issued just
+  // before) ahead of its staging loads in the instruction stream.
   auto begin = [&](int p) __attribute__((always_inline)) {
-    if (p + 1 < nphase) issue(seq_gf(p + 1), ((p + 1) & 1) ? buf1 : buf0);
+    __builtin_amdgcn_sched_barrier(0);
+    if (p + NB - 1 < nphase) issue(seq_gf(p + NB - 1), bufs[(p + NB - 1) % NB]);
+  };
+  auto sync = [&](int p) __attribute__((always_inline)) {
+    wait_staged<NB, L::NCHUNK / 4>(min(p + NB - 1, nphase - 1) - (p + 1));
+    lds_barrier();
   };
 
   const double alpha = val(gALPHA), chi = val(gCHI), K = val(gK);
@@ -307,8 +348,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
     }
   }
 
-  issue(seq_gf(0), buf0);
-  sync();
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int p = 0; p < NB - 1; ++p)
+    if (p < nphase) issue(seq_gf(p), bufs[p]);
+  sync(-1);
 
   // ---- shift (phases 0-2)
   double db[3][3];
@@ -316,8 +360,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
   double ddiv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
+    const Epi e = epi_load(gBETA + c);
+    const double Bc = val(gB + c);
     begin(c);
-    auto tap = make_ops((c & 1) ? buf1 : buf0);
+    auto tap = make_ops(bufs[c % NB]);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) db[c][ax] = D1(tap, ax);
 #pragma unroll
@@ -328,11 +374,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
       if (qj == c) ddiv[qi] += dd;
       if (qi == c && qi != qj) ddiv[qj] += dd;
     }
-    emit(gBETA + c, driver ? finish(tap, 0.75 * val(gB + c)) : 0.0);
+    emit(gBETA + c, driver ? finish(tap, 0.75 * Bc) : 0.0, e);
     keep(db[c]);
     keep(xts);
     keep(ddiv);
-    sync();
+    sync(c);
   }
   const double divb = db[0][0] + db[1][1] + db[2][2];
 
@@ -345,8 +391,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       const int p = 3 + s;
+      const Epi e = epi_load(gGT + s);
       begin(p);
-      auto tap = make_ops((p & 1) ? buf1 : buf0);
+      auto tap = make_ops(bufs[p % NB]);
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) dg[s][ax] = D1(tap, ax);
       double r = 0.0;
@@ -357,10 +404,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
       double lie = 0.0;
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) lie += g[S(i, kk)] * db[kk][jj] + g[S(jj, kk)] * db[kk][i];
-      emit(gGT + s, finish(tap, -2.0 * alpha * A[s] + lie - (2.0 / 3.0) * g[s] * divb));
+      emit(gGT + s, finish(tap, -2.0 * alpha * A[s] + lie - (2.0 / 3.0) * g[s] * divb), e);
       keep(Ric[s]);
       keep(dg[s]);
-      sync();
+      sync(p);
     }
     double Gl[3][6];
 #pragma unroll
@@ -419,8 +466,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
   double dchi[3];
   const double ichi = 1.0 / chi;
   {
+    const Epi e = epi_load(gCHI);
     begin(9);
-    auto tap = make_ops(buf1);
+    auto tap = make_ops(bufs[9 % NB]);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) dchi[ax] = D1(tap, ax);
     double cdd[6];
@@ -437,18 +485,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
     for (int s = 0; s < 6; ++s)
       Ric[s] += 0.5 * ichi * (cdd[s] + g[s] * trc) -
                 0.25 * ichi * ichi * (dchi[SI(s)] * dchi[SJ(s)] + 3.0 * g[s] * dchi2);
-    emit(gCHI, finish(tap, (2.0 / 3.0) * chi * (alpha * K - divb)));
+    emit(gCHI, finish(tap, (2.0 / 3.0) * chi * (alpha * K - divb)), e);
     keep(Ric);
     keep(dchi);
-    sync();
+    sync(9);
   }
 
   // ---- lapse (phase 10)
   double da[3];
   double DDa[6];
   {
+    const Epi e = epi_load(gALPHA);
     begin(10);
-    auto tap = make_ops(buf0);
+    auto tap = make_ops(bufs[10 % NB]);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) da[ax] = D1(tap, ax);
     double gudchi_da = 0.0;
@@ -464,10 +513,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
     keep(da);
     keep(DDa);
     if (gauge.lapse == 2)
-      emit(gALPHA, 0.0);
+      emit(gALPHA, 0.0, e);
     else
-      emit(gALPHA, finish(tap, gauge.lapse == 0 ? -2.0 * alpha * K : -alpha * alpha * K));
-    sync();
+      emit(gALPHA, finish(tap, gauge.lapse == 0 ? -2.0 * alpha * K : -alpha * alpha * K), e);
+    sync(10);
   }
 
   // ---- evolved Gt (phases 11-13)
@@ -476,7 +525,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
   for (int c = 0; c < 3; ++c) {
     const int p = 11 + c;
     begin(p);
-    auto tap = make_ops((p & 1) ? buf1 : buf0);
+    auto tap = make_ops(bufs[p % NB]);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const double d = D1(tap, ax);
@@ -490,7 +539,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
     xt_ad[c] = finish(tap, 0.0);
     keep(xt_ad[c]);
     keep(Ric);
-    sync();
+    sync(p);
   }
 
   // ---- K (phase 14)
@@ -515,12 +564,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
   }
   double xsrc[3];
   {
+    const Epi e = epi_load(gK);
+    const Epi ex[3] = {epi_load(gXT), epi_load(gXT + 1), epi_load(gXT + 2)};
     begin(14);
-    auto tap = make_ops(buf0);
+    auto tap = make_ops(bufs[14 % NB]);
     double dK[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) dK[ax] = D1(tap, ax);
-    emit(gK, finish(tap, -chi * trDDa + alpha * (AA + K * K * (1.0 / 3.0))));
+    emit(gK, finish(tap, -chi * trDDa + alpha * (AA + K * K * (1.0 / 3.0))), e);
     // Gt source, complete now
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -532,10 +583,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
       const double gdK = gu[S(c, 0)] * dK[0] + gu[S(c, 1)] * dK[1] + gu[S(c, 2)] * dK[2];
       r += 2.0 * alpha * (ga[c] - 1.5 * ichi * adchi - (2.0 / 3.0) * gdK);
       xsrc[c] = r;
-      emit(gXT + c, xt_ad[c] + r);
+      emit(gXT + c, xt_ad[c] + r, ex[c]);
     }
     keep(xsrc);
-    sync();
+    sync(14);
   }
 
   // ---- At (phases 15-20)
@@ -543,8 +594,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     const int p = 15 + s;
+    const Epi e = epi_load(gAT + s);
     begin(p);
-    auto tap = make_ops((p & 1) ? buf1 : buf0);
+    auto tap = make_ops(bufs[p % NB]);
     const int i = SI(s), jj = SJ(s);
     double la = 0.0, aa = 0.0;
 #pragma unroll
@@ -556,8 +608,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
     }
     const double X = alpha * Ric[s] - DDa[s];
     emit(gAT + s, finish(tap, chi * (X - (1.0 / 3.0) * g[s] * trX) + alpha * (K * A[s] - 2.0 * aa) + la -
-                              (2.0 / 3.0) * A[s] * divb));
-    sync();
+                              (2.0 / 3.0) * A[s] * divb), e);
+    sync(p);
   }
 
   // ---- Gamma-driver B (phases 21-23)
@@ -565,14 +617,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int p = 21 + c;
+      const Epi e = epi_load(gB + c);
+      const double Bc = val(gB + c);
       begin(p);
-      auto tap = make_ops((p & 1) ? buf1 : buf0);
-      emit(gB + c, finish(tap, xsrc[c] - gauge.eta * val(gB + c)));
-      sync();
+      auto tap = make_ops(bufs[p % NB]);
+      emit(gB + c, finish(tap, xsrc[c] - gauge.eta * Bc), e);
+      sync(p);
     }
   } else {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) emit(gB + c, 0.0);
+    for (int c = 0; c < 3; ++c) emit(gB + c, 0.0, epi_load(gB + c));
   }
 }
 
@@ -581,13 +635,27 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* bu
 // range of tiles.  Batched form: a persistent grid strides over the
 // concatenated tiles of all patches of a plan; work-group b takes the
 // contiguous chunk of XCD (b mod 8), so neighbouring tiles share its L2.
-// One wave per SIMD: the double buffer takes 45-141 KB of the 160 KB LDS.
-template <int ORDER, bool UPWIND, int R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
+// One wave per SIMD (about 400 registers per lane); the NB staging buffers
+// take 88-141 KB of the 160 KB LDS.
+#ifndef CHEMORA_WAVES_PER_EU
+#define CHEMORA_WAVES_PER_EU 1
+#endif
+template <int ORDER, bool UPWIND, int R, int NB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CHEMORA_WAVES_PER_EU)))
 void stage_kernel(StageArgs a1, BatchTable bt) {
   using L = LdsLayout<R, ORDER / 2>;
-  __shared__ double buf0[L::SIZEP];
-  __shared__ double buf1[L::SIZEP];
+  static_assert(NB >= 2 && NB <= 5, "staging depth");
+  static_assert(NB * L::SIZEP * 8 <= 160 * 1024, "LDS");
+  // separate arrays, so the compiler can tell the buffers' staging loads apart
+  __shared__ double b0[L::SIZEP];
+  __shared__ double b1[L::SIZEP];
+  __shared__ double b2[NB > 2 ? L::SIZEP : 1];
+  __shared__ double b3[NB > 3 ? L::SIZEP : 1];
+  __shared__ double b4[NB > 4 ? L::SIZEP : 1];
+  double* const all[5] = {b0, b1, b2, b3, b4};
+  double* bufs[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) bufs[i] = all[i];
   const bool batched = bt.ntiles > 0;
   int first, last;
   if (!batched) {
@@ -606,10 +674,10 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
     StageArgs a = a1;
     if (batched) {
       const int p = batch_patch(bt, t);
-      a = bt.args[p];
-      tt = t - bt.tile_start[p];
+      a = uniform_args(bt.args + p);
+      tt = t - uniform(bt.tile_start[p]);
     }
-    stage_tile<ORDER, UPWIND, R>(a, tt, buf0, buf1);
+    stage_tile<ORDER, UPWIND, R, NB>(a, tt, bufs);
   }
 }
 

@@ -2,12 +2,17 @@
 // The staged axis reach R is 2 (centred, Kreiss-Oliger r <= 2) or 3 (upwinded, or r = 3).
 #include "stage_kernel.hpp"
 
+// staging buffers in flight: the staged neighbourhood is 22-28 KB, so 4 buffers fit with room to spare
+#ifndef CHEMORA_STAGING_DEPTH_O4
+#define CHEMORA_STAGING_DEPTH_O4 4
+#endif
+
 namespace chemora {
 
 namespace {
 template <bool UPWIND, int R>
 void launch(const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((stage_kernel<4, UPWIND, R>), dim3(grid), dim3(TILE_X, TILE_Y, 1), 0, s, a, bt);
+  hipLaunchKernelGGL((stage_kernel<4, UPWIND, R, CHEMORA_STAGING_DEPTH_O4>), dim3(grid), dim3(TILE_X, TILE_Y, 1), 0, s, a, bt);
 }
 }  // namespace
 

@@ -102,6 +102,15 @@ def test_invalid_patch_rejected_on_host():
     assert _call_rhs(p, g, rhs=FAKE + 8 * 100) == C.EINVAL
     assert "overlaps" in C.last_error()
     assert C.lib().chemora_bssn_rhs(None, None, None, None) == C.EINVAL
+    # odd nx needs one element of row padding
+    go = I.Grid((17, 16, 16), g.ghost, g.h)
+    X = C.make_patch(go, FAKE)
+    X.sy = 17 + 2 * g.ghost
+    X.sz = X.sy * (16 + 2 * g.ghost)
+    X.sf = X.sz * (16 + 2 * g.ghost)
+    assert C.lib().chemora_bssn_rhs(ctypes.byref(P), ctypes.byref(X), ctypes.c_void_p(FAKE + (1 << 34)),
+                                    None) == C.EINVAL
+    assert "row padding" in C.last_error()
     # periodic boundary needs n >= ghost
     p.bc = I.BC_PERIODIC
     gg = I.Grid((2, 16, 16), p.ghost, g.h)

@@ -1,0 +1,33 @@
+"""Host-side checks of bench.py (no GPU): its flop constants are the CPU
+oracle's own operation counts, and it refuses more than one GPU."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from paper_1307_6488_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("index", [2, 3])
+def test_rhs_flop_constants_match_oracle_count(orc, index):
+    w = I.workload(index, n_override=12)
+    counts = orc.count_rhs_flops(w.params, w.grid, w.make_state(), (4, 5, 6))
+    assert sum(counts) == bench.RHS_FLOPS[w.params.fd_order]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_traffic_is_null_once_kernel_sources_change(monkeypatch):
+    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "0" * 64)
+    assert bench.measured_traffic("brill-lindquist-128^3-o4-upwind") is None
+    assert bench.measured_traffic("no-such-workload") is None

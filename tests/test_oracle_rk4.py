@@ -130,3 +130,44 @@ def test_static_ghosts_unchanged_and_periodic_ghosts_are_images(orc):
         idx = np.arange(-g, n[3 - ax] + g) % n[3 - ax]
         ext = np.take(ext, idx, axis=ax)
     assert np.array_equal(o1[:, :, :, : w1.grid.ext[0]], ext)
+
+
+def _rk4_step_mp(f, y, dt):
+    k1 = f(y)
+    k2 = f([a + dt / 2 * b for a, b in zip(y, k1)])
+    k3 = f([a + dt / 2 * b for a, b in zip(y, k2)])
+    k4 = f([a + dt * b for a, b in zip(y, k3)])
+    return [a + dt / 6 * (b + 2 * c + 2 * d + e) for a, b, c, d, e in zip(y, k1, k2, k3, k4)]
+
+
+def test_extended_precision_rk4_step_is_the_exact_step_rounded(orc):
+    """The extended-precision oracle path (the FP64-rounding reference of the
+    GPU tests) on uniform data: one RK4 step of the ODE the system reduces to
+    (nonlinear chi / K / 1+log lapse, linear Gamma-driver pair), worked out in
+    40-digit arithmetic, must come back correctly rounded to FP64 (within
+    0.51 ulp).  Pins its 2/3, 1/3, 3/4 and dt/6 constants in its own precision."""
+    assert orc.ext_mantissa_bits() >= 64
+    v = _flat_values()
+    v[0], v[7], v[17] = 0.9, 0.3, 0.8                  # chi, K, alpha
+    v[18:21] = (0.1, -0.2, 0.05)
+    v[21:24] = (0.3, 0.1, -0.2)
+    eta, dt = 2.0, 0.37
+    grid, u = _uniform(v)
+    p = I.Params(fd_order=4, ghost=2, upwind=0, ko_radius=2, eps_diss=0.1, eta=eta, bc=I.BC_PERIODIC)
+    out = orc.rk4_ext(p, grid, u, dt, 1)
+    inner = out[(slice(None),) + grid.interior()]
+    with mpmath.workdps(40):
+        def f(y):
+            chi, K, a = y[0], y[1], y[2]
+            d = [mpmath.mpf(2) / 3 * chi * a * K, a * K * K / 3, -2 * a * K]
+            d += [mpmath.mpf(3) / 4 * y[6 + i] for i in range(3)]
+            d += [-mpmath.mpf(eta) * y[6 + i] for i in range(3)]
+            return d
+        y0 = [mpmath.mpf(float(v[i])) for i in (0, 7, 17, 18, 19, 20, 21, 22, 23)]
+        y1 = _rk4_step_mp(f, y0, mpmath.mpf(dt))
+    for slot, gf in enumerate((0, 7, 17, 18, 19, 20, 21, 22, 23)):
+        want = y1[slot]
+        ulp = np.spacing(abs(float(want)))
+        err = float(abs(mpmath.mpf(float(inner[gf].flat[0])) - want))
+        assert err <= 0.51 * ulp, (gf, err / ulp)
+        assert np.all(inner[gf] == inner[gf].flat[0])
