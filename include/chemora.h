@@ -133,7 +133,7 @@ int chemora_rk4_stage(const chemora_params *params, const chemora_patch *patch, 
  * A plan records a list of patches (each with its own spacing h, extents and
  * strides; all share params) and their RK4 scratch buffers.  One RK4 step of
  * every patch is captured once into a HIP graph: per RK stage a single
- * persistent launch covers the tiles of all patches.  Patch p advances with
+ * launch covers the tiles of all patches (one work-group per tile).  Patch p advances with
  * its own time step dt_p = courant * h_p.  Patches are independent (each
  * keeps its own ghosts); no data moves between patches. */
 typedef struct chemora_plan chemora_plan;   /* opaque, library-owned */

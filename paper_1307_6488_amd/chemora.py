@@ -13,7 +13,8 @@ import os
 from typing import Optional, Sequence
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libchemora.so")
+# the in-tree build; CHEMORA_LIB names another build of the same library
+LIB_PATH = os.environ.get("CHEMORA_LIB") or os.path.join(_HERE, "libchemora.so")
 
 OK, EINVAL, EDEVICE, ENOMEM, EUNSUPPORTED, ENOTFINITE = 0, -1, -2, -3, -4, -5
 NGF = 24

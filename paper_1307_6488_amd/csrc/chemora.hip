@@ -179,7 +179,7 @@ void dispatch_stage(const chemora_params* P, const chemora::StageArgs& a, hipStr
     chemora::launch_stage_o8(P->upwind != 0, P->ko_radius, a, none, tiles, s);
 }
 
-// batched form: a persistent grid over the plan's tile list
+// batched form: one work-group per tile of the plan's tile list
 void dispatch_batch(const chemora_params* P, const chemora::BatchTable& bt, int grid, hipStream_t s) {
   chemora::StageArgs none;
   std::memset(&none, 0, sizeof none);
@@ -369,7 +369,7 @@ struct chemora_plan {
   int npatch = 0;
   int64_t points = 0;
   int ntiles = 0;
-  int grid = 0;                                   // persistent work-groups per launch
+  int grid = 0;                                   // work-groups per launch (one per tile)
   chemora::StageArgs* d_args = nullptr;           // 4 stage tables of npatch entries
   int* d_tile_start = nullptr;
   hipStream_t capture = nullptr;
@@ -470,16 +470,8 @@ int chemora_plan_create(const chemora_params* params, const chemora_patch* patch
     return fail(CHEMORA_EDEVICE, "plan setup: %s", hipGetErrorString(e));
   }
 
-  // persistent grid: one 256-thread work-group per compute unit (the stage
-  // kernel runs one wave per SIMD: 64 KB-140 KB of LDS and ~390 registers)
-  int dev = 0, cus = 0;
-  if ((e = hipGetDevice(&dev)) == hipSuccess)
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess || cus <= 0) {
-    plan_free(pl);
-    return fail(CHEMORA_EDEVICE, "device query failed");
-  }
-  pl->grid = std::max(1, std::min(pl->ntiles, cus));
+  // one work-group per tile of the concatenated tile list
+  pl->grid = pl->ntiles;
 
   // capture one RK4 step
   e = hipStreamCreateWithFlags(&pl->capture, hipStreamNonBlocking);

@@ -158,7 +158,7 @@ __device__ __forceinline__ int batch_patch(const BatchTable& bt, int t) {
 
 // ---- host-side launchers, one per order (stage_o4.hip / stage_o8.hip) ----
 // Single-patch form: bt.ntiles == 0, grid = tiles of a.  Batched form: a is
-// unused, grid = persistent work-groups striding over bt's tiles.
+// unused, grid = bt.ntiles (one work-group per tile of the plan).
 void launch_stage_o4(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s);
 void launch_stage_o8(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s);
 

@@ -158,8 +158,8 @@ __device__ __forceinline__ void wait_staged(int m) {
 // cover a block that is deep in z and share their z halos in its L2.  Every
 // work-item of the work-group must call it (it synchronises); it ends with a
 // barrier, so the buffers may be reused right after.
-template <int ORDER, bool UPWIND, int R, int NB>
-__device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* const (&bufs)[NB]) {
+template <int ORDER, bool UPWIND, int R, int NB, bool BOUND, bool OFFS_LDS>
+__device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* const (&bufs)[NB], unsigned* offs) {
   using St = Stencil<ORDER>;
   constexpr int RM = ORDER / 2;
   using L = LdsLayout<R, RM>;
@@ -194,13 +194,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   const int ymax = G.ny - 1 + R - j0;       // last tile-relative row inside the box
   const unsigned bias = (unsigned)R * (sz + sy + 1u);
   unsigned voff[L::CPW];
+  // opaque copies: the decode depends only on lane and wave, and hoisted out
+  // of a batched kernel's tile loop it would hold 3 registers per chunk for
+  // the whole kernel; recomputed per tile it is a few dozen instructions
+  int lane_t = lane, wave_t = wave;
+  asm volatile("" : "+v"(lane_t));
+  asm volatile("" : "+s"(wave_t));
 #pragma unroll
   for (int q = 0; q < L::CPW; ++q) {
     int x, y, dz;
-    L::decode((wave + 4 * q) * L::CHUNK + 2 * lane, x, y, dz);
+    L::decode((wave_t + 4 * q) * L::CHUNK + 2 * lane_t, x, y, dz);
     y = min(y, ymax);
     if (x > xmax) x = xmax - 1;
     voff[q] = (unsigned)(dz * (int)sz + y * (int)sy + x + (int)bias) * 8u;
+    // OFFS_LDS: park the offsets in LDS (each lane reads back only its own
+    // slots, so no barrier is involved) and free their registers
+    if (OFFS_LDS) offs[q * 256 + wave * 64 + lane] = voff[q];
   }
   const unsigned tile_base = ((k + gg) * sz + (j0 + gg) * sy + i0 + gg + XB) * 8u - bias * 8u;
   auto issue = [&](int f, double* dst) __attribute__((always_inline)) {
@@ -209,40 +218,88 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     for (int q = 0; q < L::CPW; ++q) {
       const int c = wave + 4 * q;
       if (L::CPW * 4 != L::NCHUNK && c >= L::NCHUNK) break;   // wave-uniform
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr_t)(dst + c * L::CHUNK), 16, voff[q], so, 0, 0);
+      const unsigned vo = OFFS_LDS ? offs[q * 256 + wave * 64 + lane] : voff[q];
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr_t)(dst + c * L::CHUNK), 16, vo, so, 0, 0);
     }
   };
 
   const int anchor = wave * L::P + lane;
   // stencil access into the buffer of the current phase
+  // Stencil taps of the current phase's buffer.  Each phase addresses it from
+  // an opaque copy of the anchor: LDS reads are merged in pairs (8-bit
+  // offsets, +-2 KB), so a buffer needs a base register per 2 KB it spans,
+  // and shared across phases those bases would stay live through the whole
+  // kernel.  With wide (order-8) stencils every stencil group also takes a
+  // fresh copy, so a tap used by several groups is read again from LDS
+  // instead of being held in a register across the phase.
+  struct Taps {
+    const double* cur;
+    int anc;
+    __device__ __forceinline__ double operator()(int dx, int dy, int dz) const {
+      return cur[anc + L::off(dx, dy, dz)];
+    }
+    __device__ __forceinline__ Taps fresh() const {
+      Taps t = *this;
+      if (BOUND) asm volatile("" : "+v"(t.anc));
+      return t;
+    }
+  };
+  // BOUND: each stencil's result is materialised and followed by a
+  // scheduling barrier, so its taps die there.  Otherwise the combining
+  // arithmetic sinks below later stencils' reads, and with order-8 stencils
+  // the 64 taps of a mixed derivative (or more) are live at once and spill.
+  // It costs instruction-level parallelism, so order 4 uses it only where
+  // two waves share a SIMD (half the registers each).
+  auto bound = [&](double& v) __attribute__((always_inline)) {
+    if (BOUND) {
+      keep(v);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
   auto make_ops = [&](const double* cur) __attribute__((always_inline)) {
-    auto tap = [=](int dx, int dy, int dz) __attribute__((always_inline)) { return cur[anchor + L::off(dx, dy, dz)]; };
-    return tap;
+    int anc = anchor;
+    asm volatile("" : "+v"(anc));
+    return Taps{cur, anc};
   };
   const double bet[3] = {val(gBETA), val(gBETA + 1), val(gBETA + 2)};
-  auto D1 = [&](auto tap, int ax) __attribute__((always_inline)) {
-    return St::first([&](int o) { return ax == 0 ? tap(o, 0, 0) : (ax == 1 ? tap(0, o, 0) : tap(0, 0, o)); }) *
-           a.sc.d1;
+  auto D1 = [&](const Taps& t0, int ax) __attribute__((always_inline)) {
+    const Taps tap = t0.fresh();
+    double v =
+        St::first([&](int o) { return ax == 0 ? tap(o, 0, 0) : (ax == 1 ? tap(0, o, 0) : tap(0, 0, o)); }) * a.sc.d1;
+    bound(v);
+    return v;
   };
-  auto D2 = [&](auto tap, int slot) __attribute__((always_inline)) {
+  auto D2 = [&](const Taps& t0, int slot) __attribute__((always_inline)) {
+    const Taps tap = t0.fresh();
     const int ai = SI(slot), bj = SJ(slot);
     auto along = [&](int o) __attribute__((always_inline)) { return ai == 0 ? tap(o, 0, 0) : (ai == 1 ? tap(0, o, 0) : tap(0, 0, o)); };
-    if (ai == bj) return St::second(along) * a.sc.d2;
-    const double v = St::first([&](int oa) {
-      return St::first([&](int ob) {
-        int d[3] = {0, 0, 0};
-        d[ai] = oa;
-        d[bj] = ob;
-        return tap(d[0], d[1], d[2]);
-      });
-    });
-    return v * a.sc.d11;
+    double v;
+    if (ai == bj) {
+      v = St::second(along) * a.sc.d2;
+    } else {
+      // outer D1 along ai of inner D1's along bj; the barrier after each
+      // inner derivative bounds the live taps to one inner stencil
+      v = St::first([&](int oa) {
+        const Taps ti = tap.fresh();
+        double inner = St::first([&](int ob) {
+          int d[3] = {0, 0, 0};
+          d[ai] = oa;
+          d[bj] = ob;
+          return ti(d[0], d[1], d[2]);
+        });
+        bound(inner);
+        return inner;
+      }) * a.sc.d11;
+    }
+    bound(v);
+    return v;
   };
   // advection + dissipation of the staged GF; rhs = (algebra + adv) + diss
-  auto finish = [&](auto tap, double alg) __attribute__((always_inline)) {
+  auto finish = [&](const Taps& t0, double alg) __attribute__((always_inline)) {
     double adv = 0.0, diss = 0.0;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
+      const Taps tap = t0.fresh();
       auto along = [&](int o) __attribute__((always_inline)) { return ax == 0 ? tap(o, 0, 0) : (ax == 1 ? tap(0, o, 0) : tap(0, 0, o)); };
       double d;
       if (UPWIND) {
@@ -258,6 +315,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
         const double qd = ko_axis<R>(along, a.sc.ko_r, a.sc.ko);
         diss = (ax == 0) ? qd : diss + qd;
       }
+      bound(adv);
+      bound(diss);
     }
     return (alg + adv) + diss;
   };
@@ -331,22 +390,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     gu[3] = c11 * idet; gu[4] = c12 * idet; gu[5] = c22 * idet;
   }
   // traceless extrinsic curvature, raised (point values only)
-  double A[6], Au[6];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) A[s] = val(gAT + s);
-  {
-    double Am[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int jj = 0; jj < 3; ++jj)
-        Am[i][jj] = gu[S(i, 0)] * A[S(0, jj)] + gu[S(i, 1)] * A[S(1, jj)] + gu[S(i, 2)] * A[S(2, jj)];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      const int i = SI(s), jj = SJ(s);
-      Au[s] = Am[i][0] * gu[S(0, jj)] + Am[i][1] * gu[S(1, jj)] + Am[i][2] * gu[S(2, jj)];
-    }
-  }
 
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -392,6 +435,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     for (int s = 0; s < 6; ++s) {
       const int p = 3 + s;
       const Epi e = epi_load(gGT + s);
+      const double As = val(gAT + s);
       begin(p);
       auto tap = make_ops(bufs[p % NB]);
 #pragma unroll
@@ -404,7 +448,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       double lie = 0.0;
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) lie += g[S(i, kk)] * db[kk][jj] + g[S(jj, kk)] * db[kk][i];
-      emit(gGT + s, finish(tap, -2.0 * alpha * A[s] + lie - (2.0 / 3.0) * g[s] * divb), e);
+      emit(gGT + s, finish(tap, -2.0 * alpha * As + lie - (2.0 / 3.0) * g[s] * divb), e);
       keep(Ric[s]);
       keep(dg[s]);
       sync(p);
@@ -446,6 +490,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
           r += gmi * (Gl[jj][S(kk, m)] + Gl[kk][S(m, jj)]) + gmj * Gl[i][S(kk, m)];
         }
       Ric[s] = r;
+    }
+  }
+  // At_ij and At^ij (point values), loaded and formed here rather than at
+  // the start so that they are not live through the metric phases, where
+  // register pressure peaks (each metric phase loads the one component it
+  // needs; these loads hit in L2)
+  double A[6], Au[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) A[s] = val(gAT + s);
+  {
+    double Am[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj)
+        Am[i][jj] = gu[S(i, 0)] * A[S(0, jj)] + gu[S(i, 1)] * A[S(1, jj)] + gu[S(i, 2)] * A[S(2, jj)];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int i = SI(s), jj = SJ(s);
+      Au[s] = Am[i][0] * gu[S(0, jj)] + Am[i][1] * gu[S(1, jj)] + Am[i][2] * gu[S(2, jj)];
     }
   }
   // Gt^c_jk At^jk, the only later use of the Christoffel symbols besides chi/alpha
@@ -630,55 +694,42 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   }
 }
 
-// The stage kernel.  Single-patch form (bt.ntiles == 0): one tile per
-// work-group, hardware block ids remapped so that each XCD gets a contiguous
-// range of tiles.  Batched form: a persistent grid strides over the
-// concatenated tiles of all patches of a plan; work-group b takes the
-// contiguous chunk of XCD (b mod 8), so neighbouring tiles share its L2.
-// One wave per SIMD (about 400 registers per lane); the NB staging buffers
-// take 88-141 KB of the 160 KB LDS.
-#ifndef CHEMORA_WAVES_PER_EU
-#define CHEMORA_WAVES_PER_EU 1
-#endif
-template <int ORDER, bool UPWIND, int R, int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CHEMORA_WAVES_PER_EU)))
+// The stage kernel, one tile per work-group, hardware block ids remapped so
+// that each XCD gets a contiguous range of tiles (neighbours share its L2).
+// Single-patch form (bt.ntiles == 0): the tiles of patch a1.  Batched form:
+// the concatenated tiles of all patches of a plan, each work-group finding
+// its patch by binary search; the hardware dispatcher balances the uneven
+// patches dynamically.
+// WAVES work-groups share a CU (one wave per SIMD each): NB staging buffers
+// per work-group must fit the 160 KB LDS WAVES times, and with WAVES = 2 the
+// registers per lane halve to 256.
+template <int ORDER, bool UPWIND, int R, int NB, int WAVES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)))
 void stage_kernel(StageArgs a1, BatchTable bt) {
   using L = LdsLayout<R, ORDER / 2>;
   static_assert(NB >= 2 && NB <= 5, "staging depth");
-  static_assert(NB * L::SIZEP * 8 <= 160 * 1024, "LDS");
+  // with two work-groups per CU the per-lane staging offsets live in LDS
+  constexpr bool OFFS_LDS = WAVES >= 2;
+  static_assert(WAVES * (NB * L::SIZEP * 8 + (OFFS_LDS ? L::CPW * 256 * 4 : 0)) <= 160 * 1024, "LDS");
   // separate arrays, so the compiler can tell the buffers' staging loads apart
   __shared__ double b0[L::SIZEP];
   __shared__ double b1[L::SIZEP];
   __shared__ double b2[NB > 2 ? L::SIZEP : 1];
   __shared__ double b3[NB > 3 ? L::SIZEP : 1];
   __shared__ double b4[NB > 4 ? L::SIZEP : 1];
+  __shared__ unsigned offs[OFFS_LDS ? L::CPW * 256 : 1];
   double* const all[5] = {b0, b1, b2, b3, b4};
   double* bufs[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) bufs[i] = all[i];
-  const bool batched = bt.ntiles > 0;
-  int first, last;
-  if (!batched) {
-    first = xcd_tile(blockIdx.x, gridDim.x);
-    last = first + 1;
-  } else {
-    const int G = gridDim.x;
-    const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
-    const int per_xcd = (G + NXCD - 1) / NXCD;
-    const int chunk = (bt.ntiles + G - 1) / G;
-    first = (xcd * per_xcd + slot) * chunk;
-    last = min(first + chunk, bt.ntiles);
+  int t = xcd_tile(blockIdx.x, gridDim.x);
+  StageArgs a = a1;
+  if (bt.ntiles > 0) {
+    const int p = batch_patch(bt, t);
+    a = uniform_args(bt.args + p);
+    t -= uniform(bt.tile_start[p]);
   }
-  for (int t = first; t < last; ++t) {
-    int tt = t;
-    StageArgs a = a1;
-    if (batched) {
-      const int p = batch_patch(bt, t);
-      a = uniform_args(bt.args + p);
-      tt = t - uniform(bt.tile_start[p]);
-    }
-    stage_tile<ORDER, UPWIND, R, NB>(a, tt, bufs);
-  }
+  stage_tile<ORDER, UPWIND, R, NB, (ORDER >= 8 || WAVES >= 2), OFFS_LDS>(a, t, bufs, offs);
 }
 
 }  // namespace chemora

@@ -2,9 +2,16 @@
 // The staged axis reach R is 2 (centred, Kreiss-Oliger r <= 2) or 3 (upwinded, or r = 3).
 #include "stage_kernel.hpp"
 
-// staging buffers in flight: the staged neighbourhood is 22-28 KB, so 4 buffers fit with room to spare
+// Staging depth and work-groups per CU.  The staged neighbourhood of one
+// grid function is 22-28 KB: two buffers per work-group let two work-groups
+// share a CU (one wave per SIMD each, 256 registers per lane), which hides
+// more latency than a deeper pipeline at one wave per SIMD (4.0 vs 4.3 ms
+// per 128^3 RK4 step).
 #ifndef CHEMORA_STAGING_DEPTH_O4
-#define CHEMORA_STAGING_DEPTH_O4 4
+#define CHEMORA_STAGING_DEPTH_O4 2
+#endif
+#ifndef CHEMORA_WAVES_O4
+#define CHEMORA_WAVES_O4 2
 #endif
 
 namespace chemora {
@@ -12,7 +19,7 @@ namespace chemora {
 namespace {
 template <bool UPWIND, int R>
 void launch(const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((stage_kernel<4, UPWIND, R, CHEMORA_STAGING_DEPTH_O4>), dim3(grid), dim3(TILE_X, TILE_Y, 1), 0, s, a, bt);
+  hipLaunchKernelGGL((stage_kernel<4, UPWIND, R, CHEMORA_STAGING_DEPTH_O4, CHEMORA_WAVES_O4>), dim3(grid), dim3(TILE_X, TILE_Y, 1), 0, s, a, bt);
 }
 }  // namespace
 

@@ -2,9 +2,14 @@
 // The staged axis reach R is 4 (centred, Kreiss-Oliger r <= 4) or 5 (upwinded, or r = 5).
 #include "stage_kernel.hpp"
 
-// staging buffers in flight: the staged neighbourhood is 62-70 KB, so only 2 buffers fit
+// Staging depth and work-groups per CU.  The staged neighbourhood of one
+// grid function is 62-70 KB, so two buffers and one work-group (one wave per
+// SIMD) per CU is all the LDS holds.
 #ifndef CHEMORA_STAGING_DEPTH_O8
 #define CHEMORA_STAGING_DEPTH_O8 2
+#endif
+#ifndef CHEMORA_WAVES_O8
+#define CHEMORA_WAVES_O8 1
 #endif
 
 namespace chemora {
@@ -12,7 +17,7 @@ namespace chemora {
 namespace {
 template <bool UPWIND, int R>
 void launch(const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((stage_kernel<8, UPWIND, R, CHEMORA_STAGING_DEPTH_O8>), dim3(grid), dim3(TILE_X, TILE_Y, 1), 0, s, a, bt);
+  hipLaunchKernelGGL((stage_kernel<8, UPWIND, R, CHEMORA_STAGING_DEPTH_O8, CHEMORA_WAVES_O8>), dim3(grid), dim3(TILE_X, TILE_Y, 1), 0, s, a, bt);
 }
 }  // namespace
 
