@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--workload", type=int, default=2, choices=[2, 3])
     ap.add_argument("--n", type=int, default=0, help="override the interior edge (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="run the untuned default tile variant")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-patch batched form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -107,6 +109,11 @@ def main():
     scratch = P.scratch()
     stream = torch.cuda.current_stream()
     sp = scratch.data_ptr()
+    # the autotuner picks the tile variant of this patch's class (outside the
+    # timed region; it times stage-2 launches of this patch)
+    variant = C.chemora_tile_variant(P.params, P.patch) if args.no_tune else \
+        C.chemora_tune(P.params, P.patch, sp, None, stream)
+    tile = C.chemora_tile_variant_shape(variant)
 
     def step():
         for s in (1, 2, 3, 4):
@@ -168,6 +175,8 @@ def main():
             "ko_radius": w.params.ko_radius,
             "dt": w.dt,
             "boundary": "static",
+            "tile": f"{tile[0]}x{tile[1]}",
+            "tuned": not args.no_tune,
         },
         "roofline": {
             "bound": "hbm",
@@ -190,9 +199,44 @@ def main():
         "stage_ms": [float(x) for x in stage_ms.mean(axis=0)],
         "host_wall_s": wall,
     }
+    if not args.no_batched:
+        del P, scratch
+        torch.cuda.empty_cache()
+        out["batched"] = batched_form(C, I, torch, args.no_tune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, u0)
     print(json.dumps(out), flush=True)
+
+
+def batched_form(C, I, torch, no_tune, steps=10, warmup=2):
+    """The batched form: 64 patches of 24-96 points per edge (h = 1/8 or
+    1/16, Brill-Lindquist data on each patch's own domain, order 4 upwind,
+    static ghosts, dt = h/4 per patch), one plan, one captured RK4 step per
+    graph launch; the plan tunes the tile variant of every size class."""
+    grids = I.patch_list()
+    params = I.workload(2).params
+    states = [I.brill_lindquist(g) for g in grids]
+    npts = sum(g.npoints for g in grids)
+    B = C.Batch(params, grids, states, 0.25, tune_cache_path=None if no_tune else _tune_cache())
+    B.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    B.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    variants = sorted(set(B.variants()))
+    B.close()
+    return {"workload": "64 patches, 24-96 points per edge, order 4 upwind (batched plan)", "patches": len(grids),
+            "points": npts, "steps": steps, "ms_per_step": ms, "value": npts / (ms * 1e-3),
+            "unit": "updates/s", "tile_variants": [f"{a}x{b}" for a, b in map(C.chemora_tile_variant_shape, variants)]}
+
+
+def _tune_cache():
+    import tempfile
+    return os.path.join(tempfile.gettempdir(), f"chemora_tiles_{os.getpid()}.json")
 
 
 def cpu_baseline(w, u0, min_seconds=10.0, max_steps=20):

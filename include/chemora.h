@@ -129,6 +129,41 @@ int chemora_rk4_step(const chemora_params *params, const chemora_patch *patch, d
 int chemora_rk4_stage(const chemora_params *params, const chemora_patch *patch, int stage, double dt,
                       double *scratch, void *stream);
 
+/* ---- autotuner: tile variants per size class -----------------------------
+ * The stage kernel runs in one of several tile shapes ("variants": 0 = 64x4,
+ * 1 = 64x8, 2 = 32x8, 3 = 32x16 points per work-group, x by y; order 8
+ * builds 0 and 2).  All variants compute bit-identical results; they differ
+ * in lane use on ragged extents, halo overhead and occupancy.  The choice is
+ * kept per size class -- (GPU architecture, fd_order, upwind, staged reach,
+ * precision, bucket of n[0]: <=32 <=64 <=96 <=128 >128, bucket of n[1]:
+ * <=16 <=32 <=64 >64) -- in a process-wide table (thread-safe) that every
+ * call and plan consults; a class without an entry uses variant 2 (order 4)
+ * or 0 (order 8).  The
+ * paper tunes tile shapes with a model (section "Tile Size Selection"); here
+ * they are timed on the target GPU, as its autotuning sections describe. */
+
+/* Chooses the variant for patch's class: an entry already in the table (set,
+ * tuned or loaded) is kept; otherwise every built variant is timed on one
+ * RK4 stage-2 launch of this patch (reads patch.u and scratch, overwrites the
+ * S_B and accumulator parts of scratch; scratch as for chemora_rk4_step)
+ * and the fastest is recorded.  cache_path (may be NULL): a JSON cache read
+ * before and rewritten after (written to <path>.tmp, then renamed); entries
+ * of this process win over the file's.  Synchronises `stream`.  *variant
+ * (may be NULL) receives the choice.  Errors as chemora_rk4_step, EINVAL if
+ * the cache cannot be written, EDEVICE on HIP failure. */
+int chemora_tune(const chemora_params *params, const chemora_patch *patch, double *scratch,
+                 const char *cache_path, void *stream, int32_t *variant);
+
+/* Variant the library uses for patch's class (>= 0), or a negative status. */
+int chemora_tile_variant(const chemora_params *params, const chemora_patch *patch);
+
+/* Sets the variant of patch's class (EINVAL: unknown id; EUNSUPPORTED: not
+ * built for params->fd_order).  Takes effect for later calls and plans. */
+int chemora_set_tile_variant(const chemora_params *params, const chemora_patch *patch, int32_t variant);
+
+/* Tile extent of a variant in x and y (either pointer may be NULL). */
+int chemora_tile_variant_shape(int32_t variant, int32_t *tile_x, int32_t *tile_y);
+
 /* ---- batched form: many patches advanced together ------------------------
  * A plan records a list of patches (each with its own spacing h, extents and
  * strides; all share params) and their RK4 scratch buffers.  One RK4 step of
@@ -143,9 +178,14 @@ typedef struct chemora_plan chemora_plan;   /* opaque, library-owned */
  * caller, until chemora_plan_destroy.  With static ghosts the stage buffers'
  * ghosts are copied from u once, here, on `stream`.  Validation as for
  * chemora_rk4_step, per patch (EINVAL / EUNSUPPORTED before any HIP call);
- * courant must be finite and > 0; npatch >= 1.  tune_cache_path is reserved
- * (may be NULL).  Device tables and the graph are allocated here (ENOMEM or
- * EDEVICE on failure, nothing leaked). */
+ * courant must be finite and > 0; npatch >= 1.  Each patch runs with its
+ * class's tile variant (see chemora_tune).  tune_cache_path NULL: the
+ * variants chosen so far in this process (else the defaults).  Otherwise the
+ * cache file is read if it exists, every class of the plan without an entry
+ * is timed on its first patch (chemora_tune; this synchronises `stream` and
+ * overwrites that patch's scratch, before the ghosts are prepared), and the
+ * file is rewritten with all entries.  Device tables and the graph are
+ * allocated here (ENOMEM or EDEVICE on failure, nothing leaked). */
 int chemora_plan_create(const chemora_params *params, const chemora_patch *patches, double *const *scratch,
                         int32_t npatch, double courant, const char *tune_cache_path, void *stream,
                         chemora_plan **out);
@@ -156,6 +196,9 @@ int chemora_batch_step(chemora_plan *plan, int32_t nsteps, void *stream);
 
 /* Total interior points of the plan's patches (0 for NULL). */
 int64_t chemora_plan_points(const chemora_plan *plan);
+
+/* Tile variant the plan runs patch p (0 <= p < npatch) with; EINVAL else. */
+int chemora_plan_patch_variant(const chemora_plan *plan, int32_t p);
 
 /* Releases the plan (waits for its own work to finish).  NULL is a no-op. */
 int chemora_plan_destroy(chemora_plan *plan);

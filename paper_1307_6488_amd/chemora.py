@@ -24,6 +24,8 @@ EXPORTS = (
     "chemora_required_ghost", "chemora_bssn_rhs", "chemora_rk4_scratch_elems", "chemora_rk4_step",
     "chemora_rk4_stage", "chemora_check_finite", "chemora_last_error", "chemora_abi_version",
     "chemora_plan_create", "chemora_batch_step", "chemora_plan_points", "chemora_plan_destroy",
+    "chemora_plan_patch_variant", "chemora_tune", "chemora_tile_variant", "chemora_set_tile_variant",
+    "chemora_tile_variant_shape",
 )
 
 
@@ -79,6 +81,18 @@ def lib() -> ctypes.CDLL:
         L.chemora_plan_points.restype = ctypes.c_int64
         L.chemora_plan_destroy.argtypes = [ctypes.c_void_p]
         L.chemora_plan_destroy.restype = ctypes.c_int
+        L.chemora_plan_patch_variant.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.chemora_plan_patch_variant.restype = ctypes.c_int
+        L.chemora_tune.argtypes = [P, X, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_int32)]
+        L.chemora_tune.restype = ctypes.c_int
+        L.chemora_tile_variant.argtypes = [P, X]
+        L.chemora_tile_variant.restype = ctypes.c_int
+        L.chemora_set_tile_variant.argtypes = [P, X, ctypes.c_int32]
+        L.chemora_set_tile_variant.restype = ctypes.c_int
+        L.chemora_tile_variant_shape.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_int32)]
+        L.chemora_tile_variant_shape.restype = ctypes.c_int
         L.chemora_abi_version.argtypes = []
         L.chemora_abi_version.restype = ctypes.c_int
         _lib = L
@@ -91,6 +105,13 @@ def last_error() -> str:
 
 def _check(rc: int) -> int:
     if rc != OK:
+        raise ChemoraError(rc, last_error())
+    return rc
+
+
+def _check_id(rc: int) -> int:
+    """For calls that return a non-negative value or a negative status."""
+    if rc < 0:
         raise ChemoraError(rc, last_error())
     return rc
 
@@ -178,6 +199,34 @@ def chemora_plan_destroy(plan: int) -> int:
     return _check(lib().chemora_plan_destroy(ctypes.c_void_p(plan)))
 
 
+def chemora_plan_patch_variant(plan: int, p: int) -> int:
+    return _check_id(lib().chemora_plan_patch_variant(ctypes.c_void_p(plan), p))
+
+
+def chemora_tune(params: chemora_params, patch: chemora_patch, scratch_ptr: int, cache_path=None,
+                 stream=None) -> int:
+    """Tile variant of the patch's class (timed on this patch unless known)."""
+    v = ctypes.c_int32(-1)
+    _check(lib().chemora_tune(ctypes.byref(params), ctypes.byref(patch), ctypes.c_void_p(scratch_ptr),
+                              cache_path.encode() if cache_path else None, _stream(stream), ctypes.byref(v)))
+    return int(v.value)
+
+
+def chemora_tile_variant(params: chemora_params, patch: chemora_patch) -> int:
+    return _check_id(lib().chemora_tile_variant(ctypes.byref(params), ctypes.byref(patch)))
+
+
+def chemora_set_tile_variant(params: chemora_params, patch: chemora_patch, variant: int) -> int:
+    return _check(lib().chemora_set_tile_variant(ctypes.byref(params), ctypes.byref(patch), variant))
+
+
+def chemora_tile_variant_shape(variant: int):
+    """(tile_x, tile_y) of a tile variant."""
+    tx, ty = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().chemora_tile_variant_shape(variant, ctypes.byref(tx), ctypes.byref(ty)))
+    return int(tx.value), int(ty.value)
+
+
 def chemora_abi_version() -> int:
     return lib().chemora_abi_version()
 
@@ -214,6 +263,11 @@ class Patch:
         chemora_bssn_rhs(self.params, self.patch, out.data_ptr(), stream or torch.cuda.current_stream())
         return out
 
+    def tune(self, cache_path=None, stream=None) -> int:
+        import torch
+        return chemora_tune(self.params, self.patch, self.scratch().data_ptr(), cache_path,
+                            stream or torch.cuda.current_stream())
+
     def rk4_step(self, dt: float, nsteps: int = 1, stream=None):
         import torch
         s = stream or torch.cuda.current_stream()
@@ -226,13 +280,16 @@ class Patch:
 class Batch:
     """Several device-resident patches advanced together through a plan."""
 
-    def __init__(self, params, grids, states, courant: float, device="cuda"):
+    def __init__(self, params, grids, states, courant: float, device="cuda", tune_cache_path=None):
         import torch
         self.patches = [Patch(params, g, s, device=device) for g, s in zip(grids, states)]
         self.params = make_params(params)
         scr = [p.scratch().data_ptr() for p in self.patches]
-        self.plan = chemora_plan_create(self.params, [p.patch for p in self.patches], scr, courant, None,
-                                        torch.cuda.current_stream())
+        self.plan = chemora_plan_create(self.params, [p.patch for p in self.patches], scr, courant,
+                                        tune_cache_path, torch.cuda.current_stream())
+
+    def variants(self):
+        return [chemora_plan_patch_variant(self.plan, p) for p in range(len(self.patches))]
 
     def step(self, nsteps: int = 1, stream=None):
         import torch

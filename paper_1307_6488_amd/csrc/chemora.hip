@@ -11,13 +11,18 @@
 // "Automated Code Generation with Kranc", "Optimization").
 #include <hip/hip_runtime.h>
 
+#include <cctype>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -129,7 +134,8 @@ int validate(const chemora_params* P, const chemora_patch* X) {
                 (long long)X->sy);
   if (X->sz < X->sy * (X->n[1] + g2)) return fail(CHEMORA_EINVAL, "sz %lld < sy*(ny + 2g)", (long long)X->sz);
   if (X->sf < X->sz * (X->n[2] + g2)) return fail(CHEMORA_EINVAL, "sf %lld < sz*(nz + 2g)", (long long)X->sf);
-  const int64_t tiles = (int64_t)((X->n[0] + 63) / 64) * ((X->n[1] + 3) / 4) * X->n[2];
+  // the most tiles any variant makes (32 columns, 4 rows)
+  const int64_t tiles = (int64_t)((X->n[0] + 31) / 32) * ((X->n[1] + 3) / 4) * X->n[2];
   if (X->sz > INT32_MAX || tiles > INT32_MAX || X->n[1] + g2 > 65535 || X->n[2] + g2 > 65535)
     return fail(CHEMORA_EINVAL, "patch too large for the launch geometry");
   if (((uint64_t)CHEMORA_NGF * (uint64_t)X->sf + 8) * 8 > 0xFFFFFFFFull)
@@ -168,25 +174,156 @@ chemora::Scales make_scales(const chemora_params* P, double h) {
   return s;
 }
 
-// single-patch form: one work-group per tile
-void dispatch_stage(const chemora_params* P, const chemora::StageArgs& a, hipStream_t s) {
+// tile counts of tile variant v
+void set_tiles(chemora::StageArgs& a, int v) {
+  a.tiles_x = (a.geo.nx + chemora::VARIANTS[v].tx - 1) / chemora::VARIANTS[v].tx;
+  a.tiles_y = (a.geo.ny + chemora::variant_ty(v) - 1) / chemora::variant_ty(v);
+}
+
+// single-patch form: one work-group per tile (a's tile counts are set here)
+void dispatch_stage(const chemora_params* P, chemora::StageArgs& a, int v, hipStream_t s) {
   chemora::BatchTable none;
   std::memset(&none, 0, sizeof none);
+  set_tiles(a, v);
   const int tiles = a.tiles_x * a.tiles_y * a.geo.nz;
   if (P->fd_order == 4)
-    chemora::launch_stage_o4(P->upwind != 0, P->ko_radius, a, none, tiles, s);
+    chemora::launch_stage_o4(v, P->upwind != 0, P->ko_radius, a, none, tiles, s);
   else
-    chemora::launch_stage_o8(P->upwind != 0, P->ko_radius, a, none, tiles, s);
+    chemora::launch_stage_o8(v, P->upwind != 0, P->ko_radius, a, none, tiles, s);
 }
 
 // batched form: one work-group per tile of the plan's tile list
-void dispatch_batch(const chemora_params* P, const chemora::BatchTable& bt, int grid, hipStream_t s) {
+void dispatch_batch(const chemora_params* P, int v, const chemora::BatchTable& bt, hipStream_t s) {
   chemora::StageArgs none;
   std::memset(&none, 0, sizeof none);
   if (P->fd_order == 4)
-    chemora::launch_stage_o4(P->upwind != 0, P->ko_radius, none, bt, grid, s);
+    chemora::launch_stage_o4(v, P->upwind != 0, P->ko_radius, none, bt, bt.ntiles, s);
   else
-    chemora::launch_stage_o8(P->upwind != 0, P->ko_radius, none, bt, grid, s);
+    chemora::launch_stage_o8(v, P->upwind != 0, P->ko_radius, none, bt, bt.ntiles, s);
+}
+
+// ---------------------------------------------------------------------------
+// tile variants: the per-class choice and its cache
+// ---------------------------------------------------------------------------
+// Patches fall into classes by (GPU architecture, order, upwinding, staged
+// reach, precision, x-extent bucket, y-extent bucket); each class maps to a
+// tile variant, default_variant() unless tuned, set or loaded.
+std::mutex g_tune_mu;
+std::map<std::string, int> g_variant;            // class -> variant
+std::map<std::string, std::string> g_timing;     // class -> measured times (cache file detail)
+
+std::string device_arch() {
+  static std::mutex mu;
+  static std::map<int, std::string> known;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "unknown";
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = known.find(dev);
+  if (it != known.end()) return it->second;
+  std::string arch = "unknown";
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+  } else {
+    (void)hipGetLastError();
+  }
+  known[dev] = arch;
+  return arch;
+}
+
+int bucket(int n, const int* edges, int ne) {
+  int b = 0;
+  while (b < ne && n > edges[b]) ++b;
+  return b;
+}
+
+std::string class_key(const chemora_params* P, const chemora_patch* X) {
+  static const int xe[] = {32, 64, 96, 128};   // x extent: <=32 <=64 <=96 <=128 >128
+  static const int ye[] = {16, 32, 64};        // y extent: <=16 <=32 <=64 >64
+  char buf[192];
+  std::snprintf(buf, sizeof buf, "%s/o%d/u%d/r%d/fp64/x%d/y%d", device_arch().c_str(), P->fd_order,
+                P->upwind ? 1 : 0, required_ghost(P->fd_order, P->upwind, P->ko_radius), bucket(X->n[0], xe, 4),
+                bucket(X->n[1], ye, 3));
+  return buf;
+}
+
+// Variant of a class nobody tuned or set: 32 x 8 for order 4 (fastest in
+// most classes measured on MI355X, 64^3-128^3 and the 24-96 patches alike),
+// 64 x 4 for order 8.
+int default_variant(const chemora_params* P) { return P->fd_order == 4 ? 2 : 0; }
+
+int choose_variant(const chemora_params* P, const chemora_patch* X) {
+  const std::string key = class_key(P, X);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_variant.find(key);
+  return (it != g_variant.end() && chemora::variant_supported(P->fd_order, it->second)) ? it->second
+                                                                                      : default_variant(P);
+}
+
+std::string variant_name(int v) {
+  return std::to_string(chemora::VARIANTS[v].tx) + "x" + std::to_string(chemora::variant_ty(v));
+}
+
+// Reads a cache file (the JSON save_cache writes, in any whitespace layout):
+// every object member  "<class>": { ... "variant": <v> ... }  becomes a table
+// entry.  Entries already in the table (tuned or set in this process) win.
+void load_cache(const char* path) {
+  std::ifstream in(path);
+  if (!in) return;
+  std::stringstream ss;
+  ss << in.rdbuf();
+  const std::string text = ss.str();
+  auto skip = [&](size_t i) {
+    while (i < text.size() && std::isspace((unsigned char)text[i])) ++i;
+    return i;
+  };
+  std::string key;                     // the member whose object is open
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (size_t i = 0; i < text.size(); ++i) {
+    if (text[i] != '"') continue;
+    const size_t end = text.find('"', i + 1);
+    if (end == std::string::npos) break;
+    const std::string str = text.substr(i + 1, end - i - 1);
+    size_t k = skip(end + 1);
+    i = end;
+    if (k >= text.size() || text[k] != ':') continue;
+    k = skip(k + 1);
+    if (k < text.size() && text[k] == '{') {
+      key = str;
+    } else if (str == "variant" && !key.empty()) {
+      char* stop = nullptr;
+      const long v = std::strtol(text.c_str() + k, &stop, 10);
+      if (stop != text.c_str() + k && v >= 0 && v < chemora::NVARIANT && !g_variant.count(key)) g_variant[key] = (int)v;
+    }
+  }
+}
+
+int save_cache(const char* path) {
+  std::ostringstream o;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    o << "{\n  \"format\": \"chemora tile-variant cache\",\n  \"version\": 1,\n  \"entries\": {\n";
+    size_t i = 0;
+    for (const auto& kv : g_variant) {
+      o << "    \"" << kv.first << "\": {\"variant\": " << kv.second << ", \"tile\": \"" << variant_name(kv.second)
+        << "\"";
+      auto t = g_timing.find(kv.first);
+      if (t != g_timing.end()) o << ", \"ms\": {" << t->second << "}";
+      o << "}" << (++i < g_variant.size() ? "," : "") << "\n";
+    }
+    o << "  }\n}\n";
+  }
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream out(tmp, std::ios::trunc);
+    if (!out || !(out << o.str()) || !out.flush()) return fail(CHEMORA_EINVAL, "cannot write %s", tmp.c_str());
+  }
+  if (std::rename(tmp.c_str(), path) != 0) return fail(CHEMORA_EINVAL, "cannot rename %s to %s", tmp.c_str(), path);
+  return CHEMORA_OK;
 }
 
 int check_launch(const char* what) {
@@ -203,8 +340,7 @@ chemora::StageArgs base_args(const chemora_params* P, const chemora_patch* X) {
   a.gauge.lapse = P->lapse;
   a.gauge.shift = P->shift;
   a.gauge.eta = P->eta;
-  a.tiles_x = (X->n[0] + chemora::TILE_X - 1) / chemora::TILE_X;
-  a.tiles_y = (X->n[1] + chemora::TILE_Y - 1) / chemora::TILE_Y;
+  set_tiles(a, 0);
   return a;
 }
 
@@ -246,7 +382,7 @@ int chemora_bssn_rhs(const chemora_params* params, const chemora_patch* patch, d
   a.in = a.un = a.yin = patch->u;
   a.out = rhs;
   a.mode = chemora::MODE_RHS;
-  dispatch_stage(params, a, (hipStream_t)stream);
+  dispatch_stage(params, a, choose_variant(params, patch), (hipStream_t)stream);
   return check_launch("bssn_rhs");
 }
 
@@ -305,7 +441,7 @@ int rk4_stage(const chemora_params* params, const chemora_patch* patch, int stag
   chemora::StageArgs a = base_args(params, patch);
   if (stage == 1 && !periodic) launch_ghosts(false, a.geo, u, SA, SB, s);
   double* written = stage_args(a, stage, dt, u, SA, SB, Y);
-  dispatch_stage(params, a, s);
+  dispatch_stage(params, a, choose_variant(params, patch), s);
   if (periodic) launch_ghosts(true, a.geo, nullptr, written, nullptr, s);
   return check_launch("rk4 stage");
 }
@@ -362,15 +498,138 @@ int chemora_check_finite(const chemora_params* params, const chemora_patch* patc
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// autotuner (tile variants)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Times every tile variant built for the patch's order on a stage-2 launch
+// of the patch itself (reads u and S_A, writes S_B and Y of `scratch`): one
+// warm-up and three timed launches each, HIP events on `s`.  Synchronous.
+int time_variants(const chemora_params* P, const chemora_patch* X, double* scratch, hipStream_t s, int* best,
+                  std::string* timing) {
+  const size_t state = (size_t)CHEMORA_NGF * X->sf;
+  chemora::StageArgs a = base_args(P, X);
+  stage_args(a, 2, X->h * 0.25, X->u, scratch, scratch + state, scratch + 2 * state);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best_ms = 0.0f;
+  *best = 0;
+  std::ostringstream t;
+  for (int v = 0; v < chemora::NVARIANT && e == hipSuccess; ++v) {
+    if (!chemora::variant_supported(P->fd_order, v)) continue;
+    dispatch_stage(P, a, v, s);
+    e = hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) dispatch_stage(P, a, v, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) break;
+    ms /= 3.0f;
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "%s\"%s\": %.4f", t.tellp() > 0 ? ", " : "", variant_name(v).c_str(), ms);
+    t << buf;
+    if (v == 0 || ms < best_ms) {
+      best_ms = ms;
+      *best = v;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(CHEMORA_EDEVICE, "tuning: %s", hipGetErrorString(e));
+  *timing = t.str();
+  return CHEMORA_OK;
+}
+
+// The patch's class: its cached / set variant, else timed now (and recorded).
+int tune_class(const chemora_params* P, const chemora_patch* X, double* scratch, hipStream_t s, int* variant) {
+  const std::string key = class_key(P, X);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_variant.find(key);
+    if (it != g_variant.end() && chemora::variant_supported(P->fd_order, it->second)) {
+      *variant = it->second;
+      return CHEMORA_OK;
+    }
+  }
+  std::string timing;
+  int rc = time_variants(P, X, scratch, s, variant, &timing);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_variant[key] = *variant;
+  g_timing[key] = timing;
+  return CHEMORA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chemora_tune(const chemora_params* params, const chemora_patch* patch, double* scratch,
+                 const char* cache_path, void* stream, int32_t* variant) {
+  g_error.clear();
+  int rc = rk4_checks(params, patch, 1.0, scratch);
+  if (rc) return rc;
+  if (cache_path) load_cache(cache_path);
+  int v = 0;
+  if ((rc = tune_class(params, patch, scratch, (hipStream_t)stream, &v))) return rc;
+  if (cache_path && (rc = save_cache(cache_path))) return rc;
+  if (variant) *variant = v;
+  return CHEMORA_OK;
+}
+
+int chemora_tile_variant(const chemora_params* params, const chemora_patch* patch) {
+  g_error.clear();
+  int rc = validate(params, patch);
+  return rc ? rc : choose_variant(params, patch);
+}
+
+int chemora_set_tile_variant(const chemora_params* params, const chemora_patch* patch, int32_t variant) {
+  g_error.clear();
+  int rc = validate(params, patch);
+  if (rc) return rc;
+  if (variant < 0 || variant >= chemora::NVARIANT) return fail(CHEMORA_EINVAL, "tile variant %d unknown", variant);
+  if (!chemora::variant_supported(params->fd_order, variant))
+    return fail(CHEMORA_EUNSUPPORTED, "tile variant %d not built for order %d", variant, params->fd_order);
+  const std::string key = class_key(params, patch);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_variant[key] = variant;
+  g_timing.erase(key);
+  return CHEMORA_OK;
+}
+
+int chemora_tile_variant_shape(int32_t variant, int32_t* tile_x, int32_t* tile_y) {
+  g_error.clear();
+  if (variant < 0 || variant >= chemora::NVARIANT) return fail(CHEMORA_EINVAL, "tile variant %d unknown", variant);
+  if (tile_x) *tile_x = chemora::VARIANTS[variant].tx;
+  if (tile_y) *tile_y = chemora::variant_ty(variant);
+  return CHEMORA_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
 // plans (batched form)
 // ---------------------------------------------------------------------------
+// The plan's patches are grouped by tile variant; per RK stage every group
+// is one launch over the concatenated tiles of its patches.
+struct PlanGroup {
+  int variant;
+  int first;       // first entry of the group in the stage tables
+  int count;       // patches
+  int ntiles;
+  int toff;        // offset of its tile-start prefix sums (count + 1 entries)
+};
+
 struct chemora_plan {
   chemora_params params;
   int npatch = 0;
   int64_t points = 0;
-  int ntiles = 0;
-  int grid = 0;                                   // work-groups per launch (one per tile)
-  chemora::StageArgs* d_args = nullptr;           // 4 stage tables of npatch entries
+  std::vector<PlanGroup> groups;
+  std::vector<int> variant_of;                    // per patch (caller's order)
+  chemora::StageArgs* d_args = nullptr;           // 4 stage tables of npatch entries, group order
   int* d_tile_start = nullptr;
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
@@ -399,7 +658,6 @@ extern "C" {
 int chemora_plan_create(const chemora_params* params, const chemora_patch* patches, double* const* scratch,
                         int32_t npatch, double courant, const char* tune_cache_path, void* stream,
                         chemora_plan** out) {
-  (void)tune_cache_path;
   g_error.clear();
   if (!out) return fail(CHEMORA_EINVAL, "out is NULL");
   *out = nullptr;
@@ -407,47 +665,70 @@ int chemora_plan_create(const chemora_params* params, const chemora_patch* patch
   if (npatch < 1) return fail(CHEMORA_EINVAL, "npatch %d < 1", npatch);
   if (!(courant > 0.0) || !std::isfinite(courant)) return fail(CHEMORA_EINVAL, "courant must be finite and > 0");
   int rc;
-  int64_t tiles = 0, points = 0;
+  int64_t points = 0;
   for (int p = 0; p < npatch; ++p) {
     if ((rc = rk4_checks(params, &patches[p], courant * patches[p].h, scratch[p]))) {
       const std::string m = g_error;
       return fail(rc, "patch %d: %s", p, m.c_str());
     }
-    const chemora::StageArgs a = base_args(params, &patches[p]);
-    tiles += (int64_t)a.tiles_x * a.tiles_y * a.geo.nz;
     points += (int64_t)patches[p].n[0] * patches[p].n[1] * patches[p].n[2];
   }
-  if (tiles > INT32_MAX) return fail(CHEMORA_EINVAL, "too many tiles in the plan");
+  hipStream_t s = (hipStream_t)stream;
+
+  // tile variant of every patch: tuned classes from the cache, the rest
+  // timed now on the first patch of the class (then the cache is rewritten)
+  std::vector<int> var(npatch, 0);
+  if (tune_cache_path) {
+    load_cache(tune_cache_path);
+    for (int p = 0; p < npatch; ++p)
+      if ((rc = tune_class(params, &patches[p], scratch[p], s, &var[p]))) return rc;
+    if ((rc = save_cache(tune_cache_path))) return rc;
+  } else {
+    for (int p = 0; p < npatch; ++p) var[p] = choose_variant(params, &patches[p]);
+  }
 
   chemora_plan* pl = new (std::nothrow) chemora_plan;
   if (!pl) return fail(CHEMORA_ENOMEM, "host allocation failed");
   pl->params = *params;
   pl->npatch = npatch;
   pl->points = points;
-  pl->ntiles = (int)tiles;
+  pl->variant_of = var;
 
-  // per-stage argument tables and tile offsets (host side first)
+  // group order: patches sorted by variant (stable); per-stage argument
+  // tables in that order and per-group tile prefix sums (host side first)
+  std::vector<int> order(npatch);
+  for (int p = 0; p < npatch; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return var[x] < var[y]; });
   std::vector<chemora::StageArgs> args(4 * (size_t)npatch);
-  std::vector<int> start(npatch + 1, 0);
-  for (int p = 0; p < npatch; ++p) {
-    const chemora_patch* X = &patches[p];
-    const double dt = courant * X->h;
-    const size_t state = (size_t)CHEMORA_NGF * X->sf;
-    double* u = X->u;
-    double* SA = scratch[p];
-    double* SB = scratch[p] + state;
-    double* Y = scratch[p] + 2 * state;
-    chemora::StageArgs a = base_args(params, X);
-    start[p + 1] = start[p] + a.tiles_x * a.tiles_y * a.geo.nz;
-    for (int st = 0; st < 4; ++st) {
-      chemora::StageArgs sa = a;
-      stage_args(sa, st + 1, dt, u, SA, SB, Y);
-      args[st * npatch + p] = sa;
+  std::vector<int> starts;
+  for (int r = 0; r < npatch;) {
+    PlanGroup g{var[order[r]], r, 0, 0, (int)starts.size()};
+    starts.push_back(0);
+    int64_t tiles = 0;
+    for (; r < npatch && var[order[r]] == g.variant; ++r) {
+      const chemora_patch* X = &patches[order[r]];
+      double* sc = scratch[order[r]];
+      const size_t state = (size_t)CHEMORA_NGF * X->sf;
+      chemora::StageArgs a = base_args(params, X);
+      set_tiles(a, g.variant);
+      tiles += (int64_t)a.tiles_x * a.tiles_y * a.geo.nz;
+      if (tiles > INT32_MAX) {
+        plan_free(pl);
+        return fail(CHEMORA_EINVAL, "too many tiles in the plan");
+      }
+      starts.push_back((int)tiles);
+      for (int st = 0; st < 4; ++st) {
+        chemora::StageArgs sa = a;
+        stage_args(sa, st + 1, courant * X->h, X->u, sc, sc + state, sc + 2 * state);
+        args[st * (size_t)npatch + r] = sa;
+      }
+      ++g.count;
     }
+    g.ntiles = (int)tiles;
+    pl->groups.push_back(g);
   }
-  hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMalloc((void**)&pl->d_args, args.size() * sizeof(chemora::StageArgs));
-  if (e == hipSuccess) e = hipMalloc((void**)&pl->d_tile_start, start.size() * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&pl->d_tile_start, starts.size() * sizeof(int));
   if (e != hipSuccess) {
     plan_free(pl);
     (void)hipGetLastError();
@@ -455,7 +736,7 @@ int chemora_plan_create(const chemora_params* params, const chemora_patch* patch
   }
   e = hipMemcpyAsync(pl->d_args, args.data(), args.size() * sizeof(chemora::StageArgs), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(pl->d_tile_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(pl->d_tile_start, starts.data(), starts.size() * sizeof(int), hipMemcpyHostToDevice, s);
   // static ghosts of the stage buffers, once
   if (e == hipSuccess && params->bc == CHEMORA_BC_STATIC) {
     for (int p = 0; p < npatch && e == hipSuccess; ++p) {
@@ -470,9 +751,6 @@ int chemora_plan_create(const chemora_params* params, const chemora_patch* patch
     return fail(CHEMORA_EDEVICE, "plan setup: %s", hipGetErrorString(e));
   }
 
-  // one work-group per tile of the concatenated tile list
-  pl->grid = pl->ntiles;
-
   // capture one RK4 step
   e = hipStreamCreateWithFlags(&pl->capture, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(pl->capture, hipStreamCaptureModeThreadLocal);
@@ -482,16 +760,19 @@ int chemora_plan_create(const chemora_params* params, const chemora_patch* patch
   }
   const bool periodic = params->bc == CHEMORA_BC_PERIODIC;
   for (int st = 0; st < 4; ++st) {
-    chemora::BatchTable bt;
-    bt.args = pl->d_args + st * npatch;
-    bt.tile_start = pl->d_tile_start;
-    bt.npatch = npatch;
-    bt.ntiles = pl->ntiles;
-    dispatch_batch(params, bt, pl->grid, pl->capture);
+    for (const PlanGroup& g : pl->groups) {
+      chemora::BatchTable bt;
+      bt.args = pl->d_args + st * (size_t)npatch + g.first;
+      bt.tile_start = pl->d_tile_start + g.toff;
+      bt.npatch = g.count;
+      bt.ntiles = g.ntiles;
+      dispatch_batch(params, g.variant, bt, pl->capture);
+    }
     if (periodic)
-      for (int p = 0; p < npatch; ++p) {
-        const double* wr = args[st * npatch + p].out;
-        launch_ghosts(true, make_geo(params, &patches[p]), nullptr, const_cast<double*>(wr), nullptr, pl->capture);
+      for (int r = 0; r < npatch; ++r) {
+        const double* wr = args[st * (size_t)npatch + r].out;
+        launch_ghosts(true, make_geo(params, &patches[order[r]]), nullptr, const_cast<double*>(wr), nullptr,
+                      pl->capture);
       }
   }
   hipError_t le = hipGetLastError();
@@ -507,6 +788,13 @@ int chemora_plan_create(const chemora_params* params, const chemora_patch* patch
   }
   *out = pl;
   return CHEMORA_OK;
+}
+
+int chemora_plan_patch_variant(const chemora_plan* plan, int32_t p) {
+  g_error.clear();
+  if (!plan) return fail(CHEMORA_EINVAL, "plan is NULL");
+  if (p < 0 || p >= plan->npatch) return fail(CHEMORA_EINVAL, "patch %d not in the plan", p);
+  return plan->variant_of[p];
 }
 
 int chemora_batch_step(chemora_plan* plan, int32_t nsteps, void* stream) {

@@ -65,7 +65,7 @@ struct StageArgs {
   Gauge gauge;
   double cy;                       // weight of k in the accumulator update
   double cs;                       // weight of k in the next stage input
-  int tiles_x, tiles_y;            // tile grid (TILE_X x TILE_Y points per tile)
+  int tiles_x, tiles_y;            // tile grid of the launch's tile variant
   int mode;                        // a Mode
 };
 
@@ -78,8 +78,6 @@ struct BatchTable {
   int ntiles;
 };
 
-constexpr int TILE_X = 64;
-constexpr int TILE_Y = 4;
 constexpr int NXCD = 8;
 
 // ---- device helpers ------------------------------------------------------
@@ -156,10 +154,26 @@ __device__ __forceinline__ int batch_patch(const BatchTable& bt, int t) {
   return lo;
 }
 
+// ---- tile variants: the launch shapes the tuner chooses among -----------
+// TX columns x WPG waves per work-group (a wave covers 64 / TX rows).
+struct TileVariant {
+  int tx, wpg;
+};
+constexpr int NVARIANT = 4;
+constexpr TileVariant VARIANTS[NVARIANT] = {{64, 4}, {64, 8}, {32, 4}, {32, 8}};
+inline int variant_ty(int v) { return VARIANTS[v].wpg * 64 / VARIANTS[v].tx; }
+// order 8's staged neighbourhood is too large for the 8-wave shapes
+inline bool variant_supported(int order, int v) {
+  return v >= 0 && v < NVARIANT && (order == 4 || VARIANTS[v].wpg == 4);
+}
+
 // ---- host-side launchers, one per order (stage_o4.hip / stage_o8.hip) ----
 // Single-patch form: bt.ntiles == 0, grid = tiles of a.  Batched form: a is
-// unused, grid = bt.ntiles (one work-group per tile of the plan).
-void launch_stage_o4(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s);
-void launch_stage_o8(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s);
+// unused, grid = bt.ntiles (one work-group per tile of the plan).  The tile
+// counts in a / the plan tables must be those of `variant`.
+void launch_stage_o4(int variant, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid,
+                     hipStream_t s);
+void launch_stage_o8(int variant, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid,
+                     hipStream_t s);
 
 }  // namespace chemora

@@ -58,16 +58,28 @@
 
 namespace chemora {
 
-template <int R, int RM>
+// Tile shape: TX (32 or 64) columns, WPG waves per work-group; a wave covers
+// 64 / TX rows of TX points, so a tile is TX x TY with TY = WPG * 64 / TX.
+template <int TX_, int WPG_>
+struct Shape {
+  static constexpr int TX = TX_, WPG = WPG_;
+  static constexpr int RPW = 64 / TX;          // rows per wave
+  static constexpr int TY = WPG * RPW;
+  static constexpr int NT = 64 * WPG;          // work-items per work-group
+  static_assert(TX == 32 || TX == 64, "tile width");
+};
+
+template <int R, int RM, class SH>
 struct LdsLayout {
-  static constexpr int TX = TILE_X, TY = TILE_Y;
+  static constexpr int TX = SH::TX, TY = SH::TY;
   static constexpr int P = TX + 2 * R;
   static constexpr int ROWS0 = TY + 2 * R, ROWS1 = TY + 2 * RM, ROWS2 = TY;
   static constexpr int SIZE = P * (ROWS0 + 2 * RM * ROWS1 + 2 * (R - RM) * ROWS2);
   static constexpr int CHUNK = 128;                          // doubles per LDS-DMA instruction
   static constexpr int NCHUNK = (SIZE + CHUNK - 1) / CHUNK;
   static constexpr int SIZEP = NCHUNK * CHUNK;               // buffer size incl. padding
-  static constexpr int CPW = (NCHUNK + 3) / 4;               // chunks per wave
+  static constexpr int CPW = (NCHUNK + SH::WPG - 1) / SH::WPG;  // chunks per wave (at most)
+  static constexpr int CMIN = NCHUNK / SH::WPG;                 // chunks per wave (at least)
   static_assert(P % 2 == 0, "a lane's pair of doubles must not straddle rows");
 
   // first row (y = -yhalo) of plane dz, in doubles
@@ -158,11 +170,11 @@ __device__ __forceinline__ void wait_staged(int m) {
 // cover a block that is deep in z and share their z halos in its L2.  Every
 // work-item of the work-group must call it (it synchronises); it ends with a
 // barrier, so the buffers may be reused right after.
-template <int ORDER, bool UPWIND, int R, int NB, bool BOUND, bool OFFS_LDS>
+template <int ORDER, bool UPWIND, int R, int NB, bool BOUND, bool OFFS_LDS, class SH>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* const (&bufs)[NB], unsigned* offs) {
   using St = Stencil<ORDER>;
   constexpr int RM = ORDER / 2;
-  using L = LdsLayout<R, RM>;
+  using L = LdsLayout<R, RM, SH>;
   const Geo G = a.geo;
   const int txi = t % a.tiles_x;
   const int k = (t / a.tiles_x) % G.nz;
@@ -170,10 +182,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // threadIdx.y is the wave index: uniform across the wave, so keep it (and
   // everything the staging derives from it) in scalar registers
   const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
-  const int i0 = txi * TILE_X, j0 = tyi * TILE_Y;
-  const bool valid = (i0 + lane < G.nx) && (j0 + wave < G.ny);
+  const int xr = lane % SH::TX, yr = wave * SH::RPW + lane / SH::TX;   // tile-relative point
+  const int i0 = txi * SH::TX, j0 = tyi * SH::TY;
+  const bool valid = (i0 + xr < G.nx) && (j0 + yr < G.ny);
   // pointwise accesses of work-items outside the interior use a clamped point
-  const int ic = min(i0 + lane, G.nx - 1), jc = min(j0 + wave, G.ny - 1);
+  const int ic = min(i0 + xr, G.nx - 1), jc = min(j0 + yr, G.ny - 1);
 
   // byte offsets are unsigned 32-bit (the host limits a state to 4 GiB)
   const unsigned sy = (unsigned)G.sy, sz = (unsigned)G.sz, sf = (unsigned)G.sf, gg = (unsigned)G.g;
@@ -183,7 +196,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   auto val = [&](int f) __attribute__((always_inline)) { return bload(rin, vpt, spt + f * sf * 8u); };
 
   // ---- staging offsets of this tile.  Lane l of wave w moves LDS doubles
-  // [c*128 + 2l, c*128 + 2l + 1] of chunks c = w, w+4, ...  Points outside
+  // [c*128 + 2l, c*128 + 2l + 1] of chunks c = w, w+WPG, ...  Points outside
   // the patch's stored box (rows / columns of a ragged tile past the ghost
   // zone) are clamped into it: their LDS values are never read by a valid
   // work-item.  A pair whose first column is the last one of the box (odd nx
@@ -203,27 +216,27 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
 #pragma unroll
   for (int q = 0; q < L::CPW; ++q) {
     int x, y, dz;
-    L::decode((wave_t + 4 * q) * L::CHUNK + 2 * lane_t, x, y, dz);
+    L::decode((wave_t + SH::WPG * q) * L::CHUNK + 2 * lane_t, x, y, dz);
     y = min(y, ymax);
     if (x > xmax) x = xmax - 1;
     voff[q] = (unsigned)(dz * (int)sz + y * (int)sy + x + (int)bias) * 8u;
     // OFFS_LDS: park the offsets in LDS (each lane reads back only its own
     // slots, so no barrier is involved) and free their registers
-    if (OFFS_LDS) offs[q * 256 + wave * 64 + lane] = voff[q];
+    if (OFFS_LDS) offs[q * SH::NT + wave * 64 + lane] = voff[q];
   }
   const unsigned tile_base = ((k + gg) * sz + (j0 + gg) * sy + i0 + gg + XB) * 8u - bias * 8u;
   auto issue = [&](int f, double* dst) __attribute__((always_inline)) {
     const unsigned so = tile_base + f * sf * 8u;
 #pragma unroll
     for (int q = 0; q < L::CPW; ++q) {
-      const int c = wave + 4 * q;
-      if (L::CPW * 4 != L::NCHUNK && c >= L::NCHUNK) break;   // wave-uniform
-      const unsigned vo = OFFS_LDS ? offs[q * 256 + wave * 64 + lane] : voff[q];
+      const int c = wave + SH::WPG * q;
+      if (L::CPW * SH::WPG != L::NCHUNK && c >= L::NCHUNK) break;   // wave-uniform
+      const unsigned vo = OFFS_LDS ? offs[q * SH::NT + wave * 64 + lane] : voff[q];
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr_t)(dst + c * L::CHUNK), 16, vo, so, 0, 0);
     }
   };
 
-  const int anchor = wave * L::P + lane;
+  const int anchor = yr * L::P + xr;
   // stencil access into the buffer of the current phase
   // Stencil taps of the current phase's buffer.  Each phase addresses it from
   // an opaque copy of the anchor: LDS reads are merged in pairs (8-bit
@@ -370,7 +383,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     if (p + NB - 1 < nphase) issue(seq_gf(p + NB - 1), bufs[(p + NB - 1) % NB]);
   };
   auto sync = [&](int p) __attribute__((always_inline)) {
-    wait_staged<NB, L::NCHUNK / 4>(min(p + NB - 1, nphase - 1) - (p + 1));
+    wait_staged<NB, L::CMIN>(min(p + NB - 1, nphase - 1) - (p + 1));
     lds_barrier();
   };
 
@@ -700,24 +713,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
 // the concatenated tiles of all patches of a plan, each work-group finding
 // its patch by binary search; the hardware dispatcher balances the uneven
 // patches dynamically.
-// WAVES work-groups share a CU (one wave per SIMD each): NB staging buffers
-// per work-group must fit the 160 KB LDS WAVES times, and with WAVES = 2 the
+// OCC waves share a SIMD (OCC * 4 / WPG work-groups per CU): their NB
+// staging buffers must fit the 160 KB LDS together, and with OCC = 2 the
 // registers per lane halve to 256.
-template <int ORDER, bool UPWIND, int R, int NB, int WAVES>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)))
+template <int ORDER, bool UPWIND, int R, int NB, int OCC, int TX, int WPG>
+__global__ __launch_bounds__(64 * WPG) __attribute__((amdgpu_waves_per_eu(OCC)))
 void stage_kernel(StageArgs a1, BatchTable bt) {
-  using L = LdsLayout<R, ORDER / 2>;
+  using SH = Shape<TX, WPG>;
+  using L = LdsLayout<R, ORDER / 2, SH>;
   static_assert(NB >= 2 && NB <= 5, "staging depth");
-  // with two work-groups per CU the per-lane staging offsets live in LDS
-  constexpr bool OFFS_LDS = WAVES >= 2;
-  static_assert(WAVES * (NB * L::SIZEP * 8 + (OFFS_LDS ? L::CPW * 256 * 4 : 0)) <= 160 * 1024, "LDS");
+  // with two waves per SIMD the per-lane staging offsets live in LDS
+  constexpr bool OFFS_LDS = OCC >= 2;
+  constexpr int WG_PER_CU = (OCC * 4 + WPG - 1) / WPG;
+  static_assert(WG_PER_CU * (NB * L::SIZEP * 8 + (OFFS_LDS ? L::CPW * SH::NT * 4 : 0)) <= 160 * 1024, "LDS");
   // separate arrays, so the compiler can tell the buffers' staging loads apart
   __shared__ double b0[L::SIZEP];
   __shared__ double b1[L::SIZEP];
   __shared__ double b2[NB > 2 ? L::SIZEP : 1];
   __shared__ double b3[NB > 3 ? L::SIZEP : 1];
   __shared__ double b4[NB > 4 ? L::SIZEP : 1];
-  __shared__ unsigned offs[OFFS_LDS ? L::CPW * 256 : 1];
+  __shared__ unsigned offs[OFFS_LDS ? L::CPW * SH::NT : 1];
   double* const all[5] = {b0, b1, b2, b3, b4};
   double* bufs[NB];
 #pragma unroll
@@ -729,7 +744,7 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
     a = uniform_args(bt.args + p);
     t -= uniform(bt.tile_start[p]);
   }
-  stage_tile<ORDER, UPWIND, R, NB, (ORDER >= 8 || WAVES >= 2), OFFS_LDS>(a, t, bufs, offs);
+  stage_tile<ORDER, UPWIND, R, NB, (ORDER >= 8 || OCC >= 2), OFFS_LDS, SH>(a, t, bufs, offs);
 }
 
 }  // namespace chemora

@@ -17,19 +17,31 @@
 namespace chemora {
 
 namespace {
-template <bool UPWIND, int R>
+template <int TX, int WPG, bool UPWIND, int R>
 void launch(const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((stage_kernel<4, UPWIND, R, CHEMORA_STAGING_DEPTH_O4, CHEMORA_WAVES_O4>), dim3(grid), dim3(TILE_X, TILE_Y, 1), 0, s, a, bt);
+  hipLaunchKernelGGL((stage_kernel<4, UPWIND, R, CHEMORA_STAGING_DEPTH_O4, CHEMORA_WAVES_O4, TX, WPG>), dim3(grid),
+                     dim3(64, WPG, 1), 0, s, a, bt);
+}
+
+template <int TX, int WPG>
+void by_reach(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
+  if (upwind)
+    launch<TX, WPG, true, 3>(a, bt, grid, s);
+  else if (ko_r > 2)
+    launch<TX, WPG, false, 3>(a, bt, grid, s);
+  else
+    launch<TX, WPG, false, 2>(a, bt, grid, s);
 }
 }  // namespace
 
-void launch_stage_o4(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
-  if (upwind)
-    launch<true, 3>(a, bt, grid, s);
-  else if (ko_r > 2)
-    launch<false, 3>(a, bt, grid, s);
-  else
-    launch<false, 2>(a, bt, grid, s);
+void launch_stage_o4(int variant, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid,
+                     hipStream_t s) {
+  switch (variant) {
+    case 1: by_reach<64, 8>(upwind, ko_r, a, bt, grid, s); break;
+    case 2: by_reach<32, 4>(upwind, ko_r, a, bt, grid, s); break;
+    case 3: by_reach<32, 8>(upwind, ko_r, a, bt, grid, s); break;
+    default: by_reach<64, 4>(upwind, ko_r, a, bt, grid, s); break;
+  }
 }
 
 }  // namespace chemora

@@ -15,19 +15,30 @@
 namespace chemora {
 
 namespace {
-template <bool UPWIND, int R>
+template <int TX, int WPG, bool UPWIND, int R>
 void launch(const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((stage_kernel<8, UPWIND, R, CHEMORA_STAGING_DEPTH_O8, CHEMORA_WAVES_O8>), dim3(grid), dim3(TILE_X, TILE_Y, 1), 0, s, a, bt);
+  hipLaunchKernelGGL((stage_kernel<8, UPWIND, R, CHEMORA_STAGING_DEPTH_O8, CHEMORA_WAVES_O8, TX, WPG>), dim3(grid),
+                     dim3(64, WPG, 1), 0, s, a, bt);
+}
+
+template <int TX, int WPG>
+void by_reach(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
+  if (upwind)
+    launch<TX, WPG, true, 5>(a, bt, grid, s);
+  else if (ko_r > 4)
+    launch<TX, WPG, false, 5>(a, bt, grid, s);
+  else
+    launch<TX, WPG, false, 4>(a, bt, grid, s);
 }
 }  // namespace
 
-void launch_stage_o8(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
-  if (upwind)
-    launch<true, 5>(a, bt, grid, s);
-  else if (ko_r > 4)
-    launch<false, 5>(a, bt, grid, s);
+// the 8-wave shapes are not built for order 8 (variant_supported)
+void launch_stage_o8(int variant, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid,
+                     hipStream_t s) {
+  if (variant == 2)
+    by_reach<32, 4>(upwind, ko_r, a, bt, grid, s);
   else
-    launch<false, 4>(a, bt, grid, s);
+    by_reach<64, 4>(upwind, ko_r, a, bt, grid, s);
 }
 
 }  // namespace chemora

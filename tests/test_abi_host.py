@@ -163,3 +163,61 @@ def test_plan_argument_checks_on_host():
     assert L.chemora_batch_step(None, 1, None) == C.EINVAL
     assert L.chemora_plan_destroy(None) == C.OK
     assert L.chemora_plan_points(None) == 0
+
+
+def test_tile_variant_shapes_and_table_on_host():
+    assert [C.chemora_tile_variant_shape(v) for v in range(4)] == [(64, 4), (64, 8), (32, 8), (32, 16)]
+    assert C.lib().chemora_tile_variant_shape(4, None, None) == C.EINVAL
+    p, g = _good()
+    P, X = C.make_params(p), C.make_patch(g, FAKE)
+    before = C.chemora_tile_variant(P, X)
+    try:
+        for v in range(4):
+            C.chemora_set_tile_variant(P, X, v)
+            assert C.chemora_tile_variant(P, X) == v
+        assert C.lib().chemora_set_tile_variant(ctypes.byref(P), ctypes.byref(X), 7) == C.EINVAL
+        p8 = I.workload(3, n_override=16).params
+        P8, X8 = C.make_params(p8), C.make_patch(I.workload(3, n_override=16).grid, FAKE)
+        assert C.lib().chemora_set_tile_variant(ctypes.byref(P8), ctypes.byref(X8), 1) == C.EUNSUPPORTED
+        assert "not built for order 8" in C.last_error()
+        bad = C.make_params(p)
+        bad.fd_order = 6
+        assert C.lib().chemora_set_tile_variant(ctypes.byref(bad), ctypes.byref(X), 0) == C.EINVAL
+        assert C.lib().chemora_tile_variant(ctypes.byref(bad), ctypes.byref(X)) == C.EINVAL
+    finally:
+        C.chemora_set_tile_variant(P, X, before)
+
+
+def test_tune_reads_and_rewrites_the_cache_without_timing_cached_classes(tmp_path):
+    """A class with a cache entry is taken from the file, not timed (no HIP
+    call), and the file is rewritten as valid JSON holding every entry."""
+    import json
+    p, _ = _good()
+    g = I.Grid((40, 20, 12), p.ghost, 0.125)         # a class no other test touches: buckets x1 y1
+    key = f"unknown/o4/u1/r{p.ghost}/fp64/x1/y1"
+    path = tmp_path / "tiles.json"
+    path.write_text(json.dumps({"format": "chemora tile-variant cache", "version": 1,
+                                "entries": {key: {"variant": 2, "tile": "32x8"},
+                                            "other/o8/u1/r5/fp64/x4/y3": {"variant": 0}}}, indent=1))
+    P, X = C.make_params(p), C.make_patch(g, FAKE)
+    assert C.chemora_tile_variant(P, X) == 2          # order-4 default before the cache is read
+    v = ctypes.c_int32(-1)
+    rc = C.lib().chemora_tune(ctypes.byref(P), ctypes.byref(X), ctypes.c_void_p(FAKE + (1 << 34)),
+                              str(path).encode(), None, ctypes.byref(v))
+    try:
+        assert rc == C.OK, C.last_error()
+        assert v.value == 2 and C.chemora_tile_variant(P, X) == 2
+        d = json.loads(path.read_text())
+        assert d["entries"][key]["variant"] == 2 and d["entries"][key]["tile"] == "32x8"
+        assert d["entries"]["other/o8/u1/r5/fp64/x4/y3"]["variant"] == 0
+    finally:
+        C.chemora_set_tile_variant(P, X, 2)
+
+
+def test_tune_argument_checks_on_host():
+    p, g = _good()
+    P, X = C.make_params(p), C.make_patch(g, FAKE)
+    assert C.lib().chemora_tune(ctypes.byref(P), ctypes.byref(X), None, None, None, None) == C.EINVAL
+    assert C.lib().chemora_tune(None, ctypes.byref(X), ctypes.c_void_p(FAKE + (1 << 34)), None, None,
+                                None) == C.EINVAL
+    assert C.lib().chemora_plan_patch_variant(None, 0) == C.EINVAL

@@ -316,6 +316,68 @@ def test_batched_plan_matches_oracle(torch_cuda):
     B.close()
 
 
+@pytest.mark.parametrize("index,n", [(2, (70, 37, 19)), (2, (33, 9, 7)), (3, (45, 20, 13))])
+def test_tile_variants_are_bitwise_identical(torch_cuda, index, n):
+    """Every tile variant computes every point with the same arithmetic in
+    the same order: the right-hand side and two RK4 steps agree bitwise with
+    variant 0 (ragged extents in x and y, odd nx, both orders)."""
+    from paper_1307_6488_amd import chemora as C
+    w = I.workload(index)
+    grid = bl_grid(n, w.params.ghost)
+    u = I.brill_lindquist(grid)
+    I.add_sinusoids(u, grid, np.random.default_rng(77), 1e-4, range(24), periodic_ghosts=False)
+    P, X = C.make_params(w.params), C.make_patch(grid, 0x7F0000001000)   # class key only
+    built = [v for v in range(4) if w.params.fd_order == 4 or v in (0, 2)]
+    before = C.chemora_tile_variant(P, X)
+    ref = None
+    try:
+        for v in built:
+            C.chemora_set_tile_variant(P, X, v)
+            assert C.chemora_tile_variant(P, X) == v
+            r = gpu_rhs(torch_cuda, w.params, grid, u)
+            e = gpu_rk4(torch_cuda, w.params, grid, u, 0.25 * grid.h, 2)
+            say(f"variant {v} {C.chemora_tile_variant_shape(v)} on {n}: done")
+            if ref is None:
+                ref = (r, e)
+                continue
+            assert np.array_equal(r, ref[0], equal_nan=True), v
+            assert np.array_equal(e, ref[1], equal_nan=True), v
+    finally:
+        C.chemora_set_tile_variant(P, X, before)
+
+
+def test_tuned_plan_matches_per_patch_steps_and_writes_cache(torch_cuda, tmp_path):
+    """A plan created with a tune cache times the classes of its patches,
+    records them in the cache file, groups the patches by variant, and still
+    advances every patch bitwise as per-patch rk4_step calls do."""
+    import json
+    from paper_1307_6488_amd import chemora as C
+    torch = torch_cuda
+    params = I.workload(2).params
+    grids = _small_patches(count=6, seed=21) + [bl_grid((96, 40, 24), 3), bl_grid((30, 70, 16), 3)]
+    states = [I.brill_lindquist(g) for g in grids]
+    path = tmp_path / "tiles.json"
+    B = C.Batch(params, grids, states, 0.25, tune_cache_path=str(path))
+    variants = B.variants()
+    say(f"tuned variants: {variants}")
+    d = json.loads(path.read_text())
+    for g, v in zip(grids, variants):
+        P, X = C.make_params(params), C.make_patch(g, 0x7F0000001000)
+        assert C.chemora_tile_variant(P, X) == v
+    assert all(e["variant"] in range(4) and "ms" in e for e in d["entries"].values() if e.get("ms") is not None)
+    assert len(d["entries"]) >= len({tuple(v for v in (g.n[0] <= 32, g.n[1] <= 16)) for g in grids})
+    B.step(2)
+    torch.cuda.synchronize()
+    for g, u0, p in zip(grids, states, B.patches):
+        ref = gpu_rk4(torch, params, g, u0, 0.25 * g.h, 2)
+        assert np.array_equal(p.u.cpu().numpy(), ref, equal_nan=True)
+    B.close()
+    # a second plan reads the classes from the file (no timing needed)
+    B2 = C.Batch(params, grids[:2], states[:2], 0.25, tune_cache_path=str(path))
+    assert B2.variants() == variants[:2]
+    B2.close()
+
+
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
