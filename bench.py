@@ -32,12 +32,13 @@ RK4_FLOPS = 24 * 14
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same
 # counters read for a plain 2 GiB device copy (FETCH_SIZE reads half the
 # bytes copied: x2.0; WRITE_SIZE reads them exactly: x1.0).  They hold only
-# for the kernel sources they were taken with (hash below); otherwise the
-# bench reports traffic as null.
+# for the kernel sources and tile variant they were taken with; otherwise
+# the bench reports traffic as null.
 MEASURED_TRAFFIC = {
     "brill-lindquist-128^3-o4-upwind": {
-        "sources_sha256": "ad28883b6df6ea99d9b15f79d7e2217d1f9828e9e4a0c81945a2e436aee7c6ec",
-        "fetch_kib": 1.1675e6, "write_kib": 8.1106e5, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sources_sha256": "c9684dce2cda128c9cb087eba7683e0ec37bc25fdcdc9b5c5df0d773a0f5bfb2",
+        "tile": "32x8",
+        "fetch_kib": 1.1236e6, "write_kib": 8.4087e5, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 KERNEL_SOURCES = ["stage_kernel.hpp", "stage_common.hpp", "fd_ops.hpp", "stage_o4.hip"]
@@ -53,9 +54,9 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, tile):
     m = MEASURED_TRAFFIC.get(workload)
-    if m is None or m["sources_sha256"] != kernel_sources_sha256():
+    if m is None or m["tile"] != tile or m["sources_sha256"] != kernel_sources_sha256():
         return None
     return (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024.0
 
@@ -152,7 +153,7 @@ def main():
     bytes23 = 5 * 24 * 8 * npts
     achieved = bytes23 / t23 / 1e9
     flops_update = 4 * RHS_FLOPS[w.params.fd_order] + RK4_FLOPS
-    traffic = measured_traffic(w.name)
+    traffic = measured_traffic(w.name, f"{tile[0]}x{tile[1]}")
     out = {
         "metric": "BSSN grid-point updates/s (one point advanced one full RK4 step), FP64",
         "value": value,

@@ -28,6 +28,11 @@ def test_bench_refuses_more_than_one_gpu():
 
 
 def test_traffic_is_null_once_kernel_sources_change(monkeypatch):
+    w = "brill-lindquist-128^3-o4-upwind"
+    tile = bench.MEASURED_TRAFFIC[w]["tile"]
+    assert bench.measured_traffic(w, tile) == pytest.approx(
+        (bench.MEASURED_TRAFFIC[w]["fetch_kib"] * 2.0 + bench.MEASURED_TRAFFIC[w]["write_kib"]) * 1024)
+    assert bench.measured_traffic(w, "64x64") is None
+    assert bench.measured_traffic("no-such-workload", tile) is None
     monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "0" * 64)
-    assert bench.measured_traffic("brill-lindquist-128^3-o4-upwind") is None
-    assert bench.measured_traffic("no-such-workload") is None
+    assert bench.measured_traffic(w, tile) is None
