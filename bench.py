@@ -71,6 +71,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="run the untuned default tile variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-patch batched form")
+    ap.add_argument("--no-split", action="store_true", help="skip the 256^3 split-precision comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -204,6 +205,8 @@ def main():
         del P, scratch
         torch.cuda.empty_cache()
         out["batched"] = batched_form(C, I, torch, args.no_tune)
+    if not args.no_split:
+        out["split"] = split_form(C, I, torch, args.no_tune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, u0)
     print(json.dumps(out), flush=True)
@@ -233,6 +236,47 @@ def batched_form(C, I, torch, no_tune, steps=10, warmup=2):
     return {"workload": "64 patches, 24-96 points per edge, order 4 upwind (batched plan)", "patches": len(grids),
             "points": npts, "steps": steps, "ms_per_step": ms, "value": npts / (ms * 1e-3),
             "unit": "updates/s", "tile_variants": [f"{a}x{b}" for a, b in map(C.chemora_tile_variant_shape, variants)]}
+
+
+def split_form(C, I, torch, no_tune, steps=20, warmup=2):
+    """Split precision (FP32 stencil combinations and algebra, FP64 state,
+    RK combination and near-puncture chi terms, chi_split = 0.1) against FP64
+    on the same 256^3 Brill-Lindquist data: throughput of each, and the
+    max-norm-normalised difference per GF after warmup + steps RK4 steps on
+    the central 64^3 of the grid."""
+    import numpy as np
+    w = I.workload(5)
+    u0 = w.make_state()
+    g, n = w.grid.ghost, w.grid.n[0]
+    c = n // 2 - 32
+    box = (slice(None),) + (slice(g + c, g + c + 64),) * 3
+    res, sub = {}, {}
+    for name, prec in (("fp64", I.PREC_FP64), ("split", I.PREC_SPLIT)):
+        p = I.Params(**vars(w.params))
+        p.precision = prec
+        P = C.Patch(p, w.grid, u0)
+        stream = torch.cuda.current_stream()
+        variant = C.chemora_tile_variant(P.params, P.patch) if no_tune else P.tune(None, stream)
+        P.rk4_step(w.dt, warmup)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        P.rk4_step(w.dt, steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        tile = C.chemora_tile_variant_shape(variant)
+        res[name] = {"ms_per_step": ms, "value": w.grid.npoints / (ms * 1e-3), "tile": f"{tile[0]}x{tile[1]}"}
+        sub[name] = P.u[box].cpu().numpy()
+        del P
+        torch.cuda.empty_cache()
+    scale = np.max(np.abs(sub["fp64"]), axis=(1, 2, 3))
+    err = np.max(np.abs(sub["split"] - sub["fp64"]), axis=(1, 2, 3)) / np.where(scale > 0, scale, 1.0)
+    worst = int(np.argmax(err))
+    return {"workload": w.name, "interior": list(w.grid.n), "chi_split": w.params.chi_split,
+            "steps": warmup + steps, "unit": "updates/s", "fp64": res["fp64"], "split": res["split"],
+            "speedup": res["fp64"]["ms_per_step"] / res["split"]["ms_per_step"],
+            "max_err_vs_fp64_central_64^3": float(err[worst]), "worst_gf": I.GF_NAMES[worst]}
 
 
 def _tune_cache():

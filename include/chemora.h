@@ -79,9 +79,17 @@ typedef struct chemora_params {
   int32_t shift;      /* CHEMORA_SHIFT_*                                     */
   double eta;         /* Gamma-driver damping                                */
   int32_t bc;         /* CHEMORA_BC_*: ghost treatment inside rk4_step       */
-  int32_t precision;  /* CHEMORA_PREC_FP64 (CHEMORA_PREC_SPLIT: EUNSUPPORTED
-                         until built)                                       */
-  double chi_split;   /* split precision: FP64 chi terms where min chi < it  */
+  int32_t precision;  /* CHEMORA_PREC_FP64, or CHEMORA_PREC_SPLIT (order 4
+                         only, else EUNSUPPORTED): stencil inputs are FP64
+                         differences rounded to FP32, combined with FP32
+                         weights; the algebra is FP32; the state, the RK
+                         combination and the 1/chi terms of D_i D_j alpha
+                         and the Gt source stay FP64                        */
+  double chi_split;   /* split precision: a wave of 64 points holding a
+                         point with chi < chi_split evaluates the whole chi
+                         phase (d chi, D~D~chi, R^chi, the chi RHS) in FP64
+                         (>= 0, +inf allowed; EINVAL otherwise; ignored for
+                         FP64)                                              */
 } chemora_params;
 
 /* One Cartesian patch (a grid section with its ghost zones). */

@@ -119,8 +119,13 @@ int validate(const chemora_params* P, const chemora_patch* X) {
   if (P->shift < 0 || P->shift > 1) return fail(CHEMORA_EINVAL, "shift %d unknown", P->shift);
   if (!std::isfinite(P->eta)) return fail(CHEMORA_EINVAL, "eta must be finite");
   if (P->bc != 0 && P->bc != 1) return fail(CHEMORA_EINVAL, "bc %d unknown", P->bc);
-  if (P->precision != CHEMORA_PREC_FP64)
-    return fail(CHEMORA_EUNSUPPORTED, "precision %d not built", P->precision);
+  if (P->precision != CHEMORA_PREC_FP64 && P->precision != CHEMORA_PREC_SPLIT)
+    return fail(CHEMORA_EUNSUPPORTED, "precision %d unknown", P->precision);
+  if (P->precision == CHEMORA_PREC_SPLIT) {
+    if (P->fd_order != 4) return fail(CHEMORA_EUNSUPPORTED, "split precision is built for fd_order 4 only");
+    if (!(P->chi_split >= 0.0) || std::isnan(P->chi_split))
+      return fail(CHEMORA_EINVAL, "chi_split must be >= 0 (+inf: FP64 chi terms everywhere)");
+  }
   for (int a = 0; a < 3; ++a) {
     if (X->n[a] < 1) return fail(CHEMORA_EINVAL, "n[%d] = %d < 1", a, X->n[a]);
     if (P->bc == CHEMORA_BC_PERIODIC && X->n[a] < P->ghost)
@@ -187,7 +192,8 @@ void dispatch_stage(const chemora_params* P, chemora::StageArgs& a, int v, hipSt
   set_tiles(a, v);
   const int tiles = a.tiles_x * a.tiles_y * a.geo.nz;
   if (P->fd_order == 4)
-    chemora::launch_stage_o4(v, P->upwind != 0, P->ko_radius, a, none, tiles, s);
+    chemora::launch_stage_o4(v, P->precision == CHEMORA_PREC_SPLIT, P->upwind != 0, P->ko_radius, a, none, tiles,
+                             s);
   else
     chemora::launch_stage_o8(v, P->upwind != 0, P->ko_radius, a, none, tiles, s);
 }
@@ -197,7 +203,8 @@ void dispatch_batch(const chemora_params* P, int v, const chemora::BatchTable& b
   chemora::StageArgs none;
   std::memset(&none, 0, sizeof none);
   if (P->fd_order == 4)
-    chemora::launch_stage_o4(v, P->upwind != 0, P->ko_radius, none, bt, bt.ntiles, s);
+    chemora::launch_stage_o4(v, P->precision == CHEMORA_PREC_SPLIT, P->upwind != 0, P->ko_radius, none, bt,
+                             bt.ntiles, s);
   else
     chemora::launch_stage_o8(v, P->upwind != 0, P->ko_radius, none, bt, bt.ntiles, s);
 }
@@ -245,8 +252,9 @@ std::string class_key(const chemora_params* P, const chemora_patch* X) {
   static const int xe[] = {32, 64, 96, 128};   // x extent: <=32 <=64 <=96 <=128 >128
   static const int ye[] = {16, 32, 64};        // y extent: <=16 <=32 <=64 >64
   char buf[192];
-  std::snprintf(buf, sizeof buf, "%s/o%d/u%d/r%d/fp64/x%d/y%d", device_arch().c_str(), P->fd_order,
-                P->upwind ? 1 : 0, required_ghost(P->fd_order, P->upwind, P->ko_radius), bucket(X->n[0], xe, 4),
+  std::snprintf(buf, sizeof buf, "%s/o%d/u%d/r%d/%s/x%d/y%d", device_arch().c_str(), P->fd_order,
+                P->upwind ? 1 : 0, required_ghost(P->fd_order, P->upwind, P->ko_radius),
+                P->precision == CHEMORA_PREC_SPLIT ? "split" : "fp64", bucket(X->n[0], xe, 4),
                 bucket(X->n[1], ye, 3));
   return buf;
 }
@@ -340,6 +348,7 @@ chemora::StageArgs base_args(const chemora_params* P, const chemora_patch* X) {
   a.gauge.lapse = P->lapse;
   a.gauge.shift = P->shift;
   a.gauge.eta = P->eta;
+  a.chi_split = P->precision == CHEMORA_PREC_SPLIT ? P->chi_split : 0.0;
   set_tiles(a, 0);
   return a;
 }

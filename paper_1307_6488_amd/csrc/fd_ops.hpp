@@ -19,6 +19,9 @@
 //            r=3: (15 s1 - 6 s2 + s3) * 2^-6 eps/h
 //            r=5: (210 s1 - 120 s2 + 45 s3 - 10 s4 + s5) * 2^-10 eps/h
 // For beta < 0 the lopsided stencil is mirrored and negated.
+// Split precision (order 4): the same differences, each formed in FP64 and
+// rounded to FP32, combined with FP32 weights (first_f, second_f,
+// lopsided_f, ko_axis_f).
 // The mixed derivative D_a D_b is the outer D1 along a of inner D1's along b,
 // both unscaled, divided by (12h)^2 or (840h)^2.
 #pragma once
@@ -53,6 +56,22 @@ struct Stencil<4> {
     const double c = at(0);
     return -3.0 * (at(-s) - c) + 18.0 * (at(s) - c) - 6.0 * (at(2 * s) - c) + (at(3 * s) - c);
   }
+  // split precision: FP64 differences rounded to FP32, FP32 weights
+  template <class F>
+  __device__ static __forceinline__ float first_f(F&& at) {
+    return 8.0f * (float)(at(1) - at(-1)) - (float)(at(2) - at(-2));
+  }
+  template <class F>
+  __device__ static __forceinline__ float second_f(F&& at) {
+    const double c = at(0);
+    return 16.0f * (float)((at(1) - c) + (at(-1) - c)) - (float)((at(2) - c) + (at(-2) - c));
+  }
+  template <class F>
+  __device__ static __forceinline__ float lopsided_f(F&& at, int s) {
+    const double c = at(0);
+    return -3.0f * (float)(at(-s) - c) + 18.0f * (float)(at(s) - c) - 6.0f * (float)(at(2 * s) - c) +
+           (float)(at(3 * s) - c);
+  }
 };
 
 template <>
@@ -79,7 +98,45 @@ struct Stencil<8> {
            1050.0 * (at(s) - c) - 420.0 * (at(2 * s) - c) + 140.0 * (at(3 * s) - c) -
            30.0 * (at(4 * s) - c) + 3.0 * (at(5 * s) - c);
   }
+  // split-precision forms (the host builds split precision for order 4 only)
+  template <class F>
+  __device__ static __forceinline__ float first_f(F&& at) {
+    return 672.0f * (float)(at(1) - at(-1)) - 168.0f * (float)(at(2) - at(-2)) + 32.0f * (float)(at(3) - at(-3)) -
+           3.0f * (float)(at(4) - at(-4));
+  }
+  template <class F>
+  __device__ static __forceinline__ float second_f(F&& at) {
+    const double c = at(0);
+    auto s = [&](int k) { return (float)((at(k) - c) + (at(-k) - c)); };
+    return 8064.0f * s(1) - 1008.0f * s(2) + 128.0f * s(3) - 9.0f * s(4);
+  }
+  template <class F>
+  __device__ static __forceinline__ float lopsided_f(F&& at, int s) {
+    const double c = at(0);
+    auto e = [&](int o) { return (float)(at(o) - c); };
+    return -5.0f * e(-3 * s) + 60.0f * e(-2 * s) - 420.0f * e(-s) + 1050.0f * e(s) - 420.0f * e(2 * s) +
+           140.0f * e(3 * s) - 30.0f * e(4 * s) + 3.0f * e(5 * s);
+  }
 };
+
+// Split precision: the symmetric differences s_k = (u_k - u_0) + (u_-k - u_0)
+// are formed in FP64 and rounded to FP32, weights and sum in FP32.
+template <int RMAX, class F>
+__device__ __forceinline__ float ko_axis_f(F&& at, int r, float scale) {
+  const double c = at(0);
+  auto s = [&](int k) { return (float)((at(k) - c) + (at(-k) - c)); };
+  float acc;
+  if (RMAX >= 2 && r == 2) {
+    acc = 4.0f * s(1) - s(2);
+  } else if (RMAX >= 3 && r == 3) {
+    acc = 15.0f * s(1) - 6.0f * s(2) + s(3);
+  } else if (RMAX >= 5 && r == 5) {
+    acc = 210.0f * s(1) - 120.0f * s(2) + 45.0f * s(3) - 10.0f * s(4) + s(5);
+  } else {
+    return 0.0f;
+  }
+  return acc * scale;
+}
 
 // Kreiss-Oliger term along one axis: the weighted sum of the symmetric
 // differences s_k, accumulated from k = 1 upward and scaled by

@@ -65,6 +65,7 @@ struct StageArgs {
   Gauge gauge;
   double cy;                       // weight of k in the accumulator update
   double cs;                       // weight of k in the next stage input
+  double chi_split;                // split precision: FP64 chi phase where chi < chi_split
   int tiles_x, tiles_y;            // tile grid of the launch's tile variant
   int mode;                        // a Mode
 };
@@ -86,13 +87,14 @@ constexpr int NXCD = 8;
 // kernel while the stencil reads feeding it stay early (stores intervene),
 // which keeps every tap live across the kernel.
 __device__ __forceinline__ void keep(double& x) { asm volatile("" : "+v"(x)); }
-template <int N>
-__device__ __forceinline__ void keep(double (&x)[N]) {
+__device__ __forceinline__ void keep(float& x) { asm volatile("" : "+v"(x)); }
+template <class V, int N>
+__device__ __forceinline__ void keep(V (&x)[N]) {
 #pragma unroll
   for (int n = 0; n < N; ++n) keep(x[n]);
 }
-template <int N, int M>
-__device__ __forceinline__ void keep(double (&x)[N][M]) {
+template <class V, int N, int M>
+__device__ __forceinline__ void keep(V (&x)[N][M]) {
 #pragma unroll
   for (int n = 0; n < N; ++n) keep(x[n]);
 }
@@ -171,8 +173,9 @@ inline bool variant_supported(int order, int v) {
 // Single-patch form: bt.ntiles == 0, grid = tiles of a.  Batched form: a is
 // unused, grid = bt.ntiles (one work-group per tile of the plan).  The tile
 // counts in a / the plan tables must be those of `variant`.
-void launch_stage_o4(int variant, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid,
-                     hipStream_t s);
+// split: FP32 stencil combinations and algebra (order 4 only)
+void launch_stage_o4(int variant, bool split, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt,
+                     int grid, hipStream_t s);
 void launch_stage_o8(int variant, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid,
                      hipStream_t s);
 

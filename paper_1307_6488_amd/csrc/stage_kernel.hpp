@@ -53,6 +53,8 @@
 // reach; planes are ordered dz = 0, +1, -1, +2, -2, ...
 #pragma once
 
+#include <type_traits>
+
 #include "fd_ops.hpp"
 #include "stage_common.hpp"
 
@@ -170,8 +172,13 @@ __device__ __forceinline__ void wait_staged(int m) {
 // cover a block that is deep in z and share their z halos in its L2.  Every
 // work-item of the work-group must call it (it synchronises); it ends with a
 // barrier, so the buffers may be reused right after.
-template <int ORDER, bool UPWIND, int R, int NB, bool BOUND, bool OFFS_LDS, class SH>
+template <int ORDER, bool UPWIND, int R, int NB, bool BOUND, bool OFFS_LDS, class SH, typename T>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* const (&bufs)[NB], unsigned* offs) {
+  // T: the arithmetic type of stencil combinations and algebra -- double, or
+  // float for split precision (FP64 differences rounded to FP32, FP32
+  // algebra, FP64 state, RK combination and near-puncture chi terms)
+  constexpr bool SPLIT = std::is_same<T, float>::value;
+  static_assert(!SPLIT || ORDER == 4, "split precision is built for order 4");
   using St = Stencil<ORDER>;
   constexpr int RM = ORDER / 2;
   using L = LdsLayout<R, RM, SH>;
@@ -263,7 +270,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // the 64 taps of a mixed derivative (or more) are live at once and spill.
   // It costs instruction-level parallelism, so order 4 uses it only where
   // two waves share a SIMD (half the registers each).
-  auto bound = [&](double& v) __attribute__((always_inline)) {
+  auto bound = [&](auto& v) __attribute__((always_inline)) {
     if (BOUND) {
       keep(v);
       __builtin_amdgcn_sched_barrier(0);
@@ -274,25 +281,38 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     asm volatile("" : "+v"(anc));
     return Taps{cur, anc};
   };
-  const double bet[3] = {val(gBETA), val(gBETA + 1), val(gBETA + 2)};
-  auto D1 = [&](const Taps& t0, int ax) __attribute__((always_inline)) {
+  // The stencils below take a precision tag: double() gives the FP64 forms,
+  // float() the split forms (FP64 differences rounded to FP32, FP32 weights).
+  const double bet_d[3] = {val(gBETA), val(gBETA + 1), val(gBETA + 2)};
+  auto D1 = [&](auto tag, const Taps& t0, int ax) __attribute__((always_inline)) {
+    using TC = decltype(tag);
     const Taps tap = t0.fresh();
-    double v =
-        St::first([&](int o) { return ax == 0 ? tap(o, 0, 0) : (ax == 1 ? tap(0, o, 0) : tap(0, 0, o)); }) * a.sc.d1;
+    auto along = [&](int o) __attribute__((always_inline)) { return ax == 0 ? tap(o, 0, 0) : (ax == 1 ? tap(0, o, 0) : tap(0, 0, o)); };
+    TC v;
+    if constexpr (std::is_same<TC, float>::value)
+      v = St::first_f(along) * float(a.sc.d1);
+    else
+      v = St::first(along) * a.sc.d1;
     bound(v);
     return v;
   };
-  auto D2 = [&](const Taps& t0, int slot) __attribute__((always_inline)) {
+  auto D2 = [&](auto tag, const Taps& t0, int slot) __attribute__((always_inline)) {
+    using TC = decltype(tag);
+    constexpr bool F32 = std::is_same<TC, float>::value;
     const Taps tap = t0.fresh();
     const int ai = SI(slot), bj = SJ(slot);
     auto along = [&](int o) __attribute__((always_inline)) { return ai == 0 ? tap(o, 0, 0) : (ai == 1 ? tap(0, o, 0) : tap(0, 0, o)); };
-    double v;
+    TC v;
     if (ai == bj) {
-      v = St::second(along) * a.sc.d2;
+      if constexpr (F32)
+        v = St::second_f(along) * float(a.sc.d2);
+      else
+        v = St::second(along) * a.sc.d2;
     } else {
-      // outer D1 along ai of inner D1's along bj; the barrier after each
-      // inner derivative bounds the live taps to one inner stencil
-      v = St::first([&](int oa) {
+      // outer D1 along ai of inner D1's along bj (the inner ones FP64 in
+      // both precisions); the barrier after each inner derivative bounds
+      // the live taps to one inner stencil
+      auto outer = [&](int oa) __attribute__((always_inline)) {
         const Taps ti = tap.fresh();
         double inner = St::first([&](int ob) {
           int d[3] = {0, 0, 0};
@@ -302,30 +322,50 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
         });
         bound(inner);
         return inner;
-      }) * a.sc.d11;
+      };
+      if constexpr (F32)
+        v = St::first_f(outer) * float(a.sc.d11);
+      else
+        v = St::first(outer) * a.sc.d11;
     }
     bound(v);
     return v;
   };
   // advection + dissipation of the staged GF; rhs = (algebra + adv) + diss
-  auto finish = [&](const Taps& t0, double alg) __attribute__((always_inline)) {
-    double adv = 0.0, diss = 0.0;
+  auto finish = [&](auto tag, const Taps& t0, decltype(tag) alg) __attribute__((always_inline)) {
+    using TC = decltype(tag);
+    constexpr bool F32 = std::is_same<TC, float>::value;
+    TC adv = TC(0.0), diss = TC(0.0);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const Taps tap = t0.fresh();
       auto along = [&](int o) __attribute__((always_inline)) { return ax == 0 ? tap(o, 0, 0) : (ax == 1 ? tap(0, o, 0) : tap(0, 0, o)); };
-      double d;
+      const TC b = TC(bet_d[ax]);
+      TC d;
       if (UPWIND) {
         // both lopsided stencils from the same taps, then select by the sign of beta
-        const double dp = St::lopsided(along, 1);
-        const double dm = -St::lopsided([&](int o) { return along(-o); }, 1);
-        d = (bet[ax] >= 0.0 ? dp : dm) * a.sc.up;
+        if constexpr (F32) {
+          const float dp = St::lopsided_f(along, 1);
+          const float dm = -St::lopsided_f([&](int o) { return along(-o); }, 1);
+          d = (bet_d[ax] >= 0.0 ? dp : dm) * float(a.sc.up);
+        } else {
+          const double dp = St::lopsided(along, 1);
+          const double dm = -St::lopsided([&](int o) { return along(-o); }, 1);
+          d = (bet_d[ax] >= 0.0 ? dp : dm) * a.sc.up;
+        }
       } else {
-        d = St::first(along) * a.sc.d1;
+        if constexpr (F32)
+          d = St::first_f(along) * float(a.sc.d1);
+        else
+          d = St::first(along) * a.sc.d1;
       }
-      adv += bet[ax] * d;
+      adv += b * d;
       if (a.sc.ko_r > 0) {
-        const double qd = ko_axis<R>(along, a.sc.ko_r, a.sc.ko);
+        TC qd;
+        if constexpr (F32)
+          qd = ko_axis_f<R>(along, a.sc.ko_r, float(a.sc.ko));
+        else
+          qd = ko_axis<R>(along, a.sc.ko_r, a.sc.ko);
         diss = (ax == 0) ? qd : diss + qd;
       }
       bound(adv);
@@ -346,8 +386,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const unsigned so = spt + f * sf * 8u;
     return Epi{bload(ryin, vpt, so), bload(run, vpt, so)};
   };
-  auto emit = [&](int f, double kf, const Epi& e) __attribute__((always_inline)) {
+  // the right-hand side k arrives in T and is combined in FP64
+  auto emit = [&](int f, auto kt, const Epi& e) __attribute__((always_inline)) {
     if (!valid) return;
+    const double kf = double(kt);
     const unsigned so = spt + f * sf * 8u;
     if (mode == MODE_RHS) {
       bstore(state_rsrc(a.out, G.sf), vpt, so, kf);
@@ -387,18 +429,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     lds_barrier();
   };
 
-  const double alpha = val(gALPHA), chi = val(gCHI), K = val(gK);
-  double g[6], gu[6];
+  const double alpha_d = val(gALPHA), chi_d = val(gCHI), K_d = val(gK);
+  const T alpha = T(alpha_d), chi = T(chi_d), K = T(K_d);
+  // split precision: a point with chi < chi_split (near a puncture, where
+  // the 1/chi terms are large) takes the chi phase in FP64
+  const bool near = SPLIT && chi_d < a.chi_split;
+  T g[6], gu[6];
 #pragma unroll
-  for (int s = 0; s < 6; ++s) g[s] = val(gGT + s);
+  for (int s = 0; s < 6; ++s) g[s] = T(val(gGT + s));
   {
-    const double c00 = g[3] * g[5] - g[4] * g[4];
-    const double c01 = g[2] * g[4] - g[1] * g[5];
-    const double c02 = g[1] * g[4] - g[2] * g[3];
-    const double c11 = g[0] * g[5] - g[2] * g[2];
-    const double c12 = g[1] * g[2] - g[0] * g[4];
-    const double c22 = g[0] * g[3] - g[1] * g[1];
-    const double idet = 1.0 / (g[0] * c00 + g[1] * c01 + g[2] * c02);
+    const T c00 = g[3] * g[5] - g[4] * g[4];
+    const T c01 = g[2] * g[4] - g[1] * g[5];
+    const T c02 = g[1] * g[4] - g[2] * g[3];
+    const T c11 = g[0] * g[5] - g[2] * g[2];
+    const T c12 = g[1] * g[2] - g[0] * g[4];
+    const T c22 = g[0] * g[3] - g[1] * g[1];
+    const T idet = T(1.0) / (g[0] * c00 + g[1] * c01 + g[2] * c02);
     gu[0] = c00 * idet; gu[1] = c01 * idet; gu[2] = c02 * idet;
     gu[3] = c11 * idet; gu[4] = c12 * idet; gu[5] = c22 * idet;
   }
@@ -411,68 +457,68 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   sync(-1);
 
   // ---- shift (phases 0-2)
-  double db[3][3];
-  double xts[3] = {0.0, 0.0, 0.0};
-  double ddiv[3] = {0.0, 0.0, 0.0};
+  T db[3][3];
+  T xts[3] = {T(0.0), T(0.0), T(0.0)};
+  T ddiv[3] = {T(0.0), T(0.0), T(0.0)};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const Epi e = epi_load(gBETA + c);
-    const double Bc = val(gB + c);
+    const T Bc = T(val(gB + c));
     begin(c);
     auto tap = make_ops(bufs[c % NB]);
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) db[c][ax] = D1(tap, ax);
+    for (int ax = 0; ax < 3; ++ax) db[c][ax] = D1(T(), tap, ax);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-      const double dd = D2(tap, q);
-      xts[c] += W(q) * gu[q] * dd;
+      const T dd = D2(T(), tap, q);
+      xts[c] += T(W(q)) * gu[q] * dd;
       const int qi = SI(q), qj = SJ(q);
       if (qj == c) ddiv[qi] += dd;
       if (qi == c && qi != qj) ddiv[qj] += dd;
     }
-    emit(gBETA + c, driver ? finish(tap, 0.75 * Bc) : 0.0, e);
+    emit(gBETA + c, driver ? finish(T(), tap, T(0.75) * Bc) : T(0.0), e);
     keep(db[c]);
     keep(xts);
     keep(ddiv);
     sync(c);
   }
-  const double divb = db[0][0] + db[1][1] + db[2][2];
+  const T divb = db[0][0] + db[1][1] + db[2][2];
 
   // ---- conformal metric (phases 3-8)
-  double Ric[6];
-  double Gu[3][6];
-  double Gd[3];
+  T Ric[6];
+  T Gu[3][6];
+  T Gd[3];
   {
-    double dg[6][3];
+    T dg[6][3];
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       const int p = 3 + s;
       const Epi e = epi_load(gGT + s);
-      const double As = val(gAT + s);
+      const T As = T(val(gAT + s));
       begin(p);
       auto tap = make_ops(bufs[p % NB]);
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) dg[s][ax] = D1(tap, ax);
-      double r = 0.0;
+      for (int ax = 0; ax < 3; ++ax) dg[s][ax] = D1(T(), tap, ax);
+      T r = T(0.0);
 #pragma unroll
-      for (int q = 0; q < 6; ++q) r += W(q) * gu[q] * D2(tap, q);
-      Ric[s] = -0.5 * r;
+      for (int q = 0; q < 6; ++q) r += T(W(q)) * gu[q] * D2(T(), tap, q);
+      Ric[s] = -T(0.5) * r;
       const int i = SI(s), jj = SJ(s);
-      double lie = 0.0;
+      T lie = T(0.0);
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) lie += g[S(i, kk)] * db[kk][jj] + g[S(jj, kk)] * db[kk][i];
-      emit(gGT + s, finish(tap, -2.0 * alpha * As + lie - (2.0 / 3.0) * g[s] * divb), e);
+      emit(gGT + s, finish(T(), tap, -T(2.0) * alpha * As + lie - (T(2.0) / T(3.0)) * g[s] * divb), e);
       keep(Ric[s]);
       keep(dg[s]);
       sync(p);
     }
-    double Gl[3][6];
+    T Gl[3][6];
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
       for (int s = 0; s < 6; ++s) {
         const int i = SI(s), jj = SJ(s);
-        Gl[kk][s] = 0.5 * (dg[S(kk, i)][jj] + dg[S(kk, jj)][i] - dg[s][kk]);
+        Gl[kk][s] = T(0.5) * (dg[S(kk, i)][jj] + dg[S(kk, jj)][i] - dg[s][kk]);
       }
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk)
@@ -481,24 +527,24 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
         Gu[kk][s] = gu[S(kk, 0)] * Gl[0][s] + gu[S(kk, 1)] * Gl[1][s] + gu[S(kk, 2)] * Gl[2][s];
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk) {
-      double acc = 0.0;
+      T acc = T(0.0);
 #pragma unroll
-      for (int s = 0; s < 6; ++s) acc += W(s) * gu[s] * Gu[kk][s];
+      for (int s = 0; s < 6; ++s) acc += T(W(s)) * gu[s] * Gu[kk][s];
       Gd[kk] = acc;
     }
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       const int i = SI(s), jj = SJ(s);
-      double r = Ric[s];
+      T r = Ric[s];
 #pragma unroll
-      for (int kk = 0; kk < 3; ++kk) r += 0.5 * Gd[kk] * (Gl[i][S(jj, kk)] + Gl[jj][S(i, kk)]);
+      for (int kk = 0; kk < 3; ++kk) r += T(0.5) * Gd[kk] * (Gl[i][S(jj, kk)] + Gl[jj][S(i, kk)]);
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-          const double gmi = gu[S(0, m)] * Gu[kk][S(0, i)] + gu[S(1, m)] * Gu[kk][S(1, i)] +
+          const T gmi = gu[S(0, m)] * Gu[kk][S(0, i)] + gu[S(1, m)] * Gu[kk][S(1, i)] +
                              gu[S(2, m)] * Gu[kk][S(2, i)];
-          const double gmj = gu[S(0, m)] * Gu[kk][S(0, jj)] + gu[S(1, m)] * Gu[kk][S(1, jj)] +
+          const T gmj = gu[S(0, m)] * Gu[kk][S(0, jj)] + gu[S(1, m)] * Gu[kk][S(1, jj)] +
                              gu[S(2, m)] * Gu[kk][S(2, jj)];
           r += gmi * (Gl[jj][S(kk, m)] + Gl[kk][S(m, jj)]) + gmj * Gl[i][S(kk, m)];
         }
@@ -509,11 +555,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // the start so that they are not live through the metric phases, where
   // register pressure peaks (each metric phase loads the one component it
   // needs; these loads hit in L2)
-  double A[6], Au[6];
+  T A[6], Au[6];
 #pragma unroll
-  for (int s = 0; s < 6; ++s) A[s] = val(gAT + s);
+  for (int s = 0; s < 6; ++s) A[s] = T(val(gAT + s));
   {
-    double Am[3][3];
+    T Am[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -526,12 +572,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     }
   }
   // Gt^c_jk At^jk, the only later use of the Christoffel symbols besides chi/alpha
-  double ga[3];
+  T ga[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double acc = 0.0;
+    T acc = T(0.0);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) acc += W(q) * Gu[c][q] * Au[q];
+    for (int q = 0; q < 6; ++q) acc += T(W(q)) * Gu[c][q] * Au[q];
     ga[c] = acc;
   }
   keep(Gu);
@@ -539,65 +585,110 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   keep(ga);
   keep(Ric);
 
-  // ---- chi (phase 9)
+  // ---- chi (phase 9), in precision TC: FP64, or FP32 in split waves away
+  // from the punctures; dchi is kept in FP64 for the later 1/chi terms
   double dchi[3];
-  const double ichi = 1.0 / chi;
+  const double ichi = 1.0 / chi_d;
   {
     const Epi e = epi_load(gCHI);
     begin(9);
     auto tap = make_ops(bufs[9 % NB]);
+    // the chi phase in precision TC, returned rather than applied: its Ricci
+    // contributions, d chi (FP64) and the right-hand side of chi
+    struct ChiPart {
+      T ric[6];
+      double dchi[3];
+      T k;
+    };
+    auto chi_phase = [&](auto tag) __attribute__((always_inline)) {
+      using TC = decltype(tag);
+      ChiPart out;
+      TC dc[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) dchi[ax] = D1(tap, ax);
-    double cdd[6];
+      for (int ax = 0; ax < 3; ++ax) dc[ax] = D1(tag, tap, ax);
+      TC cdd[6];
 #pragma unroll
-    for (int s = 0; s < 6; ++s)
-      cdd[s] = D2(tap, s) - (Gu[0][s] * dchi[0] + Gu[1][s] * dchi[1] + Gu[2][s] * dchi[2]);
-    double trc = 0.0, dchi2 = 0.0;
+      for (int s = 0; s < 6; ++s)
+        cdd[s] = D2(tag, tap, s) - (TC(Gu[0][s]) * dc[0] + TC(Gu[1][s]) * dc[1] + TC(Gu[2][s]) * dc[2]);
+      TC trc = TC(0.0), dchi2 = TC(0.0);
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      trc += W(s) * gu[s] * cdd[s];
-      dchi2 += W(s) * gu[s] * dchi[SI(s)] * dchi[SJ(s)];
+      for (int s = 0; s < 6; ++s) {
+        trc += TC(W(s)) * TC(gu[s]) * cdd[s];
+        dchi2 += TC(W(s)) * TC(gu[s]) * dc[SI(s)] * dc[SJ(s)];
+      }
+      const TC ic = TC(ichi);
+#pragma unroll
+      for (int s = 0; s < 6; ++s)
+        out.ric[s] = T(TC(0.5) * ic * (cdd[s] + TC(g[s]) * trc) -
+                       TC(0.25) * ic * ic * (dc[SI(s)] * dc[SJ(s)] + TC(3.0) * TC(g[s]) * dchi2));
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) out.dchi[ax] = double(dc[ax]);
+      out.k = T(finish(tag, tap, TC(2.0 / 3.0) * TC(chi_d) * (TC(alpha_d) * TC(K_d) - TC(divb))));
+      return out;
+    };
+    // apply a chi-phase result to the points that take it
+    auto apply = [&](const ChiPart& c, bool take) __attribute__((always_inline)) {
+#pragma unroll
+      for (int s = 0; s < 6; ++s) Ric[s] += take ? c.ric[s] : T(0.0);
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) dchi[ax] = take ? c.dchi[ax] : dchi[ax];
+      if (take) emit(gCHI, c.k, e);
+    };
+    if constexpr (!SPLIT) {
+      apply(chi_phase(double()), true);
+    } else {
+      // waves entirely on one side of chi_split evaluate one precision; a
+      // wave that straddles it evaluates both, each applied to its own
+      // points, so a point's arithmetic does not depend on which points
+      // share its wave (tile variants agree bitwise)
+      const uint64_t in_near = __builtin_amdgcn_ballot_w64(valid && near);
+      const uint64_t in_far = __builtin_amdgcn_ballot_w64(valid && !near);
+      if (!in_far) {
+        apply(chi_phase(double()), true);
+      } else if (!in_near) {
+        apply(chi_phase(float()), true);
+      } else {
+        apply(chi_phase(double()), near);
+        apply(chi_phase(float()), !near);
+      }
     }
-#pragma unroll
-    for (int s = 0; s < 6; ++s)
-      Ric[s] += 0.5 * ichi * (cdd[s] + g[s] * trc) -
-                0.25 * ichi * ichi * (dchi[SI(s)] * dchi[SJ(s)] + 3.0 * g[s] * dchi2);
-    emit(gCHI, finish(tap, (2.0 / 3.0) * chi * (alpha * K - divb)), e);
     keep(Ric);
     keep(dchi);
     sync(9);
   }
 
   // ---- lapse (phase 10)
-  double da[3];
-  double DDa[6];
+  T da[3];
+  T DDa[6];
   {
     const Epi e = epi_load(gALPHA);
     begin(10);
     auto tap = make_ops(bufs[10 % NB]);
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) da[ax] = D1(tap, ax);
+    for (int ax = 0; ax < 3; ++ax) da[ax] = D1(T(), tap, ax);
+    // the 1/chi correction is evaluated in FP64 in both precisions
     double gudchi_da = 0.0;
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk)
-      gudchi_da += (gu[S(kk, 0)] * dchi[0] + gu[S(kk, 1)] * dchi[1] + gu[S(kk, 2)] * dchi[2]) * da[kk];
+      gudchi_da += (double(gu[S(kk, 0)]) * dchi[0] + double(gu[S(kk, 1)]) * dchi[1] +
+                    double(gu[S(kk, 2)]) * dchi[2]) * double(da[kk]);
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       const int i = SI(s), jj = SJ(s);
-      DDa[s] = D2(tap, s) - (Gu[0][s] * da[0] + Gu[1][s] * da[1] + Gu[2][s] * da[2]) -
-               0.5 * ichi * (g[s] * gudchi_da - dchi[jj] * da[i] - dchi[i] * da[jj]);
+      const double corr = 0.5 * ichi * (double(g[s]) * gudchi_da - dchi[jj] * double(da[i]) - dchi[i] * double(da[jj]));
+      DDa[s] = D2(T(), tap, s) - (Gu[0][s] * da[0] + Gu[1][s] * da[1] + Gu[2][s] * da[2]) - T(corr);
     }
     keep(da);
     keep(DDa);
     if (gauge.lapse == 2)
-      emit(gALPHA, 0.0, e);
+      emit(gALPHA, T(0.0), e);
     else
-      emit(gALPHA, finish(tap, gauge.lapse == 0 ? -2.0 * alpha * K : -alpha * alpha * K), e);
+      emit(gALPHA, finish(T(), tap, gauge.lapse == 0 ? -T(2.0) * alpha * K : -alpha * alpha * K), e);
     sync(10);
   }
 
   // ---- evolved Gt (phases 11-13)
-  double xt_ad[3];
+  T xt_ad[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const int p = 11 + c;
@@ -605,24 +696,24 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     auto tap = make_ops(bufs[p % NB]);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const double d = D1(tap, ax);
+      const T d = D1(T(), tap, ax);
 #pragma unroll
       for (int s = 0; s < 6; ++s) {
         const int i = SI(s), jj = SJ(s);
-        if (jj == ax) Ric[s] += 0.5 * g[S(c, i)] * d;
-        if (i == ax) Ric[s] += 0.5 * g[S(c, jj)] * d;
+        if (jj == ax) Ric[s] += T(0.5) * g[S(c, i)] * d;
+        if (i == ax) Ric[s] += T(0.5) * g[S(c, jj)] * d;
       }
     }
-    xt_ad[c] = finish(tap, 0.0);
+    xt_ad[c] = finish(T(), tap, T(0.0));
     keep(xt_ad[c]);
     keep(Ric);
     sync(p);
   }
 
   // ---- K (phase 14)
-  double AA = 0.0;
+  T AA = T(0.0);
   {
-    double Am[3][3];
+    T Am[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -633,32 +724,32 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
 #pragma unroll
       for (int jj = 0; jj < 3; ++jj) AA += Am[i][jj] * Am[jj][i];
   }
-  double trDDa = 0.0, trRic = 0.0;
+  T trDDa = T(0.0), trRic = T(0.0);
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
-    trDDa += W(s) * gu[s] * DDa[s];
-    trRic += W(s) * gu[s] * Ric[s];
+    trDDa += T(W(s)) * gu[s] * DDa[s];
+    trRic += T(W(s)) * gu[s] * Ric[s];
   }
-  double xsrc[3];
+  T xsrc[3];
   {
     const Epi e = epi_load(gK);
     const Epi ex[3] = {epi_load(gXT), epi_load(gXT + 1), epi_load(gXT + 2)};
     begin(14);
     auto tap = make_ops(bufs[14 % NB]);
-    double dK[3];
+    T dK[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) dK[ax] = D1(tap, ax);
-    emit(gK, finish(tap, -chi * trDDa + alpha * (AA + K * K * (1.0 / 3.0))), e);
+    for (int ax = 0; ax < 3; ++ax) dK[ax] = D1(T(), tap, ax);
+    emit(gK, finish(T(), tap, -chi * trDDa + alpha * (AA + K * K * (T(1.0) / T(3.0)))), e);
     // Gt source, complete now
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      double r = xts[c];
-      r += (1.0 / 3.0) * (gu[S(c, 0)] * ddiv[0] + gu[S(c, 1)] * ddiv[1] + gu[S(c, 2)] * ddiv[2]);
-      r += (2.0 / 3.0) * Gd[c] * divb - (Gd[0] * db[c][0] + Gd[1] * db[c][1] + Gd[2] * db[c][2]);
-      r -= 2.0 * (Au[S(c, 0)] * da[0] + Au[S(c, 1)] * da[1] + Au[S(c, 2)] * da[2]);
-      const double adchi = Au[S(c, 0)] * dchi[0] + Au[S(c, 1)] * dchi[1] + Au[S(c, 2)] * dchi[2];
-      const double gdK = gu[S(c, 0)] * dK[0] + gu[S(c, 1)] * dK[1] + gu[S(c, 2)] * dK[2];
-      r += 2.0 * alpha * (ga[c] - 1.5 * ichi * adchi - (2.0 / 3.0) * gdK);
+      T r = xts[c];
+      r += (T(1.0) / T(3.0)) * (gu[S(c, 0)] * ddiv[0] + gu[S(c, 1)] * ddiv[1] + gu[S(c, 2)] * ddiv[2]);
+      r += (T(2.0) / T(3.0)) * Gd[c] * divb - (Gd[0] * db[c][0] + Gd[1] * db[c][1] + Gd[2] * db[c][2]);
+      r -= T(2.0) * (Au[S(c, 0)] * da[0] + Au[S(c, 1)] * da[1] + Au[S(c, 2)] * da[2]);
+      const double adchi = double(Au[S(c, 0)]) * dchi[0] + double(Au[S(c, 1)]) * dchi[1] + double(Au[S(c, 2)]) * dchi[2];
+      const T gdK = gu[S(c, 0)] * dK[0] + gu[S(c, 1)] * dK[1] + gu[S(c, 2)] * dK[2];
+      r += T(2.0) * alpha * (ga[c] - T(1.5 * ichi * adchi) - (T(2.0) / T(3.0)) * gdK);
       xsrc[c] = r;
       emit(gXT + c, xt_ad[c] + r, ex[c]);
     }
@@ -667,7 +758,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   }
 
   // ---- At (phases 15-20)
-  const double trX = alpha * trRic - trDDa;
+  const T trX = alpha * trRic - trDDa;
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     const int p = 15 + s;
@@ -675,17 +766,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     begin(p);
     auto tap = make_ops(bufs[p % NB]);
     const int i = SI(s), jj = SJ(s);
-    double la = 0.0, aa = 0.0;
+    T la = T(0.0), aa = T(0.0);
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk) {
       la += A[S(i, kk)] * db[kk][jj] + A[S(jj, kk)] * db[kk][i];
       // At_ik At^k_j = At_ik gt^kl At_lj
-      const double amkj = gu[S(kk, 0)] * A[S(0, jj)] + gu[S(kk, 1)] * A[S(1, jj)] + gu[S(kk, 2)] * A[S(2, jj)];
+      const T amkj = gu[S(kk, 0)] * A[S(0, jj)] + gu[S(kk, 1)] * A[S(1, jj)] + gu[S(kk, 2)] * A[S(2, jj)];
       aa += A[S(i, kk)] * amkj;
     }
-    const double X = alpha * Ric[s] - DDa[s];
-    emit(gAT + s, finish(tap, chi * (X - (1.0 / 3.0) * g[s] * trX) + alpha * (K * A[s] - 2.0 * aa) + la -
-                              (2.0 / 3.0) * A[s] * divb), e);
+    const T X = alpha * Ric[s] - DDa[s];
+    emit(gAT + s, finish(T(), tap, chi * (X - (T(1.0) / T(3.0)) * g[s] * trX) + alpha * (K * A[s] - T(2.0) * aa) + la -
+                              (T(2.0) / T(3.0)) * A[s] * divb), e);
     sync(p);
   }
 
@@ -695,15 +786,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     for (int c = 0; c < 3; ++c) {
       const int p = 21 + c;
       const Epi e = epi_load(gB + c);
-      const double Bc = val(gB + c);
+      const T Bc = T(val(gB + c));
       begin(p);
       auto tap = make_ops(bufs[p % NB]);
-      emit(gB + c, finish(tap, xsrc[c] - gauge.eta * Bc), e);
+      emit(gB + c, finish(T(), tap, xsrc[c] - gauge.eta * Bc), e);
       sync(p);
     }
   } else {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) emit(gB + c, 0.0, epi_load(gB + c));
+    for (int c = 0; c < 3; ++c) emit(gB + c, T(0.0), epi_load(gB + c));
   }
 }
 
@@ -714,17 +805,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
 // its patch by binary search; the hardware dispatcher balances the uneven
 // patches dynamically.
 // OCC waves share a SIMD (OCC * 4 / WPG work-groups per CU): their NB
-// staging buffers must fit the 160 KB LDS together, and with OCC = 2 the
-// registers per lane halve to 256.
-template <int ORDER, bool UPWIND, int R, int NB, int OCC, int TX, int WPG>
+// staging buffers must fit the 160 KB LDS together, and the registers per
+// lane drop to 512 / OCC.
+template <int ORDER, bool UPWIND, int R, int NB, int OCC, int TX, int WPG, typename T>
 __global__ __launch_bounds__(64 * WPG) __attribute__((amdgpu_waves_per_eu(OCC)))
 void stage_kernel(StageArgs a1, BatchTable bt) {
   using SH = Shape<TX, WPG>;
   using L = LdsLayout<R, ORDER / 2, SH>;
   static_assert(NB >= 2 && NB <= 5, "staging depth");
-  // with two waves per SIMD the per-lane staging offsets live in LDS
-  constexpr bool OFFS_LDS = OCC >= 2;
-  constexpr int WG_PER_CU = (OCC * 4 + WPG - 1) / WPG;
+  // FP64 with two waves per SIMD keeps the per-lane staging offsets in LDS
+  // (its 256 registers are otherwise exhausted); FP32 algebra needs ~156
+  constexpr bool OFFS_LDS = OCC == 2 && sizeof(T) == 8;
+  constexpr int WG_PER_CU = (OCC * 4) / WPG > 1 ? (OCC * 4) / WPG : 1;
   static_assert(WG_PER_CU * (NB * L::SIZEP * 8 + (OFFS_LDS ? L::CPW * SH::NT * 4 : 0)) <= 160 * 1024, "LDS");
   // separate arrays, so the compiler can tell the buffers' staging loads apart
   __shared__ double b0[L::SIZEP];
@@ -744,7 +836,7 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
     a = uniform_args(bt.args + p);
     t -= uniform(bt.tile_start[p]);
   }
-  stage_tile<ORDER, UPWIND, R, NB, (ORDER >= 8 || OCC >= 2), OFFS_LDS, SH>(a, t, bufs, offs);
+  stage_tile<ORDER, UPWIND, R, NB, (ORDER >= 8 || OCC >= 2), OFFS_LDS, SH, T>(a, t, bufs, offs);
 }
 
 }  // namespace chemora

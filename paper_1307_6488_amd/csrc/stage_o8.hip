@@ -17,8 +17,8 @@ namespace chemora {
 namespace {
 template <int TX, int WPG, bool UPWIND, int R>
 void launch(const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((stage_kernel<8, UPWIND, R, CHEMORA_STAGING_DEPTH_O8, CHEMORA_WAVES_O8, TX, WPG>), dim3(grid),
-                     dim3(64, WPG, 1), 0, s, a, bt);
+  hipLaunchKernelGGL((stage_kernel<8, UPWIND, R, CHEMORA_STAGING_DEPTH_O8, CHEMORA_WAVES_O8, TX, WPG, double>),
+                     dim3(grid), dim3(64, WPG, 1), 0, s, a, bt);
 }
 
 template <int TX, int WPG>

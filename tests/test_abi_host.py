@@ -70,6 +70,18 @@ BAD_PARAMS = [
 ]
 
 
+def test_split_precision_validation_on_host():
+    p, g = _good()
+    p.precision = I.PREC_SPLIT
+    for bad in (-1.0, float("nan")):
+        p.chi_split = bad
+        assert _call_rhs(p, g) == C.EINVAL and "chi_split" in C.last_error()
+    w8 = I.workload(3, n_override=16)
+    p8 = I.Params(**vars(w8.params))
+    p8.precision = I.PREC_SPLIT
+    assert _call_rhs(p8, w8.grid) == C.EUNSUPPORTED and "fd_order 4 only" in C.last_error()
+
+
 @pytest.mark.parametrize("field,value,code,word", BAD_PARAMS)
 def test_invalid_params_rejected_on_host(field, value, code, word):
     p, g = _good()

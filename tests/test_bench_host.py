@@ -30,6 +30,7 @@ def test_bench_refuses_more_than_one_gpu():
 def test_traffic_is_null_once_kernel_sources_change(monkeypatch):
     w = "brill-lindquist-128^3-o4-upwind"
     tile = bench.MEASURED_TRAFFIC[w]["tile"]
+    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: bench.MEASURED_TRAFFIC[w]["sources_sha256"])
     assert bench.measured_traffic(w, tile) == pytest.approx(
         (bench.MEASURED_TRAFFIC[w]["fetch_kib"] * 2.0 + bench.MEASURED_TRAFFIC[w]["write_kib"]) * 1024)
     assert bench.measured_traffic(w, "64x64") is None

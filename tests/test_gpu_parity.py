@@ -378,6 +378,87 @@ def test_tuned_plan_matches_per_patch_steps_and_writes_cache(torch_cuda, tmp_pat
     B2.close()
 
 
+def _split_params(chi_split):
+    p = I.Params(**vars(I.workload(5, n_override=16).params))
+    p.chi_split = chi_split
+    return p
+
+
+def _bl_pert(n, seed):
+    g = bl_grid(n, 3)
+    u = I.brill_lindquist(g)
+    I.add_sinusoids(u, g, np.random.default_rng(seed), 1e-4, range(24), periodic_ghosts=False)
+    return g, u
+
+
+# Split precision.  FP32 unit roundoff is u32 = 2^-24 = 6e-8.  A stencil rounds
+# each FP64 difference once (relative u32) and combines <= 20 of them with
+# cancellation <= 2; the algebra chains <= ~50 FP32 operations over terms up
+# to ~10x the right-hand side they sum to; so a right-hand side is off by
+# <~ 100 u32 ~ 6e-6 of its max-norm, and an RK4 step mixes those with weight
+# dt.  Bars: 1e-5 for one right-hand side and for 20 steps of evolution (the
+# FP64 path meets 1e-12 on the same data).
+@pytest.mark.parametrize("n", [(70, 37, 19), (48, 48, 48)])
+def test_split_rhs_against_oracle(torch_cuda, n):
+    g, u = _bl_pert(n, 5)
+    ref = oracle.rhs(I.workload(2).params, g, u, nthreads=NTHREADS)
+    errs = {}
+    for cs in (0.0, 0.1, float("inf")):
+        got = gpu_rhs(torch_cuda, _split_params(cs), g, u)
+        e = gf_errors(got, ref, g)
+        errs[cs] = e
+        say(f"split chi_split={cs} {n}: max err {e.max():.2e} ({I.GF_NAMES[int(np.argmax(e))]})")
+        assert np.all(np.isfinite(got[(slice(None),) + g.interior()]))
+        assert e.max() <= 1e-5, dict(zip(I.GF_NAMES, e.tolist()))
+    # the FP64 chi phase (chi_split = inf) is at least as accurate on chi as
+    # the FP32 one (chi_split = 0) near the punctures, where 1/chi is large
+    assert errs[float("inf")][I.CHI] <= errs[0.0][I.CHI]
+
+
+def test_split_evolution_against_fp64(torch_cuda):
+    g = bl_grid((48, 48, 48), 3)
+    u = I.brill_lindquist(g)
+    fp64 = gpu_rk4(torch_cuda, I.workload(2).params, g, u, 0.25 * g.h, 20)
+    split = gpu_rk4(torch_cuda, _split_params(0.1), g, u, 0.25 * g.h, 20)
+    e = gf_errors(split, fp64, g)
+    say(f"split vs FP64, 20 steps 48^3: max {e.max():.2e} ({I.GF_NAMES[int(np.argmax(e))]})")
+    assert np.all(np.isfinite(split[(slice(None),) + g.interior()]))
+    assert e.max() <= 1e-5, dict(zip(I.GF_NAMES, e.tolist()))
+
+
+def test_split_tile_variants_agree_and_plans_are_bitwise(torch_cuda):
+    """Split precision in every tile variant agrees within the split bar (the
+    FP32 kernels of different tile shapes and occupancies are compiled
+    separately and may form FMAs differently), and a plan advances each
+    patch bitwise as per-patch calls with the same variant do."""
+    from paper_1307_6488_amd import chemora as C
+    p = _split_params(0.1)
+    g, u = _bl_pert((33, 9, 7), 8)
+    P, X = C.make_params(p), C.make_patch(g, 0x7F0000001000)
+    before = C.chemora_tile_variant(P, X)
+    ref = None
+    try:
+        for v in range(4):
+            C.chemora_set_tile_variant(P, X, v)
+            r = gpu_rhs(torch_cuda, p, g, u)
+            if ref is None:
+                ref = r
+                continue
+            e = gf_errors(r, ref, g)
+            say(f"split variant {v} vs 0: max {e.max():.2e} ({I.GF_NAMES[int(np.argmax(e))]})")
+            assert e.max() <= 1e-5, v
+    finally:
+        C.chemora_set_tile_variant(P, X, before)
+    grids = _small_patches(count=4, seed=33)
+    states = [I.brill_lindquist(gg) for gg in grids]
+    B = C.Batch(p, grids, states, 0.25)
+    B.step(2)
+    torch_cuda.cuda.synchronize()
+    for gg, u0, pp in zip(grids, states, B.patches):
+        assert np.array_equal(pp.u.cpu().numpy(), gpu_rk4(torch_cuda, p, gg, u0, 0.25 * gg.h, 2), equal_nan=True)
+    B.close()
+
+
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
