@@ -2,37 +2,56 @@
 // The staged axis reach R is 2 (centred, Kreiss-Oliger r <= 2) or 3 (upwinded, or r = 3).
 #include "stage_kernel.hpp"
 
-// Staging depth and work-groups per CU.  The staged neighbourhood of one
-// grid function is 22-28 KB: two buffers per work-group let two work-groups
-// share a CU (one wave per SIMD each, 256 registers per lane), which hides
-// more latency than a deeper pipeline at one wave per SIMD (4.0 vs 4.3 ms
-// per 128^3 RK4 step).
-#ifndef CHEMORA_STAGING_DEPTH_O4
-#define CHEMORA_STAGING_DEPTH_O4 2
-#endif
+// Waves per SIMD and staging depth.  FP64 runs two waves per SIMD (256
+// registers per lane): more latency hiding than a deeper pipeline at one
+// wave per SIMD (4.0 vs 4.3 ms per 128^3 RK4 step).  The staged
+// neighbourhood of one grid function is 20-44 KB depending on the tile, and
+// each variant takes the deepest pipeline (up to CHEMORA_MAX_DEPTH_O4
+// buffers) whose work-groups still fit the LDS at that occupancy.
 #ifndef CHEMORA_WAVES_O4
 #define CHEMORA_WAVES_O4 2
+#endif
+#ifndef CHEMORA_MAX_DEPTH_O4
+#define CHEMORA_MAX_DEPTH_O4 3
 #endif
 
 namespace chemora {
 
 namespace {
-// Waves per SIMD: FP64 uses CHEMORA_WAVES_O4; split precision (about 156
-// registers) takes a third wave wherever three work-groups' staging
-// buffers fit the LDS.
+// LDS of one work-group: nb staging buffers, plus the parked staging
+// offsets where the kernel keeps them in LDS (FP64 at two waves per SIMD)
+template <int TX, int WPG, int R, typename T>
+constexpr int lds_bytes(int nb, int occ) {
+  using L = LdsLayout<R, 2, Shape<TX, WPG>>;
+  return nb * L::SIZEP * 8 + ((occ == 2 && sizeof(T) == 8) ? L::CPW * 64 * WPG * 4 : 0);
+}
+template <int WPG>
+constexpr int wgs_per_cu(int occ) {
+  return occ * 4 / WPG > 1 ? occ * 4 / WPG : 1;
+}
+
+// Waves per SIMD: FP64 uses CHEMORA_WAVES_O4; split precision (about 160
+// registers) takes a third wave wherever three work-groups fit the LDS with
+// two buffers each.
 template <int TX, int WPG, int R, typename T>
 constexpr int occupancy() {
   if (!std::is_same<T, float>::value) return CHEMORA_WAVES_O4;
-  using L = LdsLayout<R, 2, Shape<TX, WPG>>;
-  constexpr int bytes = CHEMORA_STAGING_DEPTH_O4 * L::SIZEP * 8;
-  constexpr int wgs = 12 / WPG > 1 ? 12 / WPG : 1;
-  return wgs * bytes <= 160 * 1024 ? 3 : 2;
+  return wgs_per_cu<WPG>(3) * lds_bytes<TX, WPG, R, T>(2, 3) <= 160 * 1024 ? 3 : 2;
+}
+
+template <int TX, int WPG, int R, typename T>
+constexpr int depth() {
+  constexpr int occ = occupancy<TX, WPG, R, T>();
+  int nb = 2;
+  while (nb < CHEMORA_MAX_DEPTH_O4 && wgs_per_cu<WPG>(occ) * lds_bytes<TX, WPG, R, T>(nb + 1, occ) <= 160 * 1024)
+    ++nb;
+  return nb;
 }
 
 template <int TX, int WPG, bool UPWIND, int R, typename T>
 void launch(const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
   hipLaunchKernelGGL(
-      (stage_kernel<4, UPWIND, R, CHEMORA_STAGING_DEPTH_O4, occupancy<TX, WPG, R, T>(), TX, WPG, T>),
+      (stage_kernel<4, UPWIND, R, depth<TX, WPG, R, T>(), occupancy<TX, WPG, R, T>(), TX, WPG, T>),
       dim3(grid), dim3(64, WPG, 1), 0, s, a, bt);
 }
 
