@@ -137,6 +137,15 @@ int chemora_rk4_step(const chemora_params *params, const chemora_patch *patch, d
 int chemora_rk4_stage(const chemora_params *params, const chemora_patch *patch, int stage, double dt,
                       double *scratch, void *stream);
 
+/* Hamiltonian constraint H = chi gt^ij R_ij + 2/3 K^2 - At_ij At^ij of the
+ * state at every interior point (a diagnostic, not part of the step; the
+ * paper's BBH runs monitor the constraints, section "Binary Black Hole
+ * Simulations").  H holds one grid function with the patch's strides
+ * (patch.sf doubles); its ghost entries are not written.  Computed by the
+ * stage kernel's own stencils and Ricci tensor (precision as params).
+ * Errors as chemora_bssn_rhs. */
+int chemora_hamiltonian(const chemora_params *params, const chemora_patch *patch, double *H, void *stream);
+
 /* ---- autotuner: tile variants per size class -----------------------------
  * The stage kernel runs in one of several tile shapes ("variants": 0 = 64x4,
  * 1 = 64x8, 2 = 32x8, 3 = 32x16 points per work-group, x by y; order 8

@@ -25,7 +25,7 @@ EXPORTS = (
     "chemora_rk4_stage", "chemora_check_finite", "chemora_last_error", "chemora_abi_version",
     "chemora_plan_create", "chemora_batch_step", "chemora_plan_points", "chemora_plan_destroy",
     "chemora_plan_patch_variant", "chemora_tune", "chemora_tile_variant", "chemora_set_tile_variant",
-    "chemora_tile_variant_shape",
+    "chemora_tile_variant_shape", "chemora_hamiltonian",
 )
 
 
@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
         L.chemora_plan_points.restype = ctypes.c_int64
         L.chemora_plan_destroy.argtypes = [ctypes.c_void_p]
         L.chemora_plan_destroy.restype = ctypes.c_int
+        L.chemora_hamiltonian.argtypes = [P, X, ctypes.c_void_p, ctypes.c_void_p]
+        L.chemora_hamiltonian.restype = ctypes.c_int
         L.chemora_plan_patch_variant.argtypes = [ctypes.c_void_p, ctypes.c_int32]
         L.chemora_plan_patch_variant.restype = ctypes.c_int
         L.chemora_tune.argtypes = [P, X, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p,
@@ -199,6 +201,11 @@ def chemora_plan_destroy(plan: int) -> int:
     return _check(lib().chemora_plan_destroy(ctypes.c_void_p(plan)))
 
 
+def chemora_hamiltonian(params: chemora_params, patch: chemora_patch, h_ptr: int, stream=None) -> int:
+    return _check(lib().chemora_hamiltonian(ctypes.byref(params), ctypes.byref(patch), ctypes.c_void_p(h_ptr),
+                                            _stream(stream)))
+
+
 def chemora_plan_patch_variant(plan: int, p: int) -> int:
     return _check_id(lib().chemora_plan_patch_variant(ctypes.c_void_p(plan), p))
 
@@ -262,6 +269,16 @@ class Patch:
             out = torch.full_like(self.u, float("nan"))
         chemora_bssn_rhs(self.params, self.patch, out.data_ptr(), stream or torch.cuda.current_stream())
         return out
+
+    def hamiltonian(self, stream=None):
+        """H at the interior points, as a (nz, ny, nx) torch tensor view."""
+        import torch
+        h = torch.full((self.grid.sf,), float("nan"), dtype=torch.float64, device=self.u.device)
+        chemora_hamiltonian(self.params, self.patch, h.data_ptr(), stream or torch.cuda.current_stream())
+        g = self.grid.ghost
+        n = self.grid.n
+        v = h[: self.grid.sz * (n[2] + 2 * g)].view(n[2] + 2 * g, n[1] + 2 * g, self.grid.sy)
+        return v[g:g + n[2], g:g + n[1], g:g + n[0]]
 
     def tune(self, cache_path=None, stream=None) -> int:
         import torch

@@ -395,6 +395,22 @@ int chemora_bssn_rhs(const chemora_params* params, const chemora_patch* patch, d
   return check_launch("bssn_rhs");
 }
 
+int chemora_hamiltonian(const chemora_params* params, const chemora_patch* patch, double* H, void* stream) {
+  g_error.clear();
+  int rc = validate(params, patch);
+  if (rc) return rc;
+  if (!H) return fail(CHEMORA_EINVAL, "H is NULL");
+  if (((uintptr_t)H) % 8) return fail(CHEMORA_EINVAL, "H not 8-byte aligned");
+  const size_t bytes = (size_t)CHEMORA_NGF * patch->sf * sizeof(double);
+  if (overlap(H, patch->sf * sizeof(double), patch->u, bytes)) return fail(CHEMORA_EINVAL, "H overlaps patch.u");
+  chemora::StageArgs a = base_args(params, patch);
+  a.in = a.un = a.yin = patch->u;
+  a.y = a.out = H;
+  a.mode = chemora::MODE_HAM;
+  dispatch_stage(params, a, choose_variant(params, patch), (hipStream_t)stream);
+  return check_launch("hamiltonian");
+}
+
 }  // extern "C"
 
 namespace {

@@ -43,7 +43,9 @@ struct Scales {
   int ko_r;
 };
 
-// What the kernel does with the right-hand side k it computed, with
+// What the kernel does with the right-hand side k it computed (HAM: nothing;
+// it stores the Hamiltonian constraint into out, one GF with the patch's
+// strides, instead), with
 // Y = yin[point] and U = un[point] read at every point in every mode:
 //   RHS     out = k
 //   STAGE1  y = Y + cy k,   out = U + cs k      (yin = un = u_n)
@@ -52,7 +54,7 @@ struct Scales {
 // Pointers a mode does not need are set to an array the stage reads anyway
 // (in / u_n / the accumulator), so the unconditional reads cost no HBM
 // traffic and keep the kernel free of mode-dependent loads.
-enum Mode : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE23 = 2, MODE_STAGE4 = 4 };
+enum Mode : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE23 = 2, MODE_STAGE4 = 4, MODE_HAM = 8 };
 
 struct StageArgs {
   const double* __restrict__ in;   // stencil input of this stage

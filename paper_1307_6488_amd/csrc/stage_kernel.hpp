@@ -388,7 +388,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   };
   // the right-hand side k arrives in T and is combined in FP64
   auto emit = [&](int f, auto kt, const Epi& e) __attribute__((always_inline)) {
-    if (!valid) return;
+    if (!valid || mode == MODE_HAM) return;
     const double kf = double(kt);
     const unsigned so = spt + f * sf * 8u;
     if (mode == MODE_RHS) {
@@ -730,6 +730,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     trDDa += T(W(s)) * gu[s] * DDa[s];
     trRic += T(W(s)) * gu[s] * Ric[s];
   }
+  // the Hamiltonian constraint H = chi gt^ij R_ij + 2/3 K^2 - At_ij At^ij
+  // (diagnostic mode; every phase still runs, so the staging drains normally)
+  if (mode == MODE_HAM && valid)
+    bstore(state_rsrc(a.out, G.sf), vpt, spt, double(chi * trRic + (T(2.0) / T(3.0)) * K * K - AA));
   T xsrc[3];
   {
     const Epi e = epi_load(gK);

@@ -33,10 +33,13 @@ constexpr int wgs_per_cu(int occ) {
 // Waves per SIMD: FP64 uses CHEMORA_WAVES_O4; split precision (about 160
 // registers) takes a third wave wherever three work-groups fit the LDS with
 // two buffers each.
+#ifndef CHEMORA_SPLIT_MAX_WAVES
+#define CHEMORA_SPLIT_MAX_WAVES 3
+#endif
 template <int TX, int WPG, int R, typename T>
 constexpr int occupancy() {
   if (!std::is_same<T, float>::value) return CHEMORA_WAVES_O4;
-  return wgs_per_cu<WPG>(3) * lds_bytes<TX, WPG, R, T>(2, 3) <= 160 * 1024 ? 3 : 2;
+  return CHEMORA_SPLIT_MAX_WAVES >= 3 && wgs_per_cu<WPG>(3) * lds_bytes<TX, WPG, R, T>(2, 3) <= 160 * 1024 ? 3 : 2;
 }
 
 template <int TX, int WPG, int R, typename T>

@@ -140,6 +140,17 @@ def test_rk4_argument_checks_on_host():
     assert C.lib().chemora_rk4_scratch_elems(None) == 0
 
 
+def test_hamiltonian_argument_checks_on_host():
+    p, g = _good()
+    P, X = C.make_params(p), C.make_patch(g, FAKE)
+    assert C.lib().chemora_hamiltonian(ctypes.byref(P), ctypes.byref(X), None, None) == C.EINVAL
+    assert C.lib().chemora_hamiltonian(ctypes.byref(P), ctypes.byref(X), ctypes.c_void_p(FAKE + 8 * 7),
+                                       None) == C.EINVAL
+    assert "overlaps" in C.last_error()
+    assert C.lib().chemora_hamiltonian(ctypes.byref(P), ctypes.byref(X), ctypes.c_void_p(FAKE + (1 << 34) + 4),
+                                       None) == C.EINVAL
+
+
 def test_check_finite_argument_checks_on_host():
     p, g = _good()
     P, X = C.make_params(p), C.make_patch(g, FAKE)

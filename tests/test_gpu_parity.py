@@ -459,6 +459,25 @@ def test_split_tile_variants_agree_and_plans_are_bitwise(torch_cuda):
     B.close()
 
 
+@pytest.mark.parametrize("n", [(48, 40, 36), (33, 9, 7)])
+def test_hamiltonian_constraint_against_oracle(torch_cuda, n):
+    """The GPU Hamiltonian-constraint diagnostic against the oracle's on
+    Brill-Lindquist data with 1e-3 sinusoids in every GF (so that H is far
+    from zero); bar 1e-10 of max |H| (the same arithmetic as one RHS, whose
+    terms cancel into H), and exactly 0 in flat space."""
+    from paper_1307_6488_amd.chemora import Patch
+    g = bl_grid(n, 3)
+    u = I.brill_lindquist(g)
+    I.add_sinusoids(u, g, np.random.default_rng(12), 1e-3, range(24), periodic_ghosts=False)
+    params = I.workload(2).params
+    ref = oracle.hamiltonian(params, g, u, nthreads=NTHREADS)
+    got = Patch(params, g, u).hamiltonian().cpu().numpy()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    say(f"H {n}: max |H| {np.max(np.abs(ref)):.3e}, normalised err {err:.2e}")
+    assert np.all(np.isfinite(got)) and err <= 1e-10
+    assert np.all(Patch(params, g, I.flat(g)).hamiltonian().cpu().numpy() == 0.0)
+
+
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
