@@ -143,6 +143,17 @@ def main():
     wall = time.perf_counter() - wall0
     total_ms = t0.elapsed_time(t1)
     stage_ms = np.array([[ev[k][s - 1].elapsed_time(ev[k][s]) for s in (1, 2, 3, 4)] for k in range(K)])
+    # spread: 5 more repetitions of the same K steps (reported beside value)
+    reps = []
+    for _ in range(5):
+        r0 = torch.cuda.Event(enable_timing=True)
+        r1 = torch.cuda.Event(enable_timing=True)
+        r0.record(stream)
+        for _k in range(K):
+            step()
+        r1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(r0.elapsed_time(r1) / K)
     bad = C.chemora_check_finite(P.params, P.patch)
     if bad:
         print(f"warning: {bad} non-finite values after the run", file=sys.stderr)
@@ -199,6 +210,8 @@ def main():
             "stage23_traffic_over_algorithmic": None if traffic is None else traffic / bytes23,
         },
         "stage_ms": [float(x) for x in stage_ms.mean(axis=0)],
+        "repeat_ms_per_step": {"reps": len(reps), "steps_each": K, "median": float(np.median(reps)),
+                               "min": float(np.min(reps)), "max": float(np.max(reps))},
         "host_wall_s": wall,
     }
     if not args.no_batched:
