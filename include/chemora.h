@@ -11,7 +11,9 @@
  *
  * Conventions shared by every call
  *  - Every entry point returns a chemora_status (0 = OK, < 0 = error) and
- *    never aborts.  On error chemora_last_error() returns a thread-local,
+ *    never aborts, except the queries documented as returning a value (a
+ *    size, a count, a ghost width, a tile variant >= 0 or a negative
+ *    status).  On error chemora_last_error() returns a thread-local,
  *    NUL-terminated message owned by the library (valid until the next call
  *    on the same thread).
  *  - All argument checks run on the host before any HIP call; a call that
@@ -19,9 +21,10 @@
  *  - Device pointers are plain HIP device addresses (e.g. a torch tensor's
  *    data_ptr()); the caller owns and keeps them alive until the work has
  *    completed on `stream`.  `stream` is a hipStream_t passed as void*
- *    (NULL = the default stream).  Work is enqueued asynchronously; there is
- *    no host synchronisation inside these calls.  Device faults surface at
- *    the caller's next synchronisation.
+ *    (NULL = the default stream).  Work is enqueued asynchronously; only
+ *    chemora_check_finite, chemora_tune, chemora_plan_create and
+ *    chemora_plan_destroy synchronise (each says so).  Device faults
+ *    surface at the caller's next synchronisation.
  *  - CHEMORA_EDEVICE reports a failed HIP launch/runtime call.
  *
  * State layout (one patch): 24 grid functions (GFs), FP64, structure of
@@ -85,11 +88,10 @@ typedef struct chemora_params {
                          weights; the algebra is FP32; the state, the RK
                          combination and the 1/chi terms of D_i D_j alpha
                          and the Gt source stay FP64                        */
-  double chi_split;   /* split precision: a wave of 64 points holding a
-                         point with chi < chi_split evaluates the whole chi
-                         phase (d chi, D~D~chi, R^chi, the chi RHS) in FP64
-                         (>= 0, +inf allowed; EINVAL otherwise; ignored for
-                         FP64)                                              */
+  double chi_split;   /* split precision: points with chi < chi_split (near
+                         a puncture) evaluate the whole chi phase (d chi,
+                         D~D~chi, R^chi, the chi RHS) in FP64 (>= 0, +inf
+                         allowed; EINVAL otherwise; ignored for FP64)       */
 } chemora_params;
 
 /* One Cartesian patch (a grid section with its ghost zones). */
@@ -149,8 +151,10 @@ int chemora_hamiltonian(const chemora_params *params, const chemora_patch *patch
 /* ---- autotuner: tile variants per size class -----------------------------
  * The stage kernel runs in one of several tile shapes ("variants": 0 = 64x4,
  * 1 = 64x8, 2 = 32x8, 3 = 32x16 points per work-group, x by y; order 8
- * builds 0 and 2).  All variants compute bit-identical results; they differ
- * in lane use on ragged extents, halo overhead and occupancy.  The choice is
+ * builds 0 and 2).  In FP64 all variants compute bit-identical results; in
+ * split precision they agree to FP32 rounding (their FP32 kernels are
+ * compiled separately).  They differ in lane use on ragged extents, halo
+ * overhead, staging depth and occupancy.  The choice is
  * kept per size class -- (GPU architecture, fd_order, upwind, staged reach,
  * precision, bucket of n[0]: <=32 <=64 <=96 <=128 >128, bucket of n[1]:
  * <=16 <=32 <=64 >64) -- in a process-wide table (thread-safe) that every
@@ -184,9 +188,10 @@ int chemora_tile_variant_shape(int32_t variant, int32_t *tile_x, int32_t *tile_y
 /* ---- batched form: many patches advanced together ------------------------
  * A plan records a list of patches (each with its own spacing h, extents and
  * strides; all share params) and their RK4 scratch buffers.  One RK4 step of
- * every patch is captured once into a HIP graph: per RK stage a single
- * launch covers the tiles of all patches (one work-group per tile).  Patch p advances with
- * its own time step dt_p = courant * h_p.  Patches are independent (each
+ * every patch is captured once into a HIP graph: per RK stage one launch
+ * per tile variant covers the tiles of all the plan's patches of that
+ * variant (one work-group per tile).  Patch p advances with its own time
+ * step dt_p = courant * h_p.  Patches are independent (each
  * keeps its own ghosts); no data moves between patches. */
 typedef struct chemora_plan chemora_plan;   /* opaque, library-owned */
 
@@ -217,7 +222,8 @@ int64_t chemora_plan_points(const chemora_plan *plan);
 /* Tile variant the plan runs patch p (0 <= p < npatch) with; EINVAL else. */
 int chemora_plan_patch_variant(const chemora_plan *plan, int32_t p);
 
-/* Releases the plan (waits for its own work to finish).  NULL is a no-op. */
+/* Releases the plan after synchronising the device (hipDeviceSynchronize:
+ * its graph may still be running).  NULL is a no-op. */
 int chemora_plan_destroy(chemora_plan *plan);
 
 /* Counts NaN/Inf in the interior of all 24 GFs (ghost width from params),
