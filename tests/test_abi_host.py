@@ -129,6 +129,27 @@ def test_invalid_patch_rejected_on_host():
     assert _call_rhs(p, gg) == C.EINVAL
 
 
+def test_size_limits_rejected_on_host():
+    """A 24-GF state over 4 GiB (32-bit byte offsets) is EUNSUPPORTED with a
+    hint to split the patch; extents beyond the launch geometry are EINVAL."""
+    p, _ = _good()
+    P = C.make_params(p)
+    big = I.Grid((300, 300, 300), p.ghost, 0.125)             # 306^3 padded: 5.2 GB of state
+    X = C.make_patch(big, FAKE)
+    assert C.lib().chemora_bssn_rhs(ctypes.byref(P), ctypes.byref(X), ctypes.c_void_p(FAKE + (1 << 40)),
+                                    None) == C.EUNSUPPORTED
+    assert "4 GiB" in C.last_error()
+    ok = I.Grid((280, 280, 256), p.ghost, 0.125)              # just under the limit
+    X = C.make_patch(ok, FAKE)
+    assert 24 * ok.sf * 8 + 64 <= 1 << 32
+    assert C.lib().chemora_rk4_scratch_elems(ctypes.byref(X)) == 3 * 24 * ok.sf
+    tall = I.Grid((8, 70000, 1), p.ghost, 0.125)
+    X = C.make_patch(tall, FAKE)
+    assert C.lib().chemora_bssn_rhs(ctypes.byref(P), ctypes.byref(X), ctypes.c_void_p(FAKE + (1 << 40)),
+                                    None) == C.EINVAL
+    assert "launch geometry" in C.last_error()
+
+
 def test_rk4_argument_checks_on_host():
     p, g = _good()
     for dt in (0.0, -1.0, float("nan"), float("inf")):

@@ -506,6 +506,36 @@ def test_periodic_plan_equals_per_patch_steps(torch_cuda):
     B.close()
 
 
+@pytest.mark.parametrize("n", [(1, 1, 1), (1, 5, 3), (65, 1, 2), (2, 33, 1)])
+def test_degenerate_extents_against_oracle(torch_cuda, n):
+    """Patches one point thick (and a single point): every tile is ragged in
+    x and y, the staging clamps almost everything into the ghost box.  The
+    patch sits off the symmetry point of the two punctures (at the origin
+    K's right-hand side is a near-total cancellation, and one point's
+    max-norm would normalise by that remainder)."""
+    g = I.Grid(n, 3, 1.0 / 8.0, (1.3, 0.7, -0.4))
+    u = I.brill_lindquist(g)
+    I.add_sinusoids(u, g, np.random.default_rng(90), 1e-4, range(24), periodic_ghosts=False)
+    params = I.workload(2).params
+    ref = oracle.rhs(params, g, u, nthreads=NTHREADS)
+    assert_parity(gpu_rhs(torch_cuda, params, g, u), ref, g, 1e-12, f"degenerate {n}")
+    ref = oracle.rk4(params, g, u, 0.25 * g.h, 2, nthreads=NTHREADS)
+    assert_parity(gpu_rk4(torch_cuda, params, g, u, 0.25 * g.h, 2), ref, g, 1e-10, f"degenerate rk4 {n}")
+
+
+def test_rhs_parity_largest_workload(torch_cuda):
+    """The largest single-patch workload (256^3, 3 ghosts, order 4 upwind,
+    FP64): the full right-hand side against the oracle's, element by element."""
+    w = I.workload(5)
+    params = I.Params(**vars(w.params))
+    params.precision = I.PREC_FP64
+    u = w.make_state()
+    say(f"rhs parity at {w.grid.n}")
+    got = gpu_rhs(torch_cuda, params, w.grid, u)
+    ref = oracle.rhs(params, w.grid, u, nthreads=NTHREADS)
+    assert_parity(got, ref, w.grid, 1e-12, "rhs 256^3")
+
+
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
