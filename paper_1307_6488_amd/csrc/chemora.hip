@@ -176,6 +176,11 @@ chemora::Scales make_scales(const chemora_params* P, double h) {
   s.up = 1.0 / (D1 * h);
   s.ko_r = P->ko_radius;
   s.ko = P->ko_radius > 0 ? std::ldexp(P->eps_diss / h, -2 * P->ko_radius) : 0.0;
+  // binomial weights of the 2r-th difference in symmetric differences
+  static const double kw2[5] = {4.0, -1.0, 0.0, 0.0, 0.0}, kw3[5] = {15.0, -6.0, 1.0, 0.0, 0.0},
+                      kw5[5] = {210.0, -120.0, 45.0, -10.0, 1.0};
+  const double* kw = P->ko_radius == 2 ? kw2 : (P->ko_radius == 3 ? kw3 : (P->ko_radius == 5 ? kw5 : nullptr));
+  for (int k = 0; k < 5; ++k) s.kow[k] = kw ? kw[k] : 0.0;
   return s;
 }
 

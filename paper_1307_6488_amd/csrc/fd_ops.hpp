@@ -119,54 +119,37 @@ struct Stencil<8> {
   }
 };
 
-// Split precision: the symmetric differences s_k = (u_k - u_0) + (u_-k - u_0)
-// are formed in FP64 and rounded to FP32, weights and sum in FP32.
+// Kreiss-Oliger term along one axis for radius r <= RMAX (the reach of the
+// caller's staged neighbourhood): the weighted sum of the symmetric
+// differences s_k = (u_k - u_0) + (u_-k - u_0), accumulated from k = 1 upward
+// with the integer weights w[k-1] of the radius (zero past it, so that the
+// radius is data, not a branch), times scale = 2^(-2r) eps / h.  It is a
+// 2r-th difference that cancels by many orders of magnitude on smooth data,
+// so it is evaluated without FMA contraction in this fixed order: the result
+// is then reproducible to the bit across compilers and independent of how
+// the rest is scheduled.  A zero weight adds an exact zero.
 template <int RMAX, class F>
-__device__ __forceinline__ float ko_axis_f(F&& at, int r, float scale) {
+__device__ __forceinline__ double ko_axis(F&& at, const double (&w)[5], double scale) {
+#pragma clang fp contract(off)
+  static_assert(RMAX >= 1 && RMAX <= 5, "radius");
   const double c = at(0);
-  auto s = [&](int k) { return (float)((at(k) - c) + (at(-k) - c)); };
-  float acc;
-  if (RMAX >= 2 && r == 2) {
-    acc = 4.0f * s(1) - s(2);
-  } else if (RMAX >= 3 && r == 3) {
-    acc = 15.0f * s(1) - 6.0f * s(2) + s(3);
-  } else if (RMAX >= 5 && r == 5) {
-    acc = 210.0f * s(1) - 120.0f * s(2) + 45.0f * s(3) - 10.0f * s(4) + s(5);
-  } else {
-    return 0.0f;
-  }
+  auto s = [&](int k) { return (at(k) - c) + (at(-k) - c); };
+  double acc = w[0] * s(1);
+#pragma unroll
+  for (int k = 2; k <= RMAX; ++k) acc = acc + w[k - 1] * s(k);
   return acc * scale;
 }
 
-// Kreiss-Oliger term along one axis: the weighted sum of the symmetric
-// differences s_k, accumulated from k = 1 upward and scaled by
-// scale = 2^(-2r) eps / h.  It is a 2r-th difference that cancels by many
-// orders of magnitude on smooth data, so it is evaluated without FMA
-// contraction in this fixed order: the result is then reproducible to the
-// bit across compilers and independent of how the rest is scheduled.  Radii
-// above RMAX (the reach of the caller's staged neighbourhood) are not built.
+// Split precision: the symmetric differences are formed in FP64 and rounded
+// to FP32, weights and sum in FP32.
 template <int RMAX, class F>
-__device__ __forceinline__ double ko_axis(F&& at, int r, double scale) {
-#pragma clang fp contract(off)
+__device__ __forceinline__ float ko_axis_f(F&& at, const double (&w)[5], float scale) {
+  static_assert(RMAX >= 1 && RMAX <= 5, "radius");
   const double c = at(0);
-  auto s = [&](int k) { return (at(k) - c) + (at(-k) - c); };
-  double acc;
-  if (RMAX >= 2 && r == 2) {
-    acc = 4.0 * s(1);
-    acc = acc - 1.0 * s(2);
-  } else if (RMAX >= 3 && r == 3) {
-    acc = 15.0 * s(1);
-    acc = acc - 6.0 * s(2);
-    acc = acc + 1.0 * s(3);
-  } else if (RMAX >= 5 && r == 5) {
-    acc = 210.0 * s(1);
-    acc = acc - 120.0 * s(2);
-    acc = acc + 45.0 * s(3);
-    acc = acc - 10.0 * s(4);
-    acc = acc + 1.0 * s(5);
-  } else {
-    return 0.0;
-  }
+  auto s = [&](int k) { return (float)((at(k) - c) + (at(-k) - c)); };
+  float acc = float(w[0]) * s(1);
+#pragma unroll
+  for (int k = 2; k <= RMAX; ++k) acc += float(w[k - 1]) * s(k);
   return acc * scale;
 }
 

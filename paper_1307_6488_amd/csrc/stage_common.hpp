@@ -40,6 +40,7 @@ struct Scales {
   double d11;   // 1 / (D1 h)^2
   double up;    // 1 / (DU h)
   double ko;    // 2^(-2r) * (eps / h)
+  double kow[5];  // Kreiss-Oliger weights of s_1 .. s_5 for radius ko_r, zero past it
   int ko_r;
 };
 

@@ -131,6 +131,14 @@ struct LdsLayout {
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
+// a staged grid function's advection and dissipation terms; its right-hand
+// side is (algebra + advection) + dissipation
+template <typename TC>
+struct AdvDiss {
+  TC adv, diss;
+  __device__ __forceinline__ TC rhs(TC alg) const { return (alg + adv) + diss; }
+};
+
 // s_waitcnt vmcnt(N) lgkmcnt(0) (gfx9 encoding: vmcnt bits 3:0 and 15:14,
 // expcnt 6:4 left at its maximum, lgkmcnt 11:8)
 template <int N>
@@ -281,13 +289,61 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     asm volatile("" : "+v"(anc));
     return Taps{cur, anc};
   };
+  // Taps along the three axes through the point serve a phase's first and
+  // pure second derivatives, advection and dissipation.  With LINES (order 4
+  // in FP64) a phase reads all 1 + 6R of them from LDS in one group into
+  // registers, and each mixed derivative reads its 16 taps in one group, so
+  // a work-item waits for LDS a few times per phase instead of once per
+  // stencil.  Otherwise (order 8: more taps than registers to spare; split
+  // precision: three waves per SIMD) every stencil reads its own taps from a
+  // fresh anchor.
+  constexpr bool LINES = ORDER == 4 && !SPLIT;
+  struct LdsAxes {
+    Taps t;
+    __device__ __forceinline__ double operator()(int ax, int o) const {
+      return ax == 0 ? t(o, 0, 0) : (ax == 1 ? t(0, o, 0) : t(0, 0, o));
+    }
+    __device__ __forceinline__ LdsAxes fresh() const { return LdsAxes{t.fresh()}; }
+  };
+  struct RegAxes {
+    Taps t;                  // the mixed derivatives still read from LDS
+    double c;
+    double v[3][2 * R];      // offsets -R..-1, 1..R along each axis
+    __device__ __forceinline__ double operator()(int ax, int o) const {
+      return o == 0 ? c : v[ax][o < 0 ? o + R : o + R - 1];
+    }
+    __device__ __forceinline__ RegAxes fresh() const { return *this; }
+  };
+  // the taps of a phase's buffer, in the form the phase reads them
+  auto phase_src = [&](const Taps& t0) __attribute__((always_inline)) {
+    if constexpr (LINES) {
+      const Taps tap = t0.fresh();
+      RegAxes r;
+      r.t = t0;
+      r.c = tap(0, 0, 0);
+#pragma unroll
+      for (int o = 1; o <= R; ++o) {
+        r.v[0][R - o] = tap(-o, 0, 0);
+        r.v[0][R + o - 1] = tap(o, 0, 0);
+        r.v[1][R - o] = tap(0, -o, 0);
+        r.v[1][R + o - 1] = tap(0, o, 0);
+        r.v[2][R - o] = tap(0, 0, -o);
+        r.v[2][R + o - 1] = tap(0, 0, o);
+      }
+      keep(r.c);
+      keep(r.v);
+      return r;
+    } else {
+      return LdsAxes{t0};
+    }
+  };
   // The stencils below take a precision tag: double() gives the FP64 forms,
   // float() the split forms (FP64 differences rounded to FP32, FP32 weights).
   const double bet_d[3] = {val(gBETA), val(gBETA + 1), val(gBETA + 2)};
-  auto D1 = [&](auto tag, const Taps& t0, int ax) __attribute__((always_inline)) {
+  auto D1 = [&](auto tag, const auto& src, int ax) __attribute__((always_inline)) {
     using TC = decltype(tag);
-    const Taps tap = t0.fresh();
-    auto along = [&](int o) __attribute__((always_inline)) { return ax == 0 ? tap(o, 0, 0) : (ax == 1 ? tap(0, o, 0) : tap(0, 0, o)); };
+    const auto ln = src.fresh();
+    auto along = [&](int o) __attribute__((always_inline)) { return ln(ax, o); };
     TC v;
     if constexpr (std::is_same<TC, float>::value)
       v = St::first_f(along) * float(a.sc.d1);
@@ -296,22 +352,54 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     bound(v);
     return v;
   };
-  auto D2 = [&](auto tag, const Taps& t0, int slot) __attribute__((always_inline)) {
+  // pure second derivative along ax
+  auto D2d = [&](auto tag, const auto& src, int ax) __attribute__((always_inline)) {
+    using TC = decltype(tag);
+    const auto ln = src.fresh();
+    auto along = [&](int o) __attribute__((always_inline)) { return ln(ax, o); };
+    TC v;
+    if constexpr (std::is_same<TC, float>::value)
+      v = St::second_f(along) * float(a.sc.d2);
+    else
+      v = St::second(along) * a.sc.d2;
+    bound(v);
+    return v;
+  };
+  // mixed second derivative of slot (ai != bj): outer D1 along ai of inner
+  // D1's along bj (the inner ones FP64 in both precisions)
+  auto D2m = [&](auto tag, const auto& src, int slot) __attribute__((always_inline)) {
     using TC = decltype(tag);
     constexpr bool F32 = std::is_same<TC, float>::value;
-    const Taps tap = t0.fresh();
+    constexpr int M = St::R;
+    const Taps tap = src.t.fresh();
     const int ai = SI(slot), bj = SJ(slot);
-    auto along = [&](int o) __attribute__((always_inline)) { return ai == 0 ? tap(o, 0, 0) : (ai == 1 ? tap(0, o, 0) : tap(0, 0, o)); };
+    auto at2 = [&](int oa, int ob) __attribute__((always_inline)) {
+      int d[3] = {0, 0, 0};
+      d[ai] = oa;
+      d[bj] = ob;
+      return tap(d[0], d[1], d[2]);
+    };
+    auto idx = [](int o) { return o < 0 ? o + M : o + M - 1; };
     TC v;
-    if (ai == bj) {
+    if constexpr (LINES) {
+      // the 4M^2 taps in one group
+      double m[2 * M][2 * M];
+#pragma unroll
+      for (int oa = -M; oa <= M; ++oa)
+#pragma unroll
+        for (int ob = -M; ob <= M; ++ob)
+          if (oa != 0 && ob != 0) m[idx(oa)][idx(ob)] = at2(oa, ob);
+      keep(m);
+      auto outer = [&](int oa) __attribute__((always_inline)) {
+        return St::first([&](int ob) { return m[idx(oa)][idx(ob)]; });
+      };
       if constexpr (F32)
-        v = St::second_f(along) * float(a.sc.d2);
+        v = St::first_f(outer) * float(a.sc.d11);
       else
-        v = St::second(along) * a.sc.d2;
+        v = St::first(outer) * a.sc.d11;
     } else {
-      // outer D1 along ai of inner D1's along bj (the inner ones FP64 in
-      // both precisions); the barrier after each inner derivative bounds
-      // the live taps to one inner stencil
+      // the barrier after each inner derivative bounds the live taps to one
+      // inner stencil
       auto outer = [&](int oa) __attribute__((always_inline)) {
         const Taps ti = tap.fresh();
         double inner = St::first([&](int ob) {
@@ -331,15 +419,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     bound(v);
     return v;
   };
-  // advection + dissipation of the staged GF; rhs = (algebra + adv) + diss
-  auto finish = [&](auto tag, const Taps& t0, decltype(tag) alg) __attribute__((always_inline)) {
+  // advection and dissipation of the staged GF; its right-hand side is
+  // (algebra + advection) + dissipation
+  auto advdiss = [&](auto tag, const auto& src) __attribute__((always_inline)) {
     using TC = decltype(tag);
     constexpr bool F32 = std::is_same<TC, float>::value;
     TC adv = TC(0.0), diss = TC(0.0);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const Taps tap = t0.fresh();
-      auto along = [&](int o) __attribute__((always_inline)) { return ax == 0 ? tap(o, 0, 0) : (ax == 1 ? tap(0, o, 0) : tap(0, 0, o)); };
+      const auto ln = src.fresh();
+      auto along = [&](int o) __attribute__((always_inline)) { return ln(ax, o); };
       const TC b = TC(bet_d[ax]);
       TC d;
       if (UPWIND) {
@@ -360,18 +449,20 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
           d = St::first(along) * a.sc.d1;
       }
       adv += b * d;
-      if (a.sc.ko_r > 0) {
-        TC qd;
-        if constexpr (F32)
-          qd = ko_axis_f<R>(along, a.sc.ko_r, float(a.sc.ko));
-        else
-          qd = ko_axis<R>(along, a.sc.ko_r, a.sc.ko);
-        diss = (ax == 0) ? qd : diss + qd;
-      }
+      // radius 0 has zero weights and scale: the term is an exact zero
+      TC qd;
+      if constexpr (F32)
+        qd = ko_axis_f<R>(along, a.sc.kow, float(a.sc.ko));
+      else
+        qd = ko_axis<R>(along, a.sc.kow, a.sc.ko);
+      diss = (ax == 0) ? qd : diss + qd;
       bound(adv);
       bound(diss);
     }
-    return (alg + adv) + diss;
+    return AdvDiss<TC>{adv, diss};
+  };
+  auto finish = [&](auto tag, const auto& src, decltype(tag) alg) __attribute__((always_inline)) {
+    return advdiss(tag, src).rhs(alg);
   };
   // RK epilogue.  Its operands (u_n / accumulator values at the point) are
   // loaded by epi_load() before the phase issues its staging loads: loads
@@ -465,18 +556,24 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const Epi e = epi_load(gBETA + c);
     const T Bc = T(val(gB + c));
     begin(c);
-    auto tap = make_ops(bufs[c % NB]);
+    const auto src = phase_src(make_ops(bufs[c % NB]));
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) db[c][ax] = D1(T(), tap, ax);
+    for (int ax = 0; ax < 3; ++ax) db[c][ax] = D1(T(), src, ax);
+    // the axis stencils first, so that register-held axis taps die before
+    // the mixed derivatives read theirs
+    T d2p[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) d2p[ax] = D2d(T(), src, ax);
+    const AdvDiss<T> ad = advdiss(T(), src);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-      const T dd = D2(T(), tap, q);
-      xts[c] += T(W(q)) * gu[q] * dd;
       const int qi = SI(q), qj = SJ(q);
+      const T dd = qi == qj ? d2p[qi] : D2m(T(), src, q);
+      xts[c] += T(W(q)) * gu[q] * dd;
       if (qj == c) ddiv[qi] += dd;
       if (qi == c && qi != qj) ddiv[qj] += dd;
     }
-    emit(gBETA + c, driver ? finish(T(), tap, T(0.75) * Bc) : T(0.0), e);
+    emit(gBETA + c, driver ? ad.rhs(T(0.75) * Bc) : T(0.0), e);
     keep(db[c]);
     keep(xts);
     keep(ddiv);
@@ -496,18 +593,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       const Epi e = epi_load(gGT + s);
       const T As = T(val(gAT + s));
       begin(p);
-      auto tap = make_ops(bufs[p % NB]);
+      const auto src = phase_src(make_ops(bufs[p % NB]));
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) dg[s][ax] = D1(T(), tap, ax);
+      for (int ax = 0; ax < 3; ++ax) dg[s][ax] = D1(T(), src, ax);
+      T d2p[3];
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) d2p[ax] = D2d(T(), src, ax);
+      const AdvDiss<T> ad = advdiss(T(), src);
       T r = T(0.0);
 #pragma unroll
-      for (int q = 0; q < 6; ++q) r += T(W(q)) * gu[q] * D2(T(), tap, q);
+      for (int q = 0; q < 6; ++q) r += T(W(q)) * gu[q] * (SI(q) == SJ(q) ? d2p[SI(q)] : D2m(T(), src, q));
       Ric[s] = -T(0.5) * r;
       const int i = SI(s), jj = SJ(s);
       T lie = T(0.0);
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) lie += g[S(i, kk)] * db[kk][jj] + g[S(jj, kk)] * db[kk][i];
-      emit(gGT + s, finish(T(), tap, -T(2.0) * alpha * As + lie - (T(2.0) / T(3.0)) * g[s] * divb), e);
+      emit(gGT + s, ad.rhs(-T(2.0) * alpha * As + lie - (T(2.0) / T(3.0)) * g[s] * divb), e);
       keep(Ric[s]);
       keep(dg[s]);
       sync(p);
@@ -592,7 +693,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   {
     const Epi e = epi_load(gCHI);
     begin(9);
-    auto tap = make_ops(bufs[9 % NB]);
+    const auto tap = make_ops(bufs[9 % NB]);
     // the chi phase in precision TC, returned rather than applied: its Ricci
     // contributions, d chi (FP64) and the right-hand side of chi
     struct ChiPart {
@@ -603,13 +704,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     auto chi_phase = [&](auto tag) __attribute__((always_inline)) {
       using TC = decltype(tag);
       ChiPart out;
+      const auto src = phase_src(tap);
       TC dc[3];
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) dc[ax] = D1(tag, tap, ax);
+      for (int ax = 0; ax < 3; ++ax) dc[ax] = D1(tag, src, ax);
+      TC d2p[3];
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) d2p[ax] = D2d(tag, src, ax);
+      const AdvDiss<TC> ad = advdiss(tag, src);
       TC cdd[6];
 #pragma unroll
       for (int s = 0; s < 6; ++s)
-        cdd[s] = D2(tag, tap, s) - (TC(Gu[0][s]) * dc[0] + TC(Gu[1][s]) * dc[1] + TC(Gu[2][s]) * dc[2]);
+        cdd[s] = (SI(s) == SJ(s) ? d2p[SI(s)] : D2m(tag, src, s)) -
+                 (TC(Gu[0][s]) * dc[0] + TC(Gu[1][s]) * dc[1] + TC(Gu[2][s]) * dc[2]);
       TC trc = TC(0.0), dchi2 = TC(0.0);
 #pragma unroll
       for (int s = 0; s < 6; ++s) {
@@ -623,7 +730,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
                        TC(0.25) * ic * ic * (dc[SI(s)] * dc[SJ(s)] + TC(3.0) * TC(g[s]) * dchi2));
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) out.dchi[ax] = double(dc[ax]);
-      out.k = T(finish(tag, tap, TC(2.0 / 3.0) * TC(chi_d) * (TC(alpha_d) * TC(K_d) - TC(divb))));
+      out.k = T(ad.rhs(TC(2.0 / 3.0) * TC(chi_d) * (TC(alpha_d) * TC(K_d) - TC(divb))));
       return out;
     };
     // apply a chi-phase result to the points that take it
@@ -663,9 +770,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   {
     const Epi e = epi_load(gALPHA);
     begin(10);
-    auto tap = make_ops(bufs[10 % NB]);
+    const auto src = phase_src(make_ops(bufs[10 % NB]));
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) da[ax] = D1(T(), tap, ax);
+    for (int ax = 0; ax < 3; ++ax) da[ax] = D1(T(), src, ax);
+    T d2p[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) d2p[ax] = D2d(T(), src, ax);
+    const AdvDiss<T> ad = advdiss(T(), src);
     // the 1/chi correction is evaluated in FP64 in both precisions
     double gudchi_da = 0.0;
 #pragma unroll
@@ -676,14 +787,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     for (int s = 0; s < 6; ++s) {
       const int i = SI(s), jj = SJ(s);
       const double corr = 0.5 * ichi * (double(g[s]) * gudchi_da - dchi[jj] * double(da[i]) - dchi[i] * double(da[jj]));
-      DDa[s] = D2(T(), tap, s) - (Gu[0][s] * da[0] + Gu[1][s] * da[1] + Gu[2][s] * da[2]) - T(corr);
+      DDa[s] = (SI(s) == SJ(s) ? d2p[SI(s)] : D2m(T(), src, s)) - (Gu[0][s] * da[0] + Gu[1][s] * da[1] + Gu[2][s] * da[2]) -
+               T(corr);
     }
     keep(da);
     keep(DDa);
     if (gauge.lapse == 2)
       emit(gALPHA, T(0.0), e);
     else
-      emit(gALPHA, finish(T(), tap, gauge.lapse == 0 ? -T(2.0) * alpha * K : -alpha * alpha * K), e);
+      emit(gALPHA, ad.rhs(gauge.lapse == 0 ? -T(2.0) * alpha * K : -alpha * alpha * K), e);
     sync(10);
   }
 
@@ -693,10 +805,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   for (int c = 0; c < 3; ++c) {
     const int p = 11 + c;
     begin(p);
-    auto tap = make_ops(bufs[p % NB]);
+    const auto src = phase_src(make_ops(bufs[p % NB]));
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const T d = D1(T(), tap, ax);
+      const T d = D1(T(), src, ax);
 #pragma unroll
       for (int s = 0; s < 6; ++s) {
         const int i = SI(s), jj = SJ(s);
@@ -704,7 +816,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
         if (i == ax) Ric[s] += T(0.5) * g[S(c, jj)] * d;
       }
     }
-    xt_ad[c] = finish(T(), tap, T(0.0));
+    xt_ad[c] = finish(T(), src, T(0.0));
     keep(xt_ad[c]);
     keep(Ric);
     sync(p);
@@ -739,11 +851,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const Epi e = epi_load(gK);
     const Epi ex[3] = {epi_load(gXT), epi_load(gXT + 1), epi_load(gXT + 2)};
     begin(14);
-    auto tap = make_ops(bufs[14 % NB]);
+    const auto src = phase_src(make_ops(bufs[14 % NB]));
     T dK[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) dK[ax] = D1(T(), tap, ax);
-    emit(gK, finish(T(), tap, -chi * trDDa + alpha * (AA + K * K * (T(1.0) / T(3.0)))), e);
+    for (int ax = 0; ax < 3; ++ax) dK[ax] = D1(T(), src, ax);
+    emit(gK, finish(T(), src, -chi * trDDa + alpha * (AA + K * K * (T(1.0) / T(3.0)))), e);
     // Gt source, complete now
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -768,7 +880,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const int p = 15 + s;
     const Epi e = epi_load(gAT + s);
     begin(p);
-    auto tap = make_ops(bufs[p % NB]);
+    const auto src = phase_src(make_ops(bufs[p % NB]));
     const int i = SI(s), jj = SJ(s);
     T la = T(0.0), aa = T(0.0);
 #pragma unroll
@@ -779,7 +891,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       aa += A[S(i, kk)] * amkj;
     }
     const T X = alpha * Ric[s] - DDa[s];
-    emit(gAT + s, finish(T(), tap, chi * (X - (T(1.0) / T(3.0)) * g[s] * trX) + alpha * (K * A[s] - T(2.0) * aa) + la -
+    emit(gAT + s, finish(T(), src, chi * (X - (T(1.0) / T(3.0)) * g[s] * trX) + alpha * (K * A[s] - T(2.0) * aa) + la -
                               (T(2.0) / T(3.0)) * A[s] * divb), e);
     sync(p);
   }
@@ -792,8 +904,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       const Epi e = epi_load(gB + c);
       const T Bc = T(val(gB + c));
       begin(p);
-      auto tap = make_ops(bufs[p % NB]);
-      emit(gB + c, finish(T(), tap, xsrc[c] - gauge.eta * Bc), e);
+      const auto src = phase_src(make_ops(bufs[p % NB]));
+      emit(gB + c, finish(T(), src, xsrc[c] - gauge.eta * Bc), e);
       sync(p);
     }
   } else {
