@@ -395,6 +395,8 @@ int chemora_bssn_rhs(const chemora_params* params, const chemora_patch* patch, d
   chemora::StageArgs a = base_args(params, patch);
   a.in = a.un = a.yin = patch->u;
   a.out = rhs;
+  a.cu = 0.0;
+  a.cs = 1.0;
   a.mode = chemora::MODE_RHS;
   dispatch_stage(params, a, choose_variant(params, patch), (hipStream_t)stream);
   return check_launch("bssn_rhs");
@@ -439,6 +441,7 @@ int rk4_checks(const chemora_params* params, const chemora_patch* patch, double 
 // Returns the buffer the stage writes.
 double* stage_args(chemora::StageArgs& a, int stage, double dt, double* u, double* SA, double* SB, double* Y) {
   a.y = Y;
+  a.cu = 1.0;
   switch (stage) {
     case 1:
       a.in = u; a.un = u; a.yin = u; a.out = SA; a.cy = dt / 6.0; a.cs = 0.5 * dt;
@@ -453,7 +456,7 @@ double* stage_args(chemora::StageArgs& a, int stage, double dt, double* u, doubl
       a.mode = chemora::MODE_STAGE23;
       return SA;
     default:
-      a.in = SA; a.un = Y; a.yin = Y; a.out = u; a.cy = dt / 6.0; a.cs = 0.0;
+      a.in = SA; a.un = Y; a.yin = Y; a.out = u; a.cy = dt / 6.0; a.cs = dt / 6.0;
       a.mode = chemora::MODE_STAGE4;
       return u;
   }

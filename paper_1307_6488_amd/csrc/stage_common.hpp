@@ -47,11 +47,12 @@ struct Scales {
 // What the kernel does with the right-hand side k it computed (HAM: nothing;
 // it stores the Hamiltonian constraint into out, one GF with the patch's
 // strides, instead), with
-// Y = yin[point] and U = un[point] read at every point in every mode:
-//   RHS     out = k
+// Y = yin[point] and U = un[point] read at every point in every mode, and
+// out = cu U + cs k formed as fma(cs, k, cu U):
+//   RHS     out = k                             (cu = 0, cs = 1)
 //   STAGE1  y = Y + cy k,   out = U + cs k      (yin = un = u_n)
 //   STAGE23 y = Y + cy k,   out = U + cs k      (yin = y, un = u_n)
-//   STAGE4  out = Y + cy k                      (yin = accumulator)
+//   STAGE4  out = U + cs k                      (un = yin = accumulator, cs = cy)
 // Pointers a mode does not need are set to an array the stage reads anyway
 // (in / u_n / the accumulator), so the unconditional reads cost no HBM
 // traffic and keep the kernel free of mode-dependent loads.
@@ -67,7 +68,8 @@ struct StageArgs {
   Scales sc;
   Gauge gauge;
   double cy;                       // weight of k in the accumulator update
-  double cs;                       // weight of k in the next stage input
+  double cs;                       // weight of k in out
+  double cu;                       // weight of U in out (0 for the bare right-hand side)
   double chi_split;                // split precision: FP64 chi phase where chi < chi_split
   int tiles_x, tiles_y;            // tile grid of the launch's tile variant
   int mode;                        // a Mode

@@ -24,11 +24,11 @@
 //           - [d_i chi d_j chi + 3 gt_ij |d chi|^2] / (4 chi^2).
 // Each variable's right-hand side is (algebra + advection) + dissipation.
 //
-// Work decomposition.  A work-group (4 waves) owns a 64 x 4 tile of one
-// z-plane, one work-item per point.  The paper's kernels spill because every
-// derivative is formed before the algebra (section "Fat Kernel Detection");
-// here the right-hand side is evaluated grid function by grid function in
-// dependency order
+// Work decomposition.  A work-group owns a TX x TY tile of one z-plane (TX =
+// 32 or 64 columns, one wave per 64 / TX rows), one work-item per point.  The
+// paper's kernels spill because every derivative is formed before the
+// algebra (section "Fat Kernel Detection"); here the right-hand side is
+// evaluated grid function by grid function in dependency order
 //     beta(3) gt(6) chi alpha Gt(3) K At(6) B(3)
 // and every stencil result is consumed at once: second derivatives are
 // contracted straight into the Ricci, D_i D_j alpha and Gt-source
@@ -39,16 +39,16 @@
 // Staging.  Each grid function's stencil neighbourhood is copied into LDS by
 // direct global->LDS loads (buffer_load_dwordx4 ... lds: lane l moves two
 // doubles to LDS bytes [16 l, 16 l + 16) of the instruction's 1 KiB chunk), no
-// registers involved, double-buffered: the next grid function's chunks are in
-// flight while the work-items evaluate the current one's stencils from LDS
-// with compile-time offsets.  Every lane's global offset for each of its
-// wave's chunks is computed once per tile, so issuing a grid function costs
-// one instruction per chunk.  One barrier per grid function.
+// registers involved, through NB buffers: the chunks of the next NB - 1 grid
+// functions are in flight while the work-items evaluate the current one's
+// stencils from LDS with compile-time offsets.  Every lane's global offset
+// for each of its wave's chunks is computed once per tile, so issuing a grid
+// function costs one instruction per chunk.  One barrier per grid function.
 //
-// LDS layout per staged grid function (pitch P = 64 + 2R doubles):
-//   plane dz = 0            rows y in [-R,  3+R]   (x and y stencils, xy mixed)
-//   planes 1 <= |dz| <= RM  rows y in [-RM, 3+RM]  (xz / yz mixed, z stencils)
-//   planes RM < |dz| <= R   rows y in [0, 3]       (z stencils only)
+// LDS layout per staged grid function (pitch P = TX + 2R doubles):
+//   plane dz = 0            rows y in [-R,  TY-1+R]   (x and y stencils, xy mixed)
+//   planes 1 <= |dz| <= RM  rows y in [-RM, TY-1+RM]  (xz / yz mixed, z stencils)
+//   planes RM < |dz| <= R   rows y in [0, TY-1]       (z stencils only)
 // with R the axis reach (upwind, Kreiss-Oliger) and RM = ORDER/2 the mixed
 // reach; planes are ordered dz = 0, +1, -1, +2, -2, ...
 #pragma once
@@ -252,14 +252,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   };
 
   const int anchor = yr * L::P + xr;
-  // stencil access into the buffer of the current phase
   // Stencil taps of the current phase's buffer.  Each phase addresses it from
   // an opaque copy of the anchor: LDS reads are merged in pairs (8-bit
   // offsets, +-2 KB), so a buffer needs a base register per 2 KB it spans,
   // and shared across phases those bases would stay live through the whole
-  // kernel.  With wide (order-8) stencils every stencil group also takes a
-  // fresh copy, so a tap used by several groups is read again from LDS
-  // instead of being held in a register across the phase.
+  // kernel.  Every stencil group also takes a fresh copy, so a tap used by
+  // several groups is read again from LDS instead of being held in a
+  // register across the phase.
   struct Taps {
     const double* cur;
     int anc;
@@ -290,14 +289,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     return Taps{cur, anc};
   };
   // Taps along the three axes through the point serve a phase's first and
-  // pure second derivatives, advection and dissipation.  With LINES (order 4
-  // in FP64) a phase reads all 1 + 6R of them from LDS in one group into
-  // registers, and each mixed derivative reads its 16 taps in one group, so
-  // a work-item waits for LDS a few times per phase instead of once per
-  // stencil.  Otherwise (order 8: more taps than registers to spare; split
-  // precision: three waves per SIMD) every stencil reads its own taps from a
-  // fresh anchor.
-  constexpr bool LINES = ORDER == 4 && !SPLIT;
+  // pure second derivatives, advection and dissipation.  With LINES (order 4)
+  // a phase reads all 1 + 6R of them from LDS in one group into registers,
+  // and each mixed derivative reads its 16 taps in one group, so a work-item
+  // waits for LDS a few times per phase instead of once per stencil.  Order 8
+  // (more taps than registers to spare) reads every stencil's taps on their
+  // own from a fresh anchor.
+  constexpr bool LINES = ORDER == 4;
   struct LdsAxes {
     Taps t;
     __device__ __forceinline__ double operator()(int ax, int o) const {
@@ -477,19 +475,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const unsigned so = spt + f * sf * 8u;
     return Epi{bload(ryin, vpt, so), bload(run, vpt, so)};
   };
-  // the right-hand side k arrives in T and is combined in FP64
+  // the right-hand side k arrives in T and is combined in FP64; every mode
+  // but HAM stores out = fma(cs, k, cu U), stages 1-3 also the accumulator
+  const bool store_out = mode != MODE_HAM;
+  const bool store_y = mode == MODE_STAGE1 || mode == MODE_STAGE23;
   auto emit = [&](int f, auto kt, const Epi& e) __attribute__((always_inline)) {
-    if (!valid || mode == MODE_HAM) return;
+    if (!(valid && store_out)) return;
     const double kf = double(kt);
     const unsigned so = spt + f * sf * 8u;
-    if (mode == MODE_RHS) {
-      bstore(state_rsrc(a.out, G.sf), vpt, so, kf);
-    } else if (mode == MODE_STAGE4) {
-      bstore(state_rsrc(a.out, G.sf), vpt, so, e.y + a.cy * kf);
-    } else {
-      bstore(state_rsrc(a.y, G.sf), vpt, so, e.y + a.cy * kf);
-      bstore(state_rsrc(a.out, G.sf), vpt, so, e.u + a.cs * kf);
-    }
+    if (store_y) bstore(state_rsrc(a.y, G.sf), vpt, so, e.y + a.cy * kf);
+    bstore(state_rsrc(a.out, G.sf), vpt, so, __builtin_fma(a.cs, kf, a.cu * e.u));
   };
 
   // staging sequence: 24 phases (B only with the Gamma-driver shift)
