@@ -289,59 +289,46 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     return Taps{cur, anc};
   };
   // Taps along the three axes through the point serve a phase's first and
-  // pure second derivatives, advection and dissipation.  With LINES (order 4)
-  // a phase reads all 1 + 6R of them from LDS in one group into registers,
-  // and each mixed derivative reads its 16 taps in one group, so a work-item
-  // waits for LDS a few times per phase instead of once per stencil.  Order 8
-  // (more taps than registers to spare) reads every stencil's taps on their
-  // own from a fresh anchor.
-  constexpr bool LINES = ORDER == 4;
-  struct LdsAxes {
-    Taps t;
-    __device__ __forceinline__ double operator()(int ax, int o) const {
-      return ax == 0 ? t(o, 0, 0) : (ax == 1 ? t(0, o, 0) : t(0, 0, o));
-    }
-    __device__ __forceinline__ LdsAxes fresh() const { return LdsAxes{t.fresh()}; }
-  };
-  struct RegAxes {
-    Taps t;                  // the mixed derivatives still read from LDS
+  // pure second derivatives, advection and dissipation.  A phase reads all
+  // 1 + 6R of them from LDS in one group into registers, so a work-item
+  // waits for LDS a few times per phase instead of once per stencil.  At
+  // order 4 each mixed derivative also reads its 16 taps in one group; at
+  // order 8 (64 taps, more than the registers to spare) a mixed derivative
+  // reads one inner stencil at a time from a fresh anchor.
+  constexpr bool MIXED_GROUP = ORDER == 4;
+  struct Axes {
+    Taps t;                  // the mixed derivatives read from LDS
     double c;
     double v[3][2 * R];      // offsets -R..-1, 1..R along each axis
     __device__ __forceinline__ double operator()(int ax, int o) const {
       return o == 0 ? c : v[ax][o < 0 ? o + R : o + R - 1];
     }
-    __device__ __forceinline__ RegAxes fresh() const { return *this; }
   };
-  // the taps of a phase's buffer, in the form the phase reads them
+  // the axis taps of a phase's buffer, read in one group
   auto phase_src = [&](const Taps& t0) __attribute__((always_inline)) {
-    if constexpr (LINES) {
-      const Taps tap = t0.fresh();
-      RegAxes r;
-      r.t = t0;
-      r.c = tap(0, 0, 0);
+    const Taps tap = t0.fresh();
+    Axes r;
+    r.t = t0;
+    r.c = tap(0, 0, 0);
 #pragma unroll
-      for (int o = 1; o <= R; ++o) {
-        r.v[0][R - o] = tap(-o, 0, 0);
-        r.v[0][R + o - 1] = tap(o, 0, 0);
-        r.v[1][R - o] = tap(0, -o, 0);
-        r.v[1][R + o - 1] = tap(0, o, 0);
-        r.v[2][R - o] = tap(0, 0, -o);
-        r.v[2][R + o - 1] = tap(0, 0, o);
-      }
-      keep(r.c);
-      keep(r.v);
-      return r;
-    } else {
-      return LdsAxes{t0};
+    for (int o = 1; o <= R; ++o) {
+      r.v[0][R - o] = tap(-o, 0, 0);
+      r.v[0][R + o - 1] = tap(o, 0, 0);
+      r.v[1][R - o] = tap(0, -o, 0);
+      r.v[1][R + o - 1] = tap(0, o, 0);
+      r.v[2][R - o] = tap(0, 0, -o);
+      r.v[2][R + o - 1] = tap(0, 0, o);
     }
+    keep(r.c);
+    keep(r.v);
+    return r;
   };
   // The stencils below take a precision tag: double() gives the FP64 forms,
   // float() the split forms (FP64 differences rounded to FP32, FP32 weights).
   const double bet_d[3] = {val(gBETA), val(gBETA + 1), val(gBETA + 2)};
   auto D1 = [&](auto tag, const auto& src, int ax) __attribute__((always_inline)) {
     using TC = decltype(tag);
-    const auto ln = src.fresh();
-    auto along = [&](int o) __attribute__((always_inline)) { return ln(ax, o); };
+    auto along = [&](int o) __attribute__((always_inline)) { return src(ax, o); };
     TC v;
     if constexpr (std::is_same<TC, float>::value)
       v = St::first_f(along) * float(a.sc.d1);
@@ -353,8 +340,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // pure second derivative along ax
   auto D2d = [&](auto tag, const auto& src, int ax) __attribute__((always_inline)) {
     using TC = decltype(tag);
-    const auto ln = src.fresh();
-    auto along = [&](int o) __attribute__((always_inline)) { return ln(ax, o); };
+    auto along = [&](int o) __attribute__((always_inline)) { return src(ax, o); };
     TC v;
     if constexpr (std::is_same<TC, float>::value)
       v = St::second_f(along) * float(a.sc.d2);
@@ -379,7 +365,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     };
     auto idx = [](int o) { return o < 0 ? o + M : o + M - 1; };
     TC v;
-    if constexpr (LINES) {
+    if constexpr (MIXED_GROUP) {
       // the 4M^2 taps in one group
       double m[2 * M][2 * M];
 #pragma unroll
@@ -425,8 +411,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     TC adv = TC(0.0), diss = TC(0.0);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const auto ln = src.fresh();
-      auto along = [&](int o) __attribute__((always_inline)) { return ln(ax, o); };
+      auto along = [&](int o) __attribute__((always_inline)) { return src(ax, o); };
       const TC b = TC(bet_d[ax]);
       TC d;
       if (UPWIND) {
