@@ -31,15 +31,22 @@
 
 namespace chemora {
 
+constexpr int GHOST_THREADS = 256;
+
 // Ghost shells, one work-group per stored row (j, k) of the full extent.
 // STATIC: copy the ghosts of `src` into dst0 and dst1.  PERIODIC: fill the
-// ghosts of dst0 with periodic images of its own interior.
+// ghosts of dst0 with periodic images of its own interior.  A row inside the
+// y/z ghost layers is a ghost row whole; any other row has 2g ghost points,
+// g at each end.  The work-items of a row share out its (grid function,
+// point) pairs, points fastest, so all 24 grid functions are in flight at
+// once.
 template <bool PERIODIC>
-__global__ __launch_bounds__(64) void ghost_kernel(const double* __restrict__ src, double* dst0,
-                                                   double* dst1, Geo G) {
+__global__ __launch_bounds__(GHOST_THREADS) void ghost_kernel(const double* __restrict__ src, double* dst0,
+                                                              double* dst1, Geo G) {
   const int j = blockIdx.x, k = blockIdx.y;
   const int ex = G.nx + 2 * G.g;
   const bool ghost_row = j < G.g || j >= G.ny + G.g || k < G.g || k >= G.nz + G.g;
+  const int per_f = ghost_row ? ex : 2 * G.g;
   int jj = j, kk = k;
   if (PERIODIC) {
     jj = ((j - G.g) % G.ny + G.ny) % G.ny + G.g;
@@ -47,17 +54,17 @@ __global__ __launch_bounds__(64) void ghost_kernel(const double* __restrict__ sr
   }
   const int64_t row = (int64_t)k * G.sz + (int64_t)j * G.sy;
   const int64_t srow = (int64_t)kk * G.sz + (int64_t)jj * G.sy;
-  for (int i = threadIdx.x; i < ex; i += blockDim.x) {
-    if (!ghost_row && i >= G.g && i < G.nx + G.g) continue;
+  for (int t = threadIdx.x; t < 24 * per_f; t += GHOST_THREADS) {
+    const int f = t / per_f, c = t - f * per_f;
+    const int i = ghost_row ? c : (c < G.g ? c : G.nx + c);
+    const int64_t at = f * G.sf + row + i;
     if (PERIODIC) {
       const int ii = ((i - G.g) % G.nx + G.nx) % G.nx + G.g;
-      for (int f = 0; f < 24; ++f) dst0[f * G.sf + row + i] = dst0[f * G.sf + srow + ii];
+      dst0[at] = dst0[f * G.sf + srow + ii];
     } else {
-      for (int f = 0; f < 24; ++f) {
-        const double v = src[f * G.sf + row + i];
-        dst0[f * G.sf + row + i] = v;
-        dst1[f * G.sf + row + i] = v;
-      }
+      const double v = src[at];
+      dst0[at] = v;
+      dst1[at] = v;
     }
   }
 }
@@ -362,9 +369,9 @@ void launch_ghosts(bool periodic, const chemora::Geo& G, const double* src, doub
                    hipStream_t s) {
   dim3 grid(G.ny + 2 * G.g, G.nz + 2 * G.g, 1);
   if (periodic)
-    hipLaunchKernelGGL((chemora::ghost_kernel<true>), grid, dim3(64), 0, s, src, d0, d1, G);
+    hipLaunchKernelGGL((chemora::ghost_kernel<true>), grid, dim3(chemora::GHOST_THREADS), 0, s, src, d0, d1, G);
   else
-    hipLaunchKernelGGL((chemora::ghost_kernel<false>), grid, dim3(64), 0, s, src, d0, d1, G);
+    hipLaunchKernelGGL((chemora::ghost_kernel<false>), grid, dim3(chemora::GHOST_THREADS), 0, s, src, d0, d1, G);
 }
 
 }  // namespace
