@@ -164,10 +164,12 @@ int chemora_hamiltonian(const chemora_params *params, const chemora_patch *patch
  * they are timed on the target GPU, as its autotuning sections describe. */
 
 /* Chooses the variant for patch's class: an entry already in the table (set,
- * tuned or loaded) is kept; otherwise every built variant is timed on one
- * RK4 stage-2 launch of this patch (reads patch.u and scratch, overwrites the
- * S_B and accumulator parts of scratch; scratch as for chemora_rk4_step)
- * and the fastest is recorded.  cache_path (may be NULL): a JSON cache read
+ * tuned or loaded) is kept; otherwise every built variant is timed on RK4
+ * stage-2 launches of this patch (reads patch.u and scratch, overwrites the
+ * S_B and accumulator parts of scratch; scratch as for chemora_rk4_step):
+ * one warm-up launch each, then three rounds that time every variant in
+ * turn over two launches, and the variant with the fastest sample is
+ * recorded.  cache_path (may be NULL): a JSON cache read
  * before and rewritten after (written to <path>.tmp, then renamed); entries
  * of this process win over the file's.  Synchronises `stream`.  *variant
  * (may be NULL) receives the choice.  Errors as chemora_rk4_step, EINVAL if

@@ -553,29 +553,43 @@ int time_variants(const chemora_params* P, const chemora_patch* X, double* scrat
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
+  // one warm-up launch per variant, then rounds that time every variant in
+  // turn (2 launches per sample) and keep each variant's fastest sample, so
+  // that clock ramps and stray interference do not favour one variant
+  constexpr int ROUNDS = 3, PER_SAMPLE = 2;
+  float ms_v[chemora::NVARIANT];
+  for (int v = 0; v < chemora::NVARIANT; ++v) ms_v[v] = -1.0f;
+  for (int v = 0; v < chemora::NVARIANT && e == hipSuccess; ++v)
+    if (chemora::variant_supported(P->fd_order, v)) dispatch_stage(P, a, v, s);
+  for (int r = 0; r < ROUNDS && e == hipSuccess; ++r) {
+    for (int v = 0; v < chemora::NVARIANT && e == hipSuccess; ++v) {
+      if (!chemora::variant_supported(P->fd_order, v)) continue;
+      e = hipEventRecord(e0, s);
+      for (int k = 0; k < PER_SAMPLE && e == hipSuccess; ++k) dispatch_stage(P, a, v, s);
+      if (e == hipSuccess) e = hipGetLastError();
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) break;
+      ms /= PER_SAMPLE;
+      if (ms_v[v] < 0.0f || ms < ms_v[v]) ms_v[v] = ms;
+    }
+  }
   float best_ms = 0.0f;
-  *best = 0;
+  *best = -1;
   std::ostringstream t;
   for (int v = 0; v < chemora::NVARIANT && e == hipSuccess; ++v) {
-    if (!chemora::variant_supported(P->fd_order, v)) continue;
-    dispatch_stage(P, a, v, s);
-    e = hipEventRecord(e0, s);
-    for (int r = 0; r < 3 && e == hipSuccess; ++r) dispatch_stage(P, a, v, s);
-    if (e == hipSuccess) e = hipGetLastError();
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) break;
-    ms /= 3.0f;
+    if (ms_v[v] < 0.0f) continue;
     char buf[64];
-    std::snprintf(buf, sizeof buf, "%s\"%s\": %.4f", t.tellp() > 0 ? ", " : "", variant_name(v).c_str(), ms);
+    std::snprintf(buf, sizeof buf, "%s\"%s\": %.4f", t.tellp() > 0 ? ", " : "", variant_name(v).c_str(), ms_v[v]);
     t << buf;
-    if (v == 0 || ms < best_ms) {
-      best_ms = ms;
+    if (*best < 0 || ms_v[v] < best_ms) {
+      best_ms = ms_v[v];
       *best = v;
     }
   }
+  if (*best < 0) *best = 0;
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (e != hipSuccess) return fail(CHEMORA_EDEVICE, "tuning: %s", hipGetErrorString(e));

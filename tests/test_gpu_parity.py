@@ -237,6 +237,28 @@ def test_gauge_wave_harmonic_periodic(torch_cuda):
     assert_parity(got, ref, grid, 1e-12, "gauge wave 16 steps")
 
 
+@pytest.mark.parametrize("order,ghost,n", [(8, 5, (21, 14, 11)), (4, 3, (19, 12, 9))])
+def test_periodic_ragged_steps_against_oracle(torch_cuda, order, ghost, n):
+    """Periodic boundaries on ragged, odd extents (every ghost row kind of the
+    ghost kernel: whole y/z ghost rows, x ghosts of interior rows, 2g = 6 and
+    10): RK4 steps against the oracle, and the ghosts hold the periodic
+    images of the interior, bitwise."""
+    grid = I.centred_grid(n, ghost, 0.25)
+    p = I.config_params(order, 1, ghost, ghost, I.BC_PERIODIC)
+    u = I.flat(grid)
+    I.add_sinusoids(u, grid, np.random.default_rng(1312), 1e-3, range(I.NGF))
+    dt = 0.25 * grid.h
+    say(f"periodic ragged order {order} n={n}")
+    got = gpu_rk4(torch_cuda, p, grid, u, dt, 3)
+    ref = oracle.rk4(p, grid, u, dt, 3, nthreads=NTHREADS)
+    assert_parity(got, ref, grid, 1e-10, f"periodic ragged order {order}")
+    core = got[(slice(None),) + grid.interior()]
+    ext = core
+    for a in (1, 2, 3):
+        ext = np.take(ext, np.arange(-ghost, n[3 - a] + ghost) % n[3 - a], axis=a)
+    assert np.array_equal(got[:, :, :, : grid.ext[0]], ext)
+
+
 def test_check_finite(torch_cuda):
     from paper_1307_6488_amd import chemora as C
     w = I.workload(2, n_override=12)
