@@ -36,12 +36,17 @@ RK4_FLOPS = 24 * 14
 # the bench reports traffic as null.
 MEASURED_TRAFFIC = {
     "brill-lindquist-128^3-o4-upwind": {
-        "sources_sha256": "12d5a19ebc3504663b3bdc5b330d41ba1b48863ee423e77271e90e098ba3dc5c",
+        "sources_sha256": "9e12ed2eb00d58c3fc699c6a3bbc69b9771d83f5907b526e1101e65cfbb220b6",
         "tile": "32x16",
         "fetch_kib": 1.2218e6, "write_kib": 8.6130e5, "fetch_scale": 2.0, "write_scale": 1.0,
     },
+    "brill-lindquist-pert-192^3-o8-upwind": {
+        "sources_sha256": "9e12ed2eb00d58c3fc699c6a3bbc69b9771d83f5907b526e1101e65cfbb220b6",
+        "tile": "32x8",
+        "fetch_kib": 5.9608e6, "write_kib": 2.7175e6, "fetch_scale": 2.0, "write_scale": 1.0,
+    },
 }
-KERNEL_SOURCES = ["stage_kernel.hpp", "stage_common.hpp", "fd_ops.hpp", "stage_o4.hip"]
+KERNEL_SOURCES = ["stage_kernel.hpp", "stage_common.hpp", "fd_ops.hpp", "stage_o4.hip", "stage_o8.hip"]
 
 
 def kernel_sources_sha256():
