@@ -158,10 +158,10 @@ int chemora_hamiltonian(const chemora_params *params, const chemora_patch *patch
  * kept per size class -- (GPU architecture, fd_order, upwind, staged reach,
  * precision, bucket of n[0]: <=32 <=64 <=96 <=128 >128, bucket of n[1]:
  * <=16 <=32 <=64 >64) -- in a process-wide table (thread-safe) that every
- * call and plan consults; a class without an entry uses variant 2 (order 4)
- * or 0 (order 8).  The
- * paper tunes tile shapes with a model (section "Tile Size Selection"); here
- * they are timed on the target GPU, as its autotuning sections describe. */
+ * call and plan consults; a class without an entry uses variant 2 (32 x 8).
+ * The paper tunes tile shapes with a model (section "Tile Size Selection");
+ * here they are timed on the target GPU, as its autotuning sections
+ * describe. */
 
 /* Chooses the variant for patch's class: an entry already in the table (set,
  * tuned or loaded) is kept; otherwise every built variant is timed on RK4

@@ -271,10 +271,11 @@ std::string class_key(const chemora_params* P, const chemora_patch* X) {
   return buf;
 }
 
-// Variant of a class nobody tuned or set: 32 x 8 for order 4 (fastest in
-// most classes measured on MI355X, 64^3-128^3 and the 24-96 patches alike),
-// 64 x 4 for order 8.
-int default_variant(const chemora_params* P) { return P->fd_order == 4 ? 2 : 0; }
+// Variant of a class nobody tuned or set: 32 x 8 for both orders (order 4:
+// within 3 % of the fastest, 32 x 16, at 128^3 and 256^3 and without its
+// ragged-tile waste on small patches; order 8: fastest at 192^3, 6.4 ms per
+// stage-2 launch against 7.2 ms for 64 x 4, measured on MI355X).
+int default_variant(const chemora_params*) { return 2; }
 
 int choose_variant(const chemora_params* P, const chemora_patch* X) {
   const std::string key = class_key(P, X);
