@@ -1,4 +1,4 @@
-"""CPU FP64 oracle for the BSSN right-hand side and RK4 step.
+"""CPU FP64 oracle for the BSSN right-hand side and the RK4 and RK3 steps.
 
 TEST INFRASTRUCTURE ONLY.  Loaded by the test suite, the smoke check and the
 benchmark's CPU-baseline leg; the HIP library and its Python binding never
@@ -56,6 +56,7 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         L.oracle_rhs.argtypes = [P, G, dp, dp]
         L.oracle_rk4.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
+        L.oracle_rk3.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_rhs_ext.argtypes = [P, G, dp, dp]
         L.oracle_rk4_ext.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_fill_periodic.argtypes = [G, dp]
@@ -104,6 +105,15 @@ def rk4(params, grid, u: np.ndarray, dt: float, nsteps: int = 1, nthreads: int =
     v = np.ascontiguousarray(u.copy())
     _ok(lib().oracle_rk4(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), dt, nsteps,
                          _ptr(v)), "rk4")
+    return v
+
+
+def rk3(params, grid, u: np.ndarray, dt: float, nsteps: int = 1, nthreads: int = 0) -> np.ndarray:
+    """Return a copy of u advanced by nsteps third-order SSP Runge-Kutta
+    (Shu-Osher) steps."""
+    v = np.ascontiguousarray(u.copy())
+    _ok(lib().oracle_rk3(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), dt, nsteps,
+                         _ptr(v)), "rk3")
     return v
 
 

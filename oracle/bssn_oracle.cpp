@@ -1,4 +1,5 @@
-// bssn_oracle.cpp -- CPU reference of the BSSN right-hand side and RK4 step.
+// bssn_oracle.cpp -- CPU reference of the BSSN right-hand side and the RK4
+// and RK3 steps.
 //
 // TEST INFRASTRUCTURE ONLY.  This is the plain, slow, FP64 oracle that the HIP
 // library is checked against.  Only the test suite, the smoke check and the
@@ -8,11 +9,12 @@
 // What it computes (Chemora, arXiv:1307.6488): the paper's showcase is the
 // McLachlan BSSN evolution code -- the Einstein equations in BSSN form with
 // high-order finite differences (section "Scientific Motivation"), 8th-order
-// partially upwinded stencils needing 5 ghost zones and a Runge-Kutta time
-// integrator (section "Binary Black Hole Simulations", timer table: RHS
-// derivatives / advection / evaluations, boundary condition, time-integrator
-// copy).  The paper cites but does not print the equations; they are taken
-// here from the formulation it cites (Nakamura 1987; Shibata & Nakamura 1995;
+// partially upwinded stencils needing 5 ghost zones and a third-order
+// Runge-Kutta time integrator (section "Binary Black Hole Simulations", timer
+// table: RHS derivatives / advection / evaluations, boundary condition,
+// time-integrator copy); the classic RK4 step is here too.  The paper cites
+// but does not print the equations; they are taken here from the
+// formulation it cites (Nakamura 1987; Shibata & Nakamura 1995;
 // Baumgarte & Shapiro 1998; Alcubierre et al. 1999/2003), in the chi variant
 // with 1+log slicing and the advective Gamma-driver shift used by moving-
 // puncture codes, plus Kreiss-Oliger dissipation (Kreiss & Oliger 1973).
@@ -662,6 +664,48 @@ void rk4(const oracle_params& P, const oracle_grid& g, double dt_in, int nsteps,
   }
 }
 
+// nsteps third-order Runge-Kutta steps, u advanced in place: the strong
+// stability preserving scheme of Shu and Osher (1988), each stage a convex
+// combination of u_n and a forward-Euler step of the previous stage:
+//   u1      = u_n + dt L(u_n)
+//   u2      = 3/4 u_n + 1/4 (u1 + dt L(u1))
+//   u_{n+1} = 1/3 u_n + 2/3 (u2 + dt L(u2))
+// Stage inputs take their ghosts from u (static) or periodic images.
+template <class T>
+void rk3(const oracle_params& P, const oracle_grid& g, double dt_in, int nsteps, T* u) {
+  const size_t N = (size_t)g.sf * NGF;
+  const T dt = T(dt_in), three = T(3.0), four = T(4.0), one = T(1.0), two = T(2.0);
+  const T a2 = three / four, b2 = one / four, a3 = one / three, b3 = two / three;
+  std::vector<T> k(N, T(0.0)), s1(u, u + N), s2(u, u + N);
+  for (int step = 0; step < nsteps; ++step) {
+    std::copy(u, u + N, s1.begin());   // ghosts of the stage inputs
+    std::copy(u, u + N, s2.begin());
+    rhs_grid<T>(P, g, u, k.data());
+    axpy_interior<T>(g, u, dt, k.data(), s1.data());
+    if (P.bc == 1) fill_periodic<T>(g, s1.data());
+    rhs_grid<T>(P, g, s1.data(), k.data());
+#pragma omp parallel for schedule(static)
+    for (int kz = 0; kz < g.n[2]; ++kz)
+      for (int f = 0; f < NGF; ++f)
+        for (int j = 0; j < g.n[1]; ++j)
+          for (int i = 0; i < g.n[0]; ++i) {
+            const long idx = f * g.sf + at(g, i, j, kz);
+            s2[idx] = a2 * u[idx] + b2 * (s1[idx] + dt * k[idx]);
+          }
+    if (P.bc == 1) fill_periodic<T>(g, s2.data());
+    rhs_grid<T>(P, g, s2.data(), k.data());
+#pragma omp parallel for schedule(static)
+    for (int kz = 0; kz < g.n[2]; ++kz)
+      for (int f = 0; f < NGF; ++f)
+        for (int j = 0; j < g.n[1]; ++j)
+          for (int i = 0; i < g.n[0]; ++i) {
+            const long idx = f * g.sf + at(g, i, j, kz);
+            u[idx] = a3 * u[idx] + b3 * (s2[idx] + dt * k[idx]);
+          }
+    if (P.bc == 1) fill_periodic<T>(g, u);
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -686,6 +730,14 @@ int oracle_rk4(const oracle_params* P, const oracle_grid* g, double dt, int nste
   if (check(P, g) || !u || !(dt > 0.0) || nsteps < 0) return -1;
   set_threads(P);
   rk4<double>(*P, *g, dt, nsteps, u);
+  return 0;
+}
+
+// nsteps third-order SSP Runge-Kutta steps (Shu-Osher), u advanced in place.
+int oracle_rk3(const oracle_params* P, const oracle_grid* g, double dt, int nsteps, double* u) {
+  if (check(P, g) || !u || !(dt > 0.0) || nsteps < 0) return -1;
+  set_threads(P);
+  rk3<double>(*P, *g, dt, nsteps, u);
   return 0;
 }
 
