@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="run the untuned default tile variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-patch batched form")
     ap.add_argument("--no-split", action="store_true", help="skip the 256^3 split-precision comparison")
+    ap.add_argument("--no-rk3", action="store_true", help="skip the third-order Runge-Kutta form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -219,6 +220,8 @@ def main():
                                "min": float(np.min(reps)), "max": float(np.max(reps))},
         "host_wall_s": wall,
     }
+    if not args.no_rk3:
+        out["rk3"] = rk3_form(C, I, torch, w, u0)
     if not args.no_batched:
         del P, scratch
         torch.cuda.empty_cache()
@@ -254,6 +257,26 @@ def batched_form(C, I, torch, no_tune, steps=10, warmup=2):
     return {"workload": "64 patches, 24-96 points per edge, order 4 upwind (batched plan)", "patches": len(grids),
             "points": npts, "steps": steps, "ms_per_step": ms, "value": npts / (ms * 1e-3),
             "unit": "updates/s", "tile_variants": [f"{a}x{b}" for a, b in map(C.chemora_tile_variant_shape, variants)]}
+
+
+def rk3_form(C, I, torch, w, u0, steps=20, warmup=2):
+    """The paper's integrator: third-order SSP Runge-Kutta steps (3 stage
+    launches, 8 state transfers per point) on the same workload and data,
+    tile variant as tuned for it; a step advances by the same dt."""
+    P = C.Patch(w.params, w.grid, u0)
+    P.rk3_step(w.dt, warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    P.rk3_step(w.dt, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    npts = w.grid.npoints
+    return {"workload": w.name, "integrator": "SSP RK3 (Shu-Osher)", "steps": steps, "ms_per_step": ms,
+            "value": npts / (ms * 1e-3), "unit": "updates/s", "algorithmic_bytes_per_update": 8 * 24 * 8,
+            "hbm_frac": npts / (ms * 1e-3) * 8 * 24 * 8 / (HBM_PEAK_GBS * 1e9)}
 
 
 def split_form(C, I, torch, no_tune, steps=20, warmup=2):

@@ -139,6 +139,22 @@ int chemora_rk4_step(const chemora_params *params, const chemora_patch *patch, d
 int chemora_rk4_stage(const chemora_params *params, const chemora_patch *patch, int stage, double dt,
                       double *scratch, void *stream);
 
+/* Number of doubles of caller-provided scratch rk3_step needs: 2*24*sf (two
+ * stage buffers). */
+size_t chemora_rk3_scratch_elems(const chemora_patch *patch);
+
+/* One third-order Runge-Kutta step of size dt > 0 applied to patch->u in
+ * place -- the integrator of the paper's production runs (section "Binary
+ * Black Hole Simulations"), taken as the strong-stability-preserving scheme
+ * of Shu and Osher: S_A = u + dt k(u); S_B = 3/4 u + 1/4 S_A + dt/4 k(S_A);
+ * u = 1/3 u + 2/3 S_B + 2dt/3 k(S_B).  Three launches, 8 state transfers per
+ * point instead of RK4's 16.  Boundaries, scratch (at least
+ * chemora_rk3_scratch_elems(patch) doubles, not overlapping u; content on
+ * entry ignored, on return unspecified), tile variant and errors as for
+ * chemora_rk4_step. */
+int chemora_rk3_step(const chemora_params *params, const chemora_patch *patch, double dt,
+                     double *scratch, void *stream);
+
 /* Hamiltonian constraint H = chi gt^ij R_ij + 2/3 K^2 - At_ij At^ij of the
  * state at every interior point (a diagnostic, not part of the step; the
  * paper's BBH runs monitor the constraints, section "Binary Black Hole

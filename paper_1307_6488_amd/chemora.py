@@ -25,7 +25,7 @@ EXPORTS = (
     "chemora_rk4_stage", "chemora_check_finite", "chemora_last_error", "chemora_abi_version",
     "chemora_plan_create", "chemora_batch_step", "chemora_plan_points", "chemora_plan_destroy",
     "chemora_plan_patch_variant", "chemora_tune", "chemora_tile_variant", "chemora_set_tile_variant",
-    "chemora_tile_variant_shape", "chemora_hamiltonian",
+    "chemora_tile_variant_shape", "chemora_hamiltonian", "chemora_rk3_scratch_elems", "chemora_rk3_step",
 )
 
 
@@ -68,6 +68,10 @@ def lib() -> ctypes.CDLL:
         L.chemora_rk4_step.restype = ctypes.c_int
         L.chemora_rk4_stage.argtypes = [P, X, ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
         L.chemora_rk4_stage.restype = ctypes.c_int
+        L.chemora_rk3_scratch_elems.argtypes = [X]
+        L.chemora_rk3_scratch_elems.restype = ctypes.c_size_t
+        L.chemora_rk3_step.argtypes = [P, X, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+        L.chemora_rk3_step.restype = ctypes.c_int
         L.chemora_check_finite.argtypes = [P, X, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
         L.chemora_check_finite.restype = ctypes.c_int
         L.chemora_last_error.argtypes = []
@@ -157,6 +161,16 @@ def chemora_rk4_scratch_elems(patch: chemora_patch) -> int:
 def chemora_rk4_step(params: chemora_params, patch: chemora_patch, dt: float, scratch_ptr: int,
                      stream=None) -> int:
     return _check(lib().chemora_rk4_step(ctypes.byref(params), ctypes.byref(patch), dt,
+                                         ctypes.c_void_p(scratch_ptr), _stream(stream)))
+
+
+def chemora_rk3_scratch_elems(patch: chemora_patch) -> int:
+    return int(lib().chemora_rk3_scratch_elems(ctypes.byref(patch)))
+
+
+def chemora_rk3_step(params: chemora_params, patch: chemora_patch, dt: float, scratch_ptr: int,
+                     stream=None) -> int:
+    return _check(lib().chemora_rk3_step(ctypes.byref(params), ctypes.byref(patch), dt,
                                          ctypes.c_void_p(scratch_ptr), _stream(stream)))
 
 
@@ -291,6 +305,15 @@ class Patch:
         sc = self.scratch().data_ptr()
         for _ in range(nsteps):
             chemora_rk4_step(self.params, self.patch, dt, sc, s)
+        return self.u
+
+    def rk3_step(self, dt: float, nsteps: int = 1, stream=None):
+        """Third-order SSP Runge-Kutta steps (the RK4 scratch is large enough)."""
+        import torch
+        s = stream or torch.cuda.current_stream()
+        sc = self.scratch().data_ptr()
+        for _ in range(nsteps):
+            chemora_rk3_step(self.params, self.patch, dt, sc, s)
         return self.u
 
 

@@ -430,16 +430,21 @@ int chemora_hamiltonian(const chemora_params* params, const chemora_patch* patch
 
 namespace {
 
-int rk4_checks(const chemora_params* params, const chemora_patch* patch, double dt, double* scratch) {
+// checks of a Runge-Kutta call whose scratch holds nstates states
+int rk_checks(const chemora_params* params, const chemora_patch* patch, double dt, double* scratch, int nstates) {
   int rc = validate(params, patch);
   if (rc) return rc;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CHEMORA_EINVAL, "dt must be finite and > 0");
   if (!scratch) return fail(CHEMORA_EINVAL, "scratch is NULL");
   if (((uintptr_t)scratch) % 8) return fail(CHEMORA_EINVAL, "scratch not 8-byte aligned");
   const size_t state = (size_t)CHEMORA_NGF * patch->sf;
-  if (overlap(scratch, 3 * state * sizeof(double), patch->u, state * sizeof(double)))
+  if (overlap(scratch, nstates * state * sizeof(double), patch->u, state * sizeof(double)))
     return fail(CHEMORA_EINVAL, "scratch overlaps patch.u");
   return CHEMORA_OK;
+}
+
+int rk4_checks(const chemora_params* params, const chemora_patch* patch, double dt, double* scratch) {
+  return rk_checks(params, patch, dt, scratch, 3);
 }
 
 // Arguments of RK4 stage `stage` (1-4).  Buffers: u = u_n (overwritten by
@@ -470,6 +475,32 @@ double* stage_args(chemora::StageArgs& a, int stage, double dt, double* u, doubl
   }
 }
 
+// Arguments of stage `stage` (1-3) of the third-order strong-stability-
+// preserving Runge-Kutta scheme of Shu and Osher.  Buffers: u = u_n
+// (overwritten by stage 3, each point read and written by its own
+// work-item only), SA/SB stage inputs.
+//   1: SA = u + dt k(u)
+//   2: SB = 3/4 u + 1/4 SA + dt/4 k(SA)
+//   3: u  = 1/3 u + 2/3 SB + 2 dt/3 k(SB)
+// Returns the buffer the stage writes.
+double* rk3_stage_args(chemora::StageArgs& a, int stage, double dt, double* u, double* SA, double* SB) {
+  a.mode = chemora::MODE_RK3;
+  a.un = u;
+  switch (stage) {
+    case 1:
+      a.in = u; a.yin = u; a.out = SA; a.cu = 1.0; a.cyo = 0.0; a.cs = dt;
+      break;
+    case 2:
+      a.in = SA; a.yin = SA; a.out = SB; a.cu = 0.75; a.cyo = 0.25; a.cs = 0.25 * dt;
+      break;
+    default:
+      a.in = SB; a.yin = SB; a.out = u; a.cu = 1.0 / 3.0; a.cyo = 2.0 / 3.0; a.cs = dt * (2.0 / 3.0);
+      break;
+  }
+  a.y = a.out;   // not written in this mode
+  return a.out;
+}
+
 int rk4_stage(const chemora_params* params, const chemora_patch* patch, int stage, double dt, double* scratch,
               hipStream_t s) {
   if (stage < 1 || stage > 4) return fail(CHEMORA_EINVAL, "stage %d not in 1..4", stage);
@@ -498,6 +529,34 @@ int chemora_rk4_step(const chemora_params* params, const chemora_patch* patch, d
   if (rc) return rc;
   for (int st = 1; st <= 4; ++st)
     if ((rc = rk4_stage(params, patch, st, dt, scratch, (hipStream_t)stream))) return rc;
+  return CHEMORA_OK;
+}
+
+size_t chemora_rk3_scratch_elems(const chemora_patch* patch) {
+  if (!patch || patch->sf <= 0) return 0;
+  return (size_t)2 * CHEMORA_NGF * (size_t)patch->sf;
+}
+
+int chemora_rk3_step(const chemora_params* params, const chemora_patch* patch, double dt, double* scratch,
+                     void* stream) {
+  g_error.clear();
+  int rc = rk_checks(params, patch, dt, scratch, 2);
+  if (rc) return rc;
+  const size_t state = (size_t)CHEMORA_NGF * patch->sf;
+  double* u = patch->u;
+  double* SA = scratch;
+  double* SB = scratch + state;
+  hipStream_t s = (hipStream_t)stream;
+  const bool periodic = params->bc == CHEMORA_BC_PERIODIC;
+  const int v = choose_variant(params, patch);
+  for (int st = 1; st <= 3; ++st) {
+    chemora::StageArgs a = base_args(params, patch);
+    if (st == 1 && !periodic) launch_ghosts(false, a.geo, u, SA, SB, s);
+    double* written = rk3_stage_args(a, st, dt, u, SA, SB);
+    dispatch_stage(params, a, v, s);
+    if (periodic) launch_ghosts(true, a.geo, nullptr, written, nullptr, s);
+    if ((rc = check_launch("rk3 stage"))) return rc;
+  }
   return CHEMORA_OK;
 }
 

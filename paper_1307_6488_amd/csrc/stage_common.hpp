@@ -48,15 +48,16 @@ struct Scales {
 // it stores the Hamiltonian constraint into out, one GF with the patch's
 // strides, instead), with
 // Y = yin[point] and U = un[point] read at every point in every mode, and
-// out = cu U + cs k formed as fma(cs, k, cu U):
-//   RHS     out = k                             (cu = 0, cs = 1)
-//   STAGE1  y = Y + cy k,   out = U + cs k      (yin = un = u_n)
-//   STAGE23 y = Y + cy k,   out = U + cs k      (yin = y, un = u_n)
-//   STAGE4  out = U + cs k                      (un = yin = accumulator, cs = cy)
+// out = cu U + cyo Y + cs k formed as fma(cs, k, fma(cyo, Y, cu U)):
+//   RHS     out = k                             (cu = cyo = 0, cs = 1)
+//   STAGE1  y = Y + cy k,   out = U + cs k      (yin = un = u_n; RK4)
+//   STAGE23 y = Y + cy k,   out = U + cs k      (yin = y, un = u_n; RK4)
+//   STAGE4  out = U + cs k                      (un = yin = accumulator, cs = cy; RK4)
+//   RK3     out = cu U + cyo Y + cs k           (un = u_n, yin = the stage input; RK3)
 // Pointers a mode does not need are set to an array the stage reads anyway
 // (in / u_n / the accumulator), so the unconditional reads cost no HBM
 // traffic and keep the kernel free of mode-dependent loads.
-enum Mode : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE23 = 2, MODE_STAGE4 = 4, MODE_HAM = 8 };
+enum Mode : int { MODE_RHS = 0, MODE_STAGE1 = 1, MODE_STAGE23 = 2, MODE_STAGE4 = 4, MODE_HAM = 8, MODE_RK3 = 16 };
 
 struct StageArgs {
   const double* __restrict__ in;   // stencil input of this stage
@@ -70,6 +71,7 @@ struct StageArgs {
   double cy;                       // weight of k in the accumulator update
   double cs;                       // weight of k in out
   double cu;                       // weight of U in out (0 for the bare right-hand side)
+  double cyo;                      // weight of Y in out (RK3 stages 2 and 3, else 0)
   double chi_split;                // split precision: FP64 chi phase where chi < chi_split
   int tiles_x, tiles_y;            // tile grid of the launch's tile variant
   int mode;                        // a Mode

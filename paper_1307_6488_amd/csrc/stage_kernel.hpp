@@ -470,7 +470,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     return Epi{bload(ryin, vpt, so), bload(run, vpt, so)};
   };
   // the right-hand side k arrives in T and is combined in FP64; every mode
-  // but HAM stores out = fma(cs, k, cu U), stages 1-3 also the accumulator
+  // but HAM stores out = fma(cs, k, fma(cyo, Y, cu U)), RK4 stages 1-3 also
+  // the accumulator
   const bool store_out = mode != MODE_HAM;
   const bool store_y = mode == MODE_STAGE1 || mode == MODE_STAGE23;
   auto emit = [&](int f, auto kt, const Epi& e) __attribute__((always_inline)) {
@@ -478,7 +479,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const double kf = double(kt);
     const unsigned so = spt + f * sf * 8u;
     if (store_y) bstore(state_rsrc(a.y, G.sf), vpt, so, e.y + a.cy * kf);
-    bstore(state_rsrc(a.out, G.sf), vpt, so, __builtin_fma(a.cs, kf, a.cu * e.u));
+    bstore(state_rsrc(a.out, G.sf), vpt, so, __builtin_fma(a.cs, kf, __builtin_fma(a.cyo, e.y, a.cu * e.u)));
   };
 
   // staging sequence: 24 phases (B only with the Gamma-driver shift)

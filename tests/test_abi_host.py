@@ -161,6 +161,28 @@ def test_rk4_argument_checks_on_host():
     assert C.lib().chemora_rk4_scratch_elems(None) == 0
 
 
+def test_rk3_argument_checks_on_host():
+    p, g = _good()
+    P = C.make_params(p)
+
+    def call(dt=0.01, scratch=FAKE + (1 << 34), u=FAKE, params=P):
+        X = C.make_patch(g, u)
+        return C.lib().chemora_rk3_step(ctypes.byref(params), ctypes.byref(X), dt, ctypes.c_void_p(scratch), None)
+    for dt in (0.0, -1.0, float("nan"), float("inf")):
+        assert call(dt=dt) == C.EINVAL
+    assert call(scratch=0) == C.EINVAL
+    assert call(scratch=FAKE + 4) == C.EINVAL                         # misaligned
+    state = 24 * g.sf * 8
+    assert call(scratch=FAKE - 2 * state + 8) == C.EINVAL            # second stage buffer overlaps u
+    assert "overlaps" in C.last_error()
+    bad = C.make_params(p)
+    bad.fd_order = 6
+    assert call(params=bad) == C.EINVAL
+    X = C.make_patch(g, FAKE)
+    assert C.chemora_rk3_scratch_elems(X) == 2 * 24 * g.sf
+    assert C.lib().chemora_rk3_scratch_elems(None) == 0
+
+
 def test_hamiltonian_argument_checks_on_host():
     p, g = _good()
     P, X = C.make_params(p), C.make_patch(g, FAKE)
