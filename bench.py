@@ -41,9 +41,9 @@ MEASURED_TRAFFIC = {
         "fetch_kib": 1.2088e6, "write_kib": 8.6133e5, "fetch_scale": 2.0, "write_scale": 1.0,
     },
     "brill-lindquist-pert-192^3-o8-upwind": {
-        "sources_sha256": "9e12ed2eb00d58c3fc699c6a3bbc69b9771d83f5907b526e1101e65cfbb220b6",
+        "sources_sha256": "312a881f16cf8ff2418f4ebba0b038188e442d6a8e6bd699065ac0836707352f",
         "tile": "32x8",
-        "fetch_kib": 5.9608e6, "write_kib": 2.7175e6, "fetch_scale": 2.0, "write_scale": 1.0,
+        "fetch_kib": 5.9353e6, "write_kib": 2.7165e6, "fetch_scale": 2.0, "write_scale": 1.0,
     },
 }
 KERNEL_SOURCES = ["stage_kernel.hpp", "stage_common.hpp", "fd_ops.hpp", "stage_o4.hip", "stage_o8.hip"]
