@@ -57,6 +57,7 @@ def lib():
         L.oracle_rhs.argtypes = [P, G, dp, dp]
         L.oracle_rk4.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_rk3.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
+        L.oracle_enforce_algebraic.argtypes = [P, G, dp]
         L.oracle_rhs_ext.argtypes = [P, G, dp, dp]
         L.oracle_rk4_ext.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_fill_periodic.argtypes = [G, dp]
@@ -114,6 +115,15 @@ def rk3(params, grid, u: np.ndarray, dt: float, nsteps: int = 1, nthreads: int =
     v = np.ascontiguousarray(u.copy())
     _ok(lib().oracle_rk3(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), dt, nsteps,
                          _ptr(v)), "rk3")
+    return v
+
+
+def enforce_algebraic(params, grid, u: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """Return a copy of u with det(gt) = 1 and gt^ij At_ij = 0 restored at
+    every interior point (periodic ghosts refilled)."""
+    v = np.ascontiguousarray(u.copy())
+    _ok(lib().oracle_enforce_algebraic(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)),
+                                       _ptr(v)), "enforce_algebraic")
     return v
 
 

@@ -798,6 +798,56 @@ int oracle_hamiltonian(const oracle_params* P, const oracle_grid* g, const doubl
   return 0;
 }
 
+// Algebraic constraints of the conformal variables: det(gt) = 1 and
+// gt^ij At_ij = 0.  They are restored (the usual practice of moving-puncture
+// BSSN codes; the paper does not spell it out) at every interior point by
+//   gt_ij <- gt_ij / det(gt)^(1/3),   At_ij <- At_ij - 1/3 gt_ij (gt^kl At_kl)
+// with gt and its inverse taken after the rescaling.  Periodic boundaries:
+// the ghosts are refilled with the images; static ghosts are left alone.
+int oracle_enforce_algebraic(const oracle_params* P, const oracle_grid* g, double* u) {
+  if (check(P, g) || !u) return -1;
+  set_threads(P);
+  const oracle_grid G = *g;
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < G.n[2]; ++k)
+    for (int j = 0; j < G.n[1]; ++j)
+      for (int i = 0; i < G.n[0]; ++i) {
+        const long idx = at(G, i, j, k);
+        double m[3][3], A[3][3];
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) {
+            m[a][b] = u[(GT + SYM[a][b]) * G.sf + idx];
+            A[a][b] = u[(AT + SYM[a][b]) * G.sf + idx];
+          }
+        const double det = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+                           m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+                           m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+        const double s = std::cbrt(det);
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) m[a][b] = m[a][b] / s;
+        // inverse of the rescaled metric: adjugate over its determinant
+        const double dn = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+                          m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+                          m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+        double inv[3][3];
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) {
+            const int a1 = (b + 1) % 3, a2 = (b + 2) % 3, b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+            inv[a][b] = (m[a1][b1] * m[a2][b2] - m[a1][b2] * m[a2][b1]) / dn;
+          }
+        double tr = 0.0;
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) tr = tr + inv[a][b] * A[a][b];
+        for (int a = 0; a < 3; ++a)
+          for (int b = a; b < 3; ++b) {
+            u[(GT + SYM[a][b]) * G.sf + idx] = m[a][b];
+            u[(AT + SYM[a][b]) * G.sf + idx] = A[a][b] - m[a][b] * tr / 3.0;
+          }
+      }
+  if (P->bc == 1) fill_periodic<double>(G, u);
+  return 0;
+}
+
 // Pointwise algebra with caller-supplied derivatives (d1: 24x3, d2: 24x6 in
 // slot order xx xy xz yy yz zz, adv and diss: 24).
 int oracle_rhs_point(const oracle_params* P, const double* u, const double* d1, const double* d2,
