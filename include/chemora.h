@@ -155,6 +155,16 @@ size_t chemora_rk3_scratch_elems(const chemora_patch *patch);
 int chemora_rk3_step(const chemora_params *params, const chemora_patch *patch, double dt,
                      double *scratch, void *stream);
 
+/* Restores the algebraic constraints of the conformal variables, det(gt) = 1
+ * and gt^ij At_ij = 0, at every interior point of patch->u in place:
+ * gt_ij <- gt_ij / det(gt)^(1/3), then At_ij <- At_ij - gt_ij (gt^kl At_kl) / 3
+ * with the rescaled metric.  Not part of the step (call it between steps, as
+ * moving-puncture codes do; the paper leaves it to the evolution code it
+ * accelerates).  Periodic BC: ghosts refilled with the images afterwards;
+ * static BC: ghosts untouched.  One launch, 12 reads and 12 writes per point.
+ * Errors as chemora_bssn_rhs. */
+int chemora_enforce_constraints(const chemora_params *params, const chemora_patch *patch, void *stream);
+
 /* Hamiltonian constraint H = chi gt^ij R_ij + 2/3 K^2 - At_ij At^ij of the
  * state at every interior point (a diagnostic, not part of the step; the
  * paper's BBH runs monitor the constraints, section "Binary Black Hole

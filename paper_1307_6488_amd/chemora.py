@@ -26,6 +26,7 @@ EXPORTS = (
     "chemora_plan_create", "chemora_batch_step", "chemora_plan_points", "chemora_plan_destroy",
     "chemora_plan_patch_variant", "chemora_tune", "chemora_tile_variant", "chemora_set_tile_variant",
     "chemora_tile_variant_shape", "chemora_hamiltonian", "chemora_rk3_scratch_elems", "chemora_rk3_step",
+    "chemora_enforce_constraints",
 )
 
 
@@ -72,6 +73,8 @@ def lib() -> ctypes.CDLL:
         L.chemora_rk3_scratch_elems.restype = ctypes.c_size_t
         L.chemora_rk3_step.argtypes = [P, X, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
         L.chemora_rk3_step.restype = ctypes.c_int
+        L.chemora_enforce_constraints.argtypes = [P, X, ctypes.c_void_p]
+        L.chemora_enforce_constraints.restype = ctypes.c_int
         L.chemora_check_finite.argtypes = [P, X, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
         L.chemora_check_finite.restype = ctypes.c_int
         L.chemora_last_error.argtypes = []
@@ -172,6 +175,10 @@ def chemora_rk3_step(params: chemora_params, patch: chemora_patch, dt: float, sc
                      stream=None) -> int:
     return _check(lib().chemora_rk3_step(ctypes.byref(params), ctypes.byref(patch), dt,
                                          ctypes.c_void_p(scratch_ptr), _stream(stream)))
+
+
+def chemora_enforce_constraints(params: chemora_params, patch: chemora_patch, stream=None) -> int:
+    return _check(lib().chemora_enforce_constraints(ctypes.byref(params), ctypes.byref(patch), _stream(stream)))
 
 
 def chemora_rk4_stage(params: chemora_params, patch: chemora_patch, stage: int, dt: float, scratch_ptr: int,
@@ -305,6 +312,12 @@ class Patch:
         sc = self.scratch().data_ptr()
         for _ in range(nsteps):
             chemora_rk4_step(self.params, self.patch, dt, sc, s)
+        return self.u
+
+    def enforce_constraints(self, stream=None):
+        """Restore det(gt) = 1 and gt^ij At_ij = 0 at every interior point."""
+        import torch
+        chemora_enforce_constraints(self.params, self.patch, stream or torch.cuda.current_stream())
         return self.u
 
     def rk3_step(self, dt: float, nsteps: int = 1, stream=None):

@@ -69,6 +69,40 @@ __global__ __launch_bounds__(GHOST_THREADS) void ghost_kernel(const double* __re
   }
 }
 
+// Algebraic constraints det(gt) = 1 and gt^ij At_ij = 0 restored at every
+// interior point, one work-item per point (64 x 4 work-groups, x fastest):
+// gt_ij <- gt_ij / det(gt)^(1/3), then At_ij <- At_ij - gt_ij tr / 3 with
+// tr = gt^kl At_kl of the rescaled metric (its inverse = adjugate / det).
+// 12 loads and 12 stores per point, coalesced along x.
+__global__ __launch_bounds__(256) void enforce_kernel(double* __restrict__ u, Geo G) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= G.nx || j >= G.ny) return;
+  const int64_t at = (int64_t)(k + G.g) * G.sz + (int64_t)(j + G.g) * G.sy + (i + G.g);
+  double m[6], A[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    m[s] = u[(gGT + s) * G.sf + at];
+    A[s] = u[(gAT + s) * G.sf + at];
+  }
+  // symmetric slots 0..5 = xx xy xz yy yz zz
+  const double det = m[0] * (m[3] * m[5] - m[4] * m[4]) - m[1] * (m[1] * m[5] - m[4] * m[2]) +
+                     m[2] * (m[1] * m[4] - m[3] * m[2]);
+  const double sc = cbrt(det);
+#pragma unroll
+  for (int s = 0; s < 6; ++s) m[s] = m[s] / sc;
+  const double c00 = m[3] * m[5] - m[4] * m[4], c01 = m[2] * m[4] - m[1] * m[5], c02 = m[1] * m[4] - m[2] * m[3];
+  const double c11 = m[0] * m[5] - m[2] * m[2], c12 = m[1] * m[2] - m[0] * m[4], c22 = m[0] * m[3] - m[1] * m[1];
+  const double dn = m[0] * c00 + m[1] * c01 + m[2] * c02;
+  const double tr = (c00 * A[0] + c11 * A[3] + c22 * A[5] + 2.0 * (c01 * A[1] + c02 * A[2] + c12 * A[4])) / dn;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    u[(gGT + s) * G.sf + at] = m[s];
+    u[(gAT + s) * G.sf + at] = A[s] - m[s] * tr / 3.0;
+  }
+}
+
 __global__ __launch_bounds__(256) void finite_kernel(const double* __restrict__ u, Geo G,
                                                      unsigned long long* count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -567,6 +601,18 @@ int chemora_rk4_stage(const chemora_params* params, const chemora_patch* patch, 
   if (rc) return rc;
   if (stage < 1 || stage > 4) return fail(CHEMORA_EINVAL, "stage %d not in 1..4", stage);
   return rk4_stage(params, patch, stage, dt, scratch, (hipStream_t)stream);
+}
+
+int chemora_enforce_constraints(const chemora_params* params, const chemora_patch* patch, void* stream) {
+  g_error.clear();
+  int rc = validate(params, patch);
+  if (rc) return rc;
+  const chemora::Geo G = make_geo(params, patch);
+  hipStream_t s = (hipStream_t)stream;
+  dim3 grid((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
+  hipLaunchKernelGGL(chemora::enforce_kernel, grid, dim3(64, 4), 0, s, patch->u, G);
+  if (params->bc == CHEMORA_BC_PERIODIC) launch_ghosts(true, G, nullptr, patch->u, nullptr, s);
+  return check_launch("enforce_constraints");
 }
 
 int chemora_check_finite(const chemora_params* params, const chemora_patch* patch, int64_t* bad_count,

@@ -183,6 +183,17 @@ def test_rk3_argument_checks_on_host():
     assert C.lib().chemora_rk3_scratch_elems(None) == 0
 
 
+def test_enforce_constraints_argument_checks_on_host():
+    p, g = _good()
+    bad = C.make_params(p)
+    bad.fd_order = 6
+    X = C.make_patch(g, FAKE)
+    assert C.lib().chemora_enforce_constraints(ctypes.byref(bad), ctypes.byref(X), None) == C.EINVAL
+    P = C.make_params(p)
+    X = C.make_patch(g, 0)
+    assert C.lib().chemora_enforce_constraints(ctypes.byref(P), ctypes.byref(X), None) == C.EINVAL
+
+
 def test_hamiltonian_argument_checks_on_host():
     p, g = _good()
     P, X = C.make_params(p), C.make_patch(g, FAKE)

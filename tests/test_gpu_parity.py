@@ -295,6 +295,47 @@ def test_rk3_steps_against_oracle(torch_cuda, case):
         assert np.array_equal(got[mask], u[mask])
 
 
+@pytest.mark.parametrize("bc", ["static", "periodic"])
+def test_enforce_constraints_against_oracle(torch_cuda, bc):
+    """Algebraic-constraint enforcement through the C ABI on random metrics
+    (within about 30 % of the identity, as conformal metrics are; nearly
+    singular ones would make det's rounding, not the kernel, decide) and
+    curvatures of a ragged patch: equal to the oracle's to rounding,
+    det(gt) = 1 by numpy's determinant; ghosts as the boundary says."""
+    from paper_1307_6488_amd.chemora import Patch
+    from test_oracle_constraints import _random_state
+    grid = I.Grid((37, 21, 9), 3, 0.25)
+    p = I.config_params(4, 1, 3, 3, I.BC_STATIC if bc == "static" else I.BC_PERIODIC)
+    u = _random_state(grid, seed=21, amp=0.1)
+    if bc == "periodic":
+        oracle.fill_periodic(grid, u)
+    say(f"enforce constraints {bc}")
+    P = Patch(p, grid, u)
+    P.enforce_constraints()
+    torch_cuda.cuda.synchronize()
+    got = P.u.cpu().numpy()
+    ref = oracle.enforce_algebraic(p, grid, u)
+    inner = (slice(None),) + grid.interior()
+    for f in range(24):
+        scale = max(float(np.max(np.abs(ref[f][inner[1:]]))), 1e-300)
+        err = float(np.max(np.abs(got[f][inner[1:]] - ref[f][inner[1:]]))) / scale
+        assert err <= 1e-14, (I.GF_NAMES[f], err)
+    g = np.stack([np.stack([got[(I.GT + [[0, 1, 2], [1, 3, 4], [2, 4, 5]][a][b],) + grid.interior()]
+                            for b in range(3)], -1) for a in range(3)], -2)
+    assert np.max(np.abs(np.linalg.det(g) - 1.0)) < 1e-14
+    if bc == "static":
+        mask = np.ones(grid.shape, dtype=bool)
+        mask[inner] = False
+        mask[:, :, :, grid.ext[0]:] = False
+        assert np.array_equal(got[mask], u[mask])
+    else:
+        gg, n = grid.ghost, grid.n
+        ext = got[inner]
+        for a in (1, 2, 3):
+            ext = np.take(ext, np.arange(-gg, n[3 - a] + gg) % n[3 - a], axis=a)
+        assert np.array_equal(got[:, :, :, : grid.ext[0]], ext)
+
+
 def test_check_finite(torch_cuda):
     from paper_1307_6488_amd import chemora as C
     w = I.workload(2, n_override=12)

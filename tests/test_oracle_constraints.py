@@ -16,11 +16,13 @@ from paper_1307_6488_amd import inputs as I
 SYM = [[0, 1, 2], [1, 3, 4], [2, 4, 5]]
 
 
-def _random_state(grid, seed=5):
+def _random_state(grid, seed=5, amp=0.25):
+    """Random symmetric positive metrics gt = s B B^T (B = 1 + amp N, s in
+    [0.5, 2]) and random symmetric At; K random too."""
     rng = np.random.default_rng(seed)
     u = I.flat(grid)
     nz, ny, nx = grid.shape[1], grid.shape[2], grid.ext[0]
-    B = np.eye(3) + 0.25 * rng.standard_normal((nz, ny, nx, 3, 3))
+    B = np.eye(3) + amp * rng.standard_normal((nz, ny, nx, 3, 3))
     gt = np.einsum("...ik,...jk->...ij", B, B) * rng.uniform(0.5, 2.0, (nz, ny, nx, 1, 1))
     At = rng.standard_normal((nz, ny, nx, 3, 3))
     At = 0.5 * (At + np.swapaxes(At, -1, -2))
