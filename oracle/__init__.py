@@ -58,6 +58,8 @@ def lib():
         L.oracle_rk4.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_rk3.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_enforce_algebraic.argtypes = [P, G, dp]
+        L.oracle_momentum.argtypes = [P, G, dp, dp]
+        L.oracle_mom_point.argtypes = [dp, dp, dp]
         L.oracle_rhs_ext.argtypes = [P, G, dp, dp]
         L.oracle_rk4_ext.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_fill_periodic.argtypes = [G, dp]
@@ -165,6 +167,22 @@ def rhs_point(params, u, d1, d2, adv, diss) -> np.ndarray:
     assert arrs[0].size == NGF and arrs[1].size == NGF * 3 and arrs[2].size == NGF * 6
     out = np.zeros(NGF)
     _ok(lib().oracle_rhs_point(ctypes.byref(_params(params)), *[_ptr(a) for a in arrs], _ptr(out)), "rhs_point")
+    return out
+
+
+def momentum(params, grid, u: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """Momentum constraint M_i at interior points, shape (3, nz, ny, nx)."""
+    M = np.full((3,) + grid.shape[1:], np.nan)
+    _ok(lib().oracle_momentum(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), _ptr(u),
+                              _ptr(M)), "momentum")
+    return M[(slice(None),) + grid.interior()]
+
+
+def mom_point(u, d1) -> np.ndarray:
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (u, d1)]
+    assert arrs[0].size == NGF and arrs[1].size == NGF * 3
+    out = np.zeros(3)
+    _ok(lib().oracle_mom_point(*[_ptr(a) for a in arrs], _ptr(out)), "mom_point")
     return out
 
 

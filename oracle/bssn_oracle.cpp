@@ -519,6 +519,60 @@ bool needs_d2(int f) { return f == CHI || (f >= GT && f < GT + 6) || f == ALPHA 
 // ---------------------------------------------------------------------------
 // grid-point gather: every stencil the right-hand side needs at one point
 // ---------------------------------------------------------------------------
+// Momentum constraint, lower index, in the conformal variables:
+//   M_i = gt^jk (d_j At_ki - Gt^l_jk At_li - Gt^l_ji At_kl)
+//         - 3/(2 chi) gt^kl At_il d_k chi - 2/3 d_i K,
+// which is D_j K^j_i - d_i K of the physical metric gt/chi and curvature
+// (At + gt K/3)/chi when At is trace-free (conformal decomposition of the
+// ADM momentum constraint; first derivatives only).
+template <class R>
+void mom_point(const R u[NGF], const R d1[NGF][3], R M[3]) {
+  const R half = R(0.5), three_halves = R(3.0) / R(2.0), two_thirds = R(2.0) / R(3.0);
+  R g[3][3], At[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      g[i][j] = u[GT + SYM[i][j]];
+      At[i][j] = u[AT + SYM[i][j]];
+    }
+  R cof[3][3];
+  cof[0][0] = g[1][1] * g[2][2] - g[1][2] * g[2][1];
+  cof[0][1] = g[0][2] * g[2][1] - g[0][1] * g[2][2];
+  cof[0][2] = g[0][1] * g[1][2] - g[0][2] * g[1][1];
+  cof[1][1] = g[0][0] * g[2][2] - g[0][2] * g[2][0];
+  cof[1][2] = g[0][2] * g[1][0] - g[0][0] * g[1][2];
+  cof[2][2] = g[0][0] * g[1][1] - g[0][1] * g[1][0];
+  const R det = g[0][0] * cof[0][0] + g[0][1] * cof[0][1] + g[0][2] * cof[0][2];
+  R gu[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j) {
+      gu[i][j] = cof[i][j] / det;
+      gu[j][i] = gu[i][j];
+    }
+  // Gt^l_jk = 1/2 gt^lm (d_j gt_mk + d_k gt_mj - d_m gt_jk)
+  R Gam[3][3][3];
+  for (int l = 0; l < 3; ++l)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) {
+        R s = R(0.0);
+        for (int m = 0; m < 3; ++m)
+          s = s + gu[l][m] * (d1[GT + SYM[m][k]][j] + d1[GT + SYM[m][j]][k] - d1[GT + SYM[j][k]][m]);
+        Gam[l][j][k] = half * s;
+      }
+  const R chi = u[CHI];
+  for (int i = 0; i < 3; ++i) {
+    R s = R(0.0);
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) {
+        R t = d1[AT + SYM[k][i]][j];
+        for (int l = 0; l < 3; ++l) t = t - Gam[l][j][k] * At[l][i] - Gam[l][j][i] * At[k][l];
+        s = s + gu[j][k] * t;
+      }
+    for (int k = 0; k < 3; ++k)
+      for (int l = 0; l < 3; ++l) s = s - three_halves / chi * gu[k][l] * At[i][l] * d1[CHI][k];
+    M[i] = s - two_thirds * d1[TRK][i];
+  }
+}
+
 template <class R>
 struct Point {
   R u[NGF], d1[NGF][3], d2[NGF][6], adv[NGF], diss[NGF];
@@ -795,6 +849,45 @@ int oracle_hamiltonian(const oracle_params* P, const oracle_grid* g, const doubl
         H[idx] = ham_point<double>(pt.u, pt.d1, pt.d2);
       }
   }
+  return 0;
+}
+
+// Momentum constraint M_i (three grid functions with the patch's strides,
+// M[i * sf + idx]) at every interior point, from the centred first
+// derivatives of the patch's finite-difference order.
+int oracle_momentum(const oracle_params* P, const oracle_grid* g, const double* u, double* M) {
+  if (check(P, g) || !u || !M) return -1;
+  set_threads(P);
+  const Weights w = make_weights(P->fd_order);
+  const oracle_grid G = *g;
+  const long st[3] = {1, G.sy, G.sz};
+  const double inv_h = 1.0 / G.h;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k < G.n[2]; ++k) {
+    double v[NGF], d1[NGF][3];
+    for (int j = 0; j < G.n[1]; ++j)
+      for (int i = 0; i < G.n[0]; ++i) {
+        const long idx = at(G, i, j, k);
+        // first derivatives of every grid function (the right-hand side's
+        // gather skips those it does not need, At among them)
+        for (int f = 0; f < NGF; ++f) {
+          const double* q = u + f * G.sf + idx;
+          v[f] = q[0];
+          for (int a = 0; a < 3; ++a) d1[f][a] = op_d1<double>(q, st[a], w, inv_h);
+        }
+        double m[3];
+        mom_point<double>(v, d1, m);
+        for (int a = 0; a < 3; ++a) M[a * G.sf + idx] = m[a];
+      }
+  }
+  return 0;
+}
+
+int oracle_mom_point(const double* u, const double* d1, double* M) {
+  if (!u || !d1 || !M) return -1;
+  double D1[NGF][3];
+  std::memcpy(D1, d1, sizeof D1);
+  mom_point<double>(u, D1, M);
   return 0;
 }
 
