@@ -263,7 +263,8 @@ def batched_form(C, I, torch, no_tune, steps=10, warmup=2):
 def constraints_form(C, torch, P, calls=20):
     """Algebraic-constraint enforcement (det gt = 1, gt^ij At_ij = 0) on the
     evolved 128^3 state: one pointwise launch reading and writing the 12
-    conformal components, 192 algorithmic bytes per point."""
+    conformal components, 192 algorithmic bytes per point; and the
+    momentum-constraint diagnostic on the same state."""
     stream = torch.cuda.current_stream()
     C.chemora_enforce_constraints(P.params, P.patch, stream)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -276,8 +277,20 @@ def constraints_form(C, torch, P, calls=20):
     ms = e0.elapsed_time(e1) / calls
     npts = P.patch.n[0] * P.patch.n[1] * P.patch.n[2]
     gbs = npts * 192 / (ms * 1e-3) / 1e9
+    # the momentum-constraint diagnostic on the same state: reads chi, gt, K,
+    # At (14 grid functions, neighbours from L2) and writes 3: 136 B per point
+    M = torch.empty(3 * P.grid.sf, dtype=torch.float64, device=P.u.device)
+    C.chemora_momentum_constraint(P.params, P.patch, M.data_ptr(), stream)
+    e0.record(stream)
+    for _ in range(calls):
+        C.chemora_momentum_constraint(P.params, P.patch, M.data_ptr(), stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    msm = e0.elapsed_time(e1) / calls
     return {"kernel": "enforce_kernel", "calls": calls, "ms_per_call": ms, "bytes_per_point": 192,
-            "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+            "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+            "momentum": {"kernel": "momentum_kernel", "ms_per_call": msm, "bytes_per_point": 136,
+                         "achieved_gbs": npts * 136 / (msm * 1e-3) / 1e9}}
 
 
 def rk3_form(C, I, torch, w, u0, steps=20, warmup=2):

@@ -155,6 +155,18 @@ size_t chemora_rk3_scratch_elems(const chemora_patch *patch);
 int chemora_rk3_step(const chemora_params *params, const chemora_patch *patch, double dt,
                      double *scratch, void *stream);
 
+/* Momentum constraint M_i = gt^jk (d_j At_ki - Gt^l_jk At_li - Gt^l_ji At_kl)
+ * - 3/(2 chi) gt^kl At_il d_k chi - 2/3 d_i K of the state at every interior
+ * point -- the conformal form of the ADM momentum constraint, a diagnostic
+ * like the Hamiltonian constraint (the paper's BBH runs monitor the
+ * constraints, section "Binary Black Hole Simulations").  Centred first
+ * derivatives of the patch's order.  M holds three grid functions with the
+ * patch's strides (3 * patch.sf doubles, M_x at M[0 .. sf)); ghost entries
+ * are not written; M must not overlap the state.  Errors as
+ * chemora_bssn_rhs, EINVAL for a NULL, misaligned or overlapping M. */
+int chemora_momentum_constraint(const chemora_params *params, const chemora_patch *patch, double *M,
+                                void *stream);
+
 /* Restores the algebraic constraints of the conformal variables, det(gt) = 1
  * and gt^ij At_ij = 0, at every interior point of patch->u in place:
  * gt_ij <- gt_ij / det(gt)^(1/3), then At_ij <- At_ij - gt_ij (gt^kl At_kl) / 3

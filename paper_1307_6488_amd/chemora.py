@@ -26,7 +26,7 @@ EXPORTS = (
     "chemora_plan_create", "chemora_batch_step", "chemora_plan_points", "chemora_plan_destroy",
     "chemora_plan_patch_variant", "chemora_tune", "chemora_tile_variant", "chemora_set_tile_variant",
     "chemora_tile_variant_shape", "chemora_hamiltonian", "chemora_rk3_scratch_elems", "chemora_rk3_step",
-    "chemora_enforce_constraints",
+    "chemora_enforce_constraints", "chemora_momentum_constraint",
 )
 
 
@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
         L.chemora_rk3_step.restype = ctypes.c_int
         L.chemora_enforce_constraints.argtypes = [P, X, ctypes.c_void_p]
         L.chemora_enforce_constraints.restype = ctypes.c_int
+        L.chemora_momentum_constraint.argtypes = [P, X, ctypes.c_void_p, ctypes.c_void_p]
+        L.chemora_momentum_constraint.restype = ctypes.c_int
         L.chemora_check_finite.argtypes = [P, X, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
         L.chemora_check_finite.restype = ctypes.c_int
         L.chemora_last_error.argtypes = []
@@ -175,6 +177,11 @@ def chemora_rk3_step(params: chemora_params, patch: chemora_patch, dt: float, sc
                      stream=None) -> int:
     return _check(lib().chemora_rk3_step(ctypes.byref(params), ctypes.byref(patch), dt,
                                          ctypes.c_void_p(scratch_ptr), _stream(stream)))
+
+
+def chemora_momentum_constraint(params: chemora_params, patch: chemora_patch, M_ptr: int, stream=None) -> int:
+    return _check(lib().chemora_momentum_constraint(ctypes.byref(params), ctypes.byref(patch), ctypes.c_void_p(M_ptr),
+                                                    _stream(stream)))
 
 
 def chemora_enforce_constraints(params: chemora_params, patch: chemora_patch, stream=None) -> int:
@@ -300,6 +307,17 @@ class Patch:
         n = self.grid.n
         v = h[: self.grid.sz * (n[2] + 2 * g)].view(n[2] + 2 * g, n[1] + 2 * g, self.grid.sy)
         return v[g:g + n[2], g:g + n[1], g:g + n[0]]
+
+    def momentum_constraint(self, stream=None):
+        """M_i at the interior points, as a (3, nz, ny, nx) torch tensor view."""
+        import torch
+        m = torch.full((3 * self.grid.sf,), float("nan"), dtype=torch.float64, device=self.u.device)
+        chemora_momentum_constraint(self.params, self.patch, m.data_ptr(), stream or torch.cuda.current_stream())
+        g = self.grid.ghost
+        n = self.grid.n
+        v = m.view(3, self.grid.sf)[:, : self.grid.sz * (n[2] + 2 * g)].reshape(3, n[2] + 2 * g, n[1] + 2 * g,
+                                                                                  self.grid.sy)
+        return v[:, g:g + n[2], g:g + n[1], g:g + n[0]]
 
     def tune(self, cache_path=None, stream=None) -> int:
         import torch

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "chemora.h"
+#include "fd_ops.hpp"
 #include "stage_common.hpp"
 
 namespace chemora {
@@ -100,6 +101,81 @@ __global__ __launch_bounds__(256) void enforce_kernel(double* __restrict__ u, Ge
   for (int s = 0; s < 6; ++s) {
     u[(gGT + s) * G.sf + at] = m[s];
     u[(gAT + s) * G.sf + at] = A[s] - m[s] * tr / 3.0;
+  }
+}
+
+// Momentum constraint (a diagnostic, not part of the step), one work-item
+// per interior point (64 x 4 work-groups): centred first derivatives of chi,
+// gt, K and At read straight from the state (neighbours come from L2), then
+//   M_i = gt^jk (d_j At_ki - Gt^l_jk At_li - Gt^l_ji At_kl)
+//         - 3/(2 chi) gt^kl At_il d_k chi - 2/3 d_i K
+// stored as three grid functions M[i * sf + point].
+template <int ORDER>
+__global__ __launch_bounds__(256) void momentum_kernel(const double* __restrict__ u, double* __restrict__ M, Geo G,
+                                                       double d1s) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= G.nx || j >= G.ny) return;
+  const int64_t at = (int64_t)(k + G.g) * G.sz + (int64_t)(j + G.g) * G.sy + (i + G.g);
+  const int64_t st[3] = {1, G.sy, G.sz};
+  auto D = [&](int f, int a) {
+    const double* p = u + f * G.sf + at;
+    const int64_t s = st[a];
+    return Stencil<ORDER>::first([&](int o) { return p[o * s]; }) * d1s;
+  };
+  double g[6], A[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    g[q] = u[(gGT + q) * G.sf + at];
+    A[q] = u[(gAT + q) * G.sf + at];
+  }
+  const double chi = u[gCHI * G.sf + at];
+  const double c00 = g[3] * g[5] - g[4] * g[4], c01 = g[2] * g[4] - g[1] * g[5], c02 = g[1] * g[4] - g[2] * g[3];
+  const double c11 = g[0] * g[5] - g[2] * g[2], c12 = g[1] * g[2] - g[0] * g[4], c22 = g[0] * g[3] - g[1] * g[1];
+  const double idet = 1.0 / (g[0] * c00 + g[1] * c01 + g[2] * c02);
+  const double gu[6] = {c00 * idet, c01 * idet, c02 * idet, c11 * idet, c12 * idet, c22 * idet};
+  // Gt_{m,jk} = 1/2 (d_j gt_mk + d_k gt_mj - d_m gt_jk), then raised
+  double dg[3][6];
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) dg[m][q] = D(gGT + q, m);
+  double Gu[3][6];
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int jj = SI(q), kk = SJ(q);
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+        acc += gu[S(l, m)] * 0.5 * (dg[jj][S(m, kk)] + dg[kk][S(m, jj)] - dg[m][q]);
+      Gu[l][q] = acc;
+    }
+  double dchi[3], dK[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    dchi[a] = D(gCHI, a);
+    dK[a] = D(gK, a);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double acc = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) {
+        double t = D(gAT + S(kk, a), jj);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) t -= Gu[l][S(jj, kk)] * A[S(l, a)] + Gu[l][S(jj, a)] * A[S(kk, l)];
+        acc += gu[S(jj, kk)] * t;
+      }
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) acc -= 1.5 / chi * gu[S(kk, l)] * A[S(a, l)] * dchi[kk];
+    M[a * G.sf + at] = acc - (2.0 / 3.0) * dK[a];
   }
 }
 
@@ -601,6 +677,26 @@ int chemora_rk4_stage(const chemora_params* params, const chemora_patch* patch, 
   if (rc) return rc;
   if (stage < 1 || stage > 4) return fail(CHEMORA_EINVAL, "stage %d not in 1..4", stage);
   return rk4_stage(params, patch, stage, dt, scratch, (hipStream_t)stream);
+}
+
+int chemora_momentum_constraint(const chemora_params* params, const chemora_patch* patch, double* M,
+                                void* stream) {
+  g_error.clear();
+  int rc = validate(params, patch);
+  if (rc) return rc;
+  if (!M) return fail(CHEMORA_EINVAL, "M is NULL");
+  if (((uintptr_t)M) % 8) return fail(CHEMORA_EINVAL, "M not 8-byte aligned");
+  const size_t bytes = (size_t)CHEMORA_NGF * patch->sf * sizeof(double);
+  if (overlap(M, 3 * patch->sf * sizeof(double), patch->u, bytes)) return fail(CHEMORA_EINVAL, "M overlaps patch.u");
+  const chemora::Geo G = make_geo(params, patch);
+  const double d1s = 1.0 / ((params->fd_order == 8 ? 840.0 : 12.0) * patch->h);
+  hipStream_t s = (hipStream_t)stream;
+  dim3 grid((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
+  if (params->fd_order == 8)
+    hipLaunchKernelGGL(chemora::momentum_kernel<8>, grid, dim3(64, 4), 0, s, patch->u, M, G, d1s);
+  else
+    hipLaunchKernelGGL(chemora::momentum_kernel<4>, grid, dim3(64, 4), 0, s, patch->u, M, G, d1s);
+  return check_launch("momentum_constraint");
 }
 
 int chemora_enforce_constraints(const chemora_params* params, const chemora_patch* patch, void* stream) {

@@ -183,6 +183,19 @@ def test_rk3_argument_checks_on_host():
     assert C.lib().chemora_rk3_scratch_elems(None) == 0
 
 
+def test_momentum_constraint_argument_checks_on_host():
+    p, g = _good()
+    P = C.make_params(p)
+    X = C.make_patch(g, FAKE)
+
+    def call(M):
+        return C.lib().chemora_momentum_constraint(ctypes.byref(P), ctypes.byref(X), ctypes.c_void_p(M), None)
+    assert call(0) == C.EINVAL
+    assert call(FAKE + (1 << 34) + 4) == C.EINVAL                     # misaligned
+    assert call(FAKE + 8) == C.EINVAL                                  # overlaps u
+    assert "overlaps" in C.last_error()
+
+
 def test_enforce_constraints_argument_checks_on_host():
     p, g = _good()
     bad = C.make_params(p)
