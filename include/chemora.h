@@ -275,7 +275,9 @@ int chemora_check_finite(const chemora_params *params, const chemora_patch *patc
 /* Message of the last failed call on this thread ("" if none). */
 const char *chemora_last_error(void);
 
-/* ABI version of this header (major*100 + minor). */
+/* ABI version of this header (major*100 + minor): 101 (1.1 added
+ * chemora_rk3_step, chemora_rk3_scratch_elems, chemora_enforce_constraints
+ * and chemora_momentum_constraint; nothing of 1.0 changed). */
 int chemora_abi_version(void);
 
 #ifdef __cplusplus

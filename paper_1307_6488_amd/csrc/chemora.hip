@@ -489,7 +489,7 @@ void launch_ghosts(bool periodic, const chemora::Geo& G, const double* src, doub
 
 extern "C" {
 
-int chemora_abi_version(void) { return 100; }
+int chemora_abi_version(void) { return 101; }
 
 const char* chemora_last_error(void) { return g_error.c_str(); }
 

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     assert set(declared) == set(C.EXPORTS)
     for name in declared:
         assert hasattr(L, name), name
-    assert C.chemora_abi_version() == 100
+    assert C.chemora_abi_version() == 101
 
 
 def test_required_ghost_matches_inputs():
