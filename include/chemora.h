@@ -252,8 +252,16 @@ int chemora_plan_create(const chemora_params *params, const chemora_patch *patch
                         int32_t npatch, double courant, const char *tune_cache_path, void *stream,
                         chemora_plan **out);
 
-/* Advances every patch of the plan by nsteps RK4 steps (nsteps >= 0), by
- * replaying the captured graph on `stream`. */
+/* The same plan with the third-order SSP Runge-Kutta step of
+ * chemora_rk3_step captured instead of RK4 (3 launches per tile-variant
+ * group and step).  Arguments, scratch size (chemora_rk4_scratch_elems:
+ * the tuner uses all of it) and errors as chemora_plan_create. */
+int chemora_plan_create_rk3(const chemora_params *params, const chemora_patch *patches, double *const *scratch,
+                            int32_t npatch, double courant, const char *tune_cache_path, void *stream,
+                            chemora_plan **out);
+
+/* Advances every patch of the plan by nsteps steps of its integrator
+ * (nsteps >= 0), by replaying the captured graph on `stream`. */
 int chemora_batch_step(chemora_plan *plan, int32_t nsteps, void *stream);
 
 /* Total interior points of the plan's patches (0 for NULL). */
@@ -276,8 +284,9 @@ int chemora_check_finite(const chemora_params *params, const chemora_patch *patc
 const char *chemora_last_error(void);
 
 /* ABI version of this header (major*100 + minor): 101 (1.1 added
- * chemora_rk3_step, chemora_rk3_scratch_elems, chemora_enforce_constraints
- * and chemora_momentum_constraint; nothing of 1.0 changed). */
+ * chemora_rk3_step, chemora_rk3_scratch_elems, chemora_plan_create_rk3,
+ * chemora_enforce_constraints and chemora_momentum_constraint; nothing of
+ * 1.0 changed). */
 int chemora_abi_version(void);
 
 #ifdef __cplusplus

@@ -26,7 +26,7 @@ EXPORTS = (
     "chemora_plan_create", "chemora_batch_step", "chemora_plan_points", "chemora_plan_destroy",
     "chemora_plan_patch_variant", "chemora_tune", "chemora_tile_variant", "chemora_set_tile_variant",
     "chemora_tile_variant_shape", "chemora_hamiltonian", "chemora_rk3_scratch_elems", "chemora_rk3_step",
-    "chemora_enforce_constraints", "chemora_momentum_constraint",
+    "chemora_enforce_constraints", "chemora_momentum_constraint", "chemora_plan_create_rk3",
 )
 
 
@@ -84,6 +84,8 @@ def lib() -> ctypes.CDLL:
         L.chemora_plan_create.argtypes = [P, X, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_double,
                                           ctypes.c_char_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
         L.chemora_plan_create.restype = ctypes.c_int
+        L.chemora_plan_create_rk3.argtypes = L.chemora_plan_create.argtypes
+        L.chemora_plan_create_rk3.restype = ctypes.c_int
         L.chemora_batch_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
         L.chemora_batch_step.restype = ctypes.c_int
         L.chemora_plan_points.argtypes = [ctypes.c_void_p]
@@ -204,16 +206,17 @@ def chemora_check_finite(params: chemora_params, patch: chemora_patch, stream=No
 
 
 def chemora_plan_create(params: chemora_params, patches, scratch_ptrs, courant: float, tune_cache_path=None,
-                        stream=None) -> int:
+                        stream=None, rk3: bool = False) -> int:
     """Returns the opaque plan handle (an int).  patches: sequence of
-    chemora_patch; scratch_ptrs: device addresses, one per patch."""
+    chemora_patch; scratch_ptrs: device addresses, one per patch; rk3 selects
+    chemora_plan_create_rk3."""
     n = len(patches)
     arr = (chemora_patch * n)(*patches)
     sc = (ctypes.c_void_p * n)(*[ctypes.c_void_p(p) for p in scratch_ptrs])
     out = ctypes.c_void_p(0)
     path = tune_cache_path.encode() if tune_cache_path else None
-    _check(lib().chemora_plan_create(ctypes.byref(params), arr, sc, n, courant, path, _stream(stream),
-                                     ctypes.byref(out)))
+    fn = lib().chemora_plan_create_rk3 if rk3 else lib().chemora_plan_create
+    _check(fn(ctypes.byref(params), arr, sc, n, courant, path, _stream(stream), ctypes.byref(out)))
     return out.value
 
 
@@ -351,13 +354,16 @@ class Patch:
 class Batch:
     """Several device-resident patches advanced together through a plan."""
 
-    def __init__(self, params, grids, states, courant: float, device="cuda", tune_cache_path=None):
+    def __init__(self, params, grids, states, courant: float, device="cuda", tune_cache_path=None,
+                 integrator: str = "rk4"):
         import torch
+        if integrator not in ("rk4", "rk3"):
+            raise ValueError(f"integrator {integrator!r} is neither 'rk4' nor 'rk3'")
         self.patches = [Patch(params, g, s, device=device) for g, s in zip(grids, states)]
         self.params = make_params(params)
         scr = [p.scratch().data_ptr() for p in self.patches]
         self.plan = chemora_plan_create(self.params, [p.patch for p in self.patches], scr, courant,
-                                        tune_cache_path, torch.cuda.current_stream())
+                                        tune_cache_path, torch.cuda.current_stream(), rk3=integrator == "rk3")
 
     def variants(self):
         return [chemora_plan_patch_variant(self.plan, p) for p in range(len(self.patches))]

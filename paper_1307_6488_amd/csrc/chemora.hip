@@ -885,7 +885,7 @@ struct chemora_plan {
   int64_t points = 0;
   std::vector<PlanGroup> groups;
   std::vector<int> variant_of;                    // per patch (caller's order)
-  chemora::StageArgs* d_args = nullptr;           // 4 stage tables of npatch entries, group order
+  chemora::StageArgs* d_args = nullptr;           // 4 (RK4) or 3 (RK3) stage tables of npatch entries, group order
   int* d_tile_start = nullptr;
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
@@ -911,10 +911,16 @@ void plan_free(chemora_plan* pl) {
 
 extern "C" {
 
-int chemora_plan_create(const chemora_params* params, const chemora_patch* patches, double* const* scratch,
-                        int32_t npatch, double courant, const char* tune_cache_path, void* stream,
-                        chemora_plan** out) {
-  g_error.clear();
+}  // extern "C"
+
+namespace {
+
+// A plan capturing one step of RK4 (4 stages) or of the third-order SSP
+// scheme (3 stages); scratch holds 3 states per patch either way (the
+// tuner times RK4 stage-2 launches in it).
+int plan_create(const chemora_params* params, const chemora_patch* patches, double* const* scratch, int32_t npatch,
+                double courant, const char* tune_cache_path, void* stream, chemora_plan** out, bool rk3) {
+  const int nst = rk3 ? 3 : 4;
   if (!out) return fail(CHEMORA_EINVAL, "out is NULL");
   *out = nullptr;
   if (!patches || !scratch) return fail(CHEMORA_EINVAL, "patches or scratch is NULL");
@@ -955,7 +961,7 @@ int chemora_plan_create(const chemora_params* params, const chemora_patch* patch
   std::vector<int> order(npatch);
   for (int p = 0; p < npatch; ++p) order[p] = p;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return var[x] < var[y]; });
-  std::vector<chemora::StageArgs> args(4 * (size_t)npatch);
+  std::vector<chemora::StageArgs> args(nst * (size_t)npatch);
   std::vector<int> starts;
   for (int r = 0; r < npatch;) {
     PlanGroup g{var[order[r]], r, 0, 0, (int)starts.size()};
@@ -973,9 +979,12 @@ int chemora_plan_create(const chemora_params* params, const chemora_patch* patch
         return fail(CHEMORA_EINVAL, "too many tiles in the plan");
       }
       starts.push_back((int)tiles);
-      for (int st = 0; st < 4; ++st) {
+      for (int st = 0; st < nst; ++st) {
         chemora::StageArgs sa = a;
-        stage_args(sa, st + 1, courant * X->h, X->u, sc, sc + state, sc + 2 * state);
+        if (rk3)
+          rk3_stage_args(sa, st + 1, courant * X->h, X->u, sc, sc + state);
+        else
+          stage_args(sa, st + 1, courant * X->h, X->u, sc, sc + state, sc + 2 * state);
         args[st * (size_t)npatch + r] = sa;
       }
       ++g.count;
@@ -1015,7 +1024,7 @@ int chemora_plan_create(const chemora_params* params, const chemora_patch* patch
     return fail(CHEMORA_EDEVICE, "graph capture start: %s", hipGetErrorString(e));
   }
   const bool periodic = params->bc == CHEMORA_BC_PERIODIC;
-  for (int st = 0; st < 4; ++st) {
+  for (int st = 0; st < nst; ++st) {
     for (const PlanGroup& g : pl->groups) {
       chemora::BatchTable bt;
       bt.args = pl->d_args + st * (size_t)npatch + g.first;
@@ -1044,6 +1053,24 @@ int chemora_plan_create(const chemora_params* params, const chemora_patch* patch
   }
   *out = pl;
   return CHEMORA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chemora_plan_create(const chemora_params* params, const chemora_patch* patches, double* const* scratch,
+                        int32_t npatch, double courant, const char* tune_cache_path, void* stream,
+                        chemora_plan** out) {
+  g_error.clear();
+  return plan_create(params, patches, scratch, npatch, courant, tune_cache_path, stream, out, false);
+}
+
+int chemora_plan_create_rk3(const chemora_params* params, const chemora_patch* patches, double* const* scratch,
+                            int32_t npatch, double courant, const char* tune_cache_path, void* stream,
+                            chemora_plan** out) {
+  g_error.clear();
+  return plan_create(params, patches, scratch, npatch, courant, tune_cache_path, stream, out, true);
 }
 
 int chemora_plan_patch_variant(const chemora_plan* plan, int32_t p) {
