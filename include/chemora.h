@@ -2,7 +2,9 @@
  *
  * The library evaluates the right-hand side of the BSSN form of the Einstein
  * equations with high-order finite differences on a Cartesian patch, and
- * advances a patch by classic fourth-order Runge-Kutta steps (Chemora,
+ * advances a patch (or a batch of patches) by classic fourth-order or
+ * third-order SSP Runge-Kutta steps, with the Hamiltonian and momentum
+ * constraints as diagnostics and the algebraic constraints restorable (Chemora,
  * arXiv:1307.6488: the McLachlan BSSN evolution of section "Binary Black Hole
  * Simulations" -- derivative, advection and evaluation kernels, boundary
  * condition and time-integrator update -- and the per-point "numerical
@@ -22,8 +24,9 @@
  *    data_ptr()); the caller owns and keeps them alive until the work has
  *    completed on `stream`.  `stream` is a hipStream_t passed as void*
  *    (NULL = the default stream).  Work is enqueued asynchronously; only
- *    chemora_check_finite, chemora_tune, chemora_plan_create and
- *    chemora_plan_destroy synchronise (each says so).  Device faults
+ *    chemora_check_finite, chemora_tune, chemora_plan_create,
+ *    chemora_plan_create_rk3 and chemora_plan_destroy synchronise (each says
+ *    so).  Device faults
  *    surface at the caller's next synchronisation.
  *  - CHEMORA_EDEVICE reports a failed HIP launch/runtime call.
  *

@@ -1,5 +1,6 @@
-// chemora.hip -- gfx950 kernels and host ABI of the BSSN right-hand side and
-// RK4 step (see include/chemora.h for the contract).
+// chemora.hip -- gfx950 kernels and host ABI of the BSSN right-hand side, the
+// RK4 and third-order SSP steps, batched plans, the tuner and the constraint
+// kernels (see include/chemora.h for the contract).
 //
 // Stage kernel: one work-item per interior point.  It evaluates every
 // stencil the point needs straight from the stage input (the paper's
