@@ -13,7 +13,7 @@ reader of padding is caught.  Interior point (i, j, k), 0 <= i < nx, is stored
 at array index (i + g, j + g, k + g) and sits at ``origin + (i, j, k) * h``.
 
 Grid-function order (the paper counts the BSSN variables in its section
-"Scientific Motivation"; this build evolves the 24 of the moving-puncture
+"Scientific Motivation"; the library evolves the 24 of the moving-puncture
 chi-BSSN system):
 
     0 chi | 1-6 gt_xx gt_xy gt_xz gt_yy gt_yz gt_zz | 7 K |
