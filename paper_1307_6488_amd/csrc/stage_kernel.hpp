@@ -180,8 +180,9 @@ __device__ __forceinline__ void wait_staged(int m) {
 // cover a block that is deep in z and share their z halos in its L2.  Every
 // work-item of the work-group must call it (it synchronises); it ends with a
 // barrier, so the buffers may be reused right after.
-template <int ORDER, bool UPWIND, int R, int NB, bool BOUND, bool OFFS_LDS, class SH, typename T>
-__device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* const (&bufs)[NB], unsigned* offs) {
+template <int ORDER, bool UPWIND, int R, int NB, bool BOUND, bool OFFS_LDS, bool PARK, class SH, typename T>
+__device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* const (&bufs)[NB], unsigned* offs,
+                                           double* park) {
   // T: the arithmetic type of stencil combinations and algebra -- double, or
   // float for split precision (FP64 differences rounded to FP32, FP32
   // algebra, FP64 state, RK combination and near-puncture chi terms)
@@ -570,6 +571,21 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     sync(c);
   }
   const T divb = db[0][0] + db[1][1] + db[2][2];
+  // PARK: the Gt-source accumulators are not needed again before the K
+  // phase; parked in LDS (each lane its own slots, no barrier) they do not
+  // hold six registers through the metric phases, where pressure peaks
+  auto park_slot = [&](int q) __attribute__((always_inline)) {
+    int lin = wave * 64 + lane;
+    asm volatile("" : "+v"(lin));
+    return park + q * SH::NT + lin;
+  };
+  if constexpr (PARK) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      *park_slot(c) = double(xts[c]);
+      *park_slot(3 + c) = double(ddiv[c]);
+    }
+  }
 
   // ---- conformal metric (phases 3-8)
   T Ric[6];
@@ -846,6 +862,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) dK[ax] = D1(T(), src, ax);
     emit(gK, finish(T(), src, -chi * trDDa + alpha * (AA + K * K * (T(1.0) / T(3.0)))), e);
+    if constexpr (PARK) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        xts[c] = T(*park_slot(c));
+        ddiv[c] = T(*park_slot(3 + c));
+      }
+    }
     // Gt source, complete now
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -923,7 +946,10 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
   // (its 256 registers are otherwise exhausted); FP32 algebra needs ~156
   constexpr bool OFFS_LDS = OCC == 2 && sizeof(T) == 8;
   constexpr int WG_PER_CU = (OCC * 4) / WPG > 1 ? (OCC * 4) / WPG : 1;
-  static_assert(WG_PER_CU * (NB * L::SIZEP * 8 + (OFFS_LDS ? L::CPW * SH::NT * 4 : 0)) <= 160 * 1024, "LDS");
+  constexpr int LDS_BASE = NB * L::SIZEP * 8 + (OFFS_LDS ? L::CPW * SH::NT * 4 : 0);
+  static_assert(WG_PER_CU * LDS_BASE <= 160 * 1024, "LDS");
+  // order 4 at two waves per SIMD parks six accumulators in LDS where it fits
+  constexpr bool PARK = ORDER == 4 && OFFS_LDS && WG_PER_CU * (LDS_BASE + 6 * SH::NT * 8) <= 160 * 1024;
   // separate arrays, so the compiler can tell the buffers' staging loads apart
   __shared__ double b0[L::SIZEP];
   __shared__ double b1[L::SIZEP];
@@ -931,6 +957,7 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
   __shared__ double b3[NB > 3 ? L::SIZEP : 1];
   __shared__ double b4[NB > 4 ? L::SIZEP : 1];
   __shared__ unsigned offs[OFFS_LDS ? L::CPW * SH::NT : 1];
+  __shared__ double park[PARK ? 6 * SH::NT : 1];
   double* const all[5] = {b0, b1, b2, b3, b4};
   double* bufs[NB];
 #pragma unroll
@@ -942,7 +969,7 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
     a = uniform_args(bt.args + p);
     t -= uniform(bt.tile_start[p]);
   }
-  stage_tile<ORDER, UPWIND, R, NB, (ORDER >= 8 || OCC >= 2), OFFS_LDS, SH, T>(a, t, bufs, offs);
+  stage_tile<ORDER, UPWIND, R, NB, (ORDER >= 8 || OCC >= 2), OFFS_LDS, PARK, SH, T>(a, t, bufs, offs, park);
 }
 
 }  // namespace chemora
