@@ -588,6 +588,18 @@ def test_split_evolution_against_fp64(torch_cuda):
     assert e.max() <= 1e-5, dict(zip(I.GF_NAMES, e.tolist()))
 
 
+def test_split_rk3_evolution_against_fp64(torch_cuda):
+    """The RK3 step in split precision against the FP64 RK3 step (split bar)."""
+    g = bl_grid((40, 36, 32), 3)
+    u = I.brill_lindquist(g)
+    fp64 = gpu_rk3(torch_cuda, I.workload(2).params, g, u, 0.25 * g.h, 20)
+    split = gpu_rk3(torch_cuda, _split_params(0.1), g, u, 0.25 * g.h, 20)
+    e = gf_errors(split, fp64, g)
+    say(f"split vs FP64 RK3, 20 steps: max {e.max():.2e} ({I.GF_NAMES[int(np.argmax(e))]})")
+    assert np.all(np.isfinite(split[(slice(None),) + g.interior()]))
+    assert e.max() <= 1e-5, dict(zip(I.GF_NAMES, e.tolist()))
+
+
 def test_split_tile_variants_agree_and_plans_are_bitwise(torch_cuda):
     """Split precision in every tile variant agrees within the split bar (the
     FP32 kernels of different tile shapes and occupancies are compiled
