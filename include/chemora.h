@@ -247,8 +247,8 @@ typedef struct chemora_plan chemora_plan;   /* opaque, library-owned */
  * class's tile variant (see chemora_tune).  tune_cache_path NULL: the
  * variants chosen so far in this process (else the defaults).  Otherwise the
  * cache file is read if it exists, every class of the plan without an entry
- * is timed on its first patch (chemora_tune; this synchronises `stream` and
- * overwrites that patch's scratch, before the ghosts are prepared), and the
+ * is timed on its largest patch (chemora_tune; this synchronises `stream`
+ * and overwrites that patch's scratch, before the ghosts are prepared), and the
  * file is rewritten with all entries.  Device tables and the graph are
  * allocated here (ENOMEM or EDEVICE on failure, nothing leaked). */
 int chemora_plan_create(const chemora_params *params, const chemora_patch *patches, double *const *scratch,

@@ -939,11 +939,16 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
   hipStream_t s = (hipStream_t)stream;
 
   // tile variant of every patch: tuned classes from the cache, the rest
-  // timed now on the first patch of the class (then the cache is rewritten)
+  // timed now on the largest patch of the class (longer launches, less
+  // noise; then the cache is rewritten)
   std::vector<int> var(npatch, 0);
   if (tune_cache_path) {
     load_cache(tune_cache_path);
-    for (int p = 0; p < npatch; ++p)
+    std::vector<int> by_size(npatch);
+    for (int p = 0; p < npatch; ++p) by_size[p] = p;
+    auto pts = [&](int p) { return (int64_t)patches[p].n[0] * patches[p].n[1] * patches[p].n[2]; };
+    std::stable_sort(by_size.begin(), by_size.end(), [&](int x, int y) { return pts(x) > pts(y); });
+    for (int p : by_size)
       if ((rc = tune_class(params, &patches[p], scratch[p], s, &var[p]))) return rc;
     if ((rc = save_cache(tune_cache_path))) return rc;
   } else {
