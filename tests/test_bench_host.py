@@ -37,3 +37,16 @@ def test_traffic_is_null_once_kernel_sources_change(monkeypatch):
     assert bench.measured_traffic("no-such-workload", tile) is None
     monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "0" * 64)
     assert bench.measured_traffic(w, tile) is None
+
+
+def test_profile_summaries_cite_the_recorded_counters():
+    """Each recorded traffic entry has a rocprofv3 summary under profiles/
+    that names the same kernel-sources hash and the same counter readings."""
+    prof = os.path.join(ROOT, "profiles")
+    texts = [open(os.path.join(prof, f)).read() for f in os.listdir(prof) if f.endswith(".md")]
+    for w, m in bench.MEASURED_TRAFFIC.items():
+        hits = [t for t in texts if m["sources_sha256"] in t]
+        assert hits, f"no profile names the hash recorded for {w}"
+        fetch = f"{int(m['fetch_kib'] / 1e3):,}".replace(",", " ")        # thousands of KiB, e.g. "1 164"
+        write = f"{int(m['write_kib'] / 1e3):,}".replace(",", " ")
+        assert any(fetch in t and write in t for t in hits), (w, fetch, write)
