@@ -57,6 +57,7 @@ def lib():
         L.oracle_rhs.argtypes = [P, G, dp, dp]
         L.oracle_rk4.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_rk3.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
+        L.oracle_rk3_ext.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_enforce_algebraic.argtypes = [P, G, dp]
         L.oracle_momentum.argtypes = [P, G, dp, dp]
         L.oracle_mom_point.argtypes = [dp, dp, dp]
@@ -147,6 +148,14 @@ def rk4_ext(params, grid, u: np.ndarray, dt: float, nsteps: int = 1, nthreads: i
     v = np.ascontiguousarray(u.copy())
     _ok(lib().oracle_rk4_ext(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), dt, nsteps,
                              _ptr(v)), "rk4_ext")
+    return v
+
+
+def rk3_ext(params, grid, u: np.ndarray, dt: float, nsteps: int = 1, nthreads: int = 0) -> np.ndarray:
+    """rk3() evaluated in x87 extended precision, rounded to FP64 at the end."""
+    v = np.ascontiguousarray(u.copy())
+    _ok(lib().oracle_rk3_ext(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), dt, nsteps,
+                             _ptr(v)), "rk3_ext")
     return v
 
 

@@ -826,6 +826,16 @@ int oracle_rk4_ext(const oracle_params* P, const oracle_grid* g, double dt, int 
   return 0;
 }
 
+int oracle_rk3_ext(const oracle_params* P, const oracle_grid* g, double dt, int nsteps, double* u) {
+  if (check(P, g) || !u || !(dt > 0.0) || nsteps < 0) return -1;
+  set_threads(P);
+  const size_t N = (size_t)g->sf * NGF;
+  std::vector<long double> U(u, u + N);
+  rk3<long double>(*P, *g, dt, nsteps, U.data());
+  for (size_t i = 0; i < N; ++i) u[i] = (double)U[i];
+  return 0;
+}
+
 int oracle_fill_periodic(const oracle_grid* g, double* u) {
   if (!g || !u) return -1;
   fill_periodic<double>(*g, u);

@@ -82,3 +82,39 @@ def test_rk3_static_ghosts_unchanged_and_periodic_ghosts_are_images(orc):
         idx = np.arange(-g, n[3 - ax] + g) % n[3 - ax]
         ext = np.take(ext, idx, axis=ax)
     assert np.array_equal(o1[:, :, :, : w1.grid.ext[0]], ext)
+
+
+def test_extended_precision_rk3_step_is_the_exact_step_rounded(orc):
+    """The extended-precision RK3 path (the FP64-rounding reference of the GPU
+    tests) on uniform data: one step of the ODE the system reduces to, worked
+    out in 40-digit arithmetic with the same three stages, comes back
+    correctly rounded to FP64 (within 0.51 ulp); pins its 3/4, 1/4, 1/3 and
+    2/3 in its own precision."""
+    import mpmath
+    assert orc.ext_mantissa_bits() >= 64
+    v = _flat_values()
+    v[0], v[7], v[17] = 0.9, 0.3, 0.8
+    v[18:21] = (0.1, -0.2, 0.05)
+    v[21:24] = (0.3, 0.1, -0.2)
+    eta, dt = 2.0, 0.37
+    grid, u = _uniform(v)
+    p = I.Params(fd_order=4, ghost=2, upwind=0, ko_radius=2, eps_diss=0.1, eta=eta, bc=I.BC_PERIODIC)
+    out = orc.rk3_ext(p, grid, u, dt, 1)
+    inner = out[(slice(None),) + grid.interior()]
+    with mpmath.workdps(40):
+        def f(y):
+            chi, K, a = y[0], y[1], y[2]
+            d = [mpmath.mpf(2) / 3 * chi * a * K, a * K * K / 3, -2 * a * K]
+            d += [mpmath.mpf(3) / 4 * y[6 + i] for i in range(3)]
+            d += [-mpmath.mpf(eta) * y[6 + i] for i in range(3)]
+            return d
+        h = mpmath.mpf(dt)
+        y0 = [mpmath.mpf(float(v[i])) for i in (0, 7, 17, 18, 19, 20, 21, 22, 23)]
+        y1 = [a + h * b for a, b in zip(y0, f(y0))]
+        y2 = [mpmath.mpf(3) / 4 * a + (b + h * c) / 4 for a, b, c in zip(y0, y1, f(y1))]
+        y3 = [a / 3 + 2 * (b + h * c) / 3 for a, b, c in zip(y0, y2, f(y2))]
+    for slot, gf in enumerate((0, 7, 17, 18, 19, 20, 21, 22, 23)):
+        want = y3[slot]
+        ulp = np.spacing(abs(float(want)))
+        err = float(abs(mpmath.mpf(float(inner[gf].flat[0])) - want))
+        assert err <= 0.51 * ulp, (gf, err / ulp)
