@@ -20,6 +20,7 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+METRIC = "BSSN grid-point updates/s on 1 MI355X: FP64 vs batched vs split-FP32 (+% roofline)"
 
 # Floating-point operations of one right-hand-side evaluation per point, as
 # counted by the CPU oracle's counting scalar (+, -, *, / each one; no FMA):
@@ -78,6 +79,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-patch batched form")
     ap.add_argument("--no-split", action="store_true", help="skip the 256^3 split-precision comparison")
     ap.add_argument("--no-rk3", action="store_true", help="skip the third-order Runge-Kutta form")
+    ap.add_argument("--no-order8", action="store_true", help="skip the 192^3 order-8 workload")
+    ap.add_argument("--split-steps", type=int, default=100, help="RK4 steps of the split-precision comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -173,7 +176,7 @@ def main():
     flops_update = 4 * RHS_FLOPS[w.params.fd_order] + RK4_FLOPS
     traffic = measured_traffic(w.name, f"{tile[0]}x{tile[1]}")
     out = {
-        "metric": "BSSN grid-point updates/s (one point advanced one full RK4 step), FP64",
+        "metric": METRIC,
         "value": value,
         "unit": "updates/s",
         "n_gpus": 1,
@@ -220,18 +223,87 @@ def main():
                                "min": float(np.min(reps)), "max": float(np.max(reps))},
         "host_wall_s": wall,
     }
+    out["roofline"]["achievable_copy_gbs"] = copy_bandwidth(torch)
     if not args.no_rk3:
         out["rk3"] = rk3_form(C, I, torch, w, u0)
         out["constraints"] = constraints_form(C, torch, P)
+    del P, scratch
+    torch.cuda.empty_cache()
+    if not args.no_order8 and args.workload != 3:
+        out["order8"] = order8_form(C, I, torch, args.no_tune)
     if not args.no_batched:
-        del P, scratch
-        torch.cuda.empty_cache()
         out["batched"] = batched_form(C, I, torch, args.no_tune)
     if not args.no_split:
-        out["split"] = split_form(C, I, torch, args.no_tune)
+        out["split"] = split_form(C, I, torch, args.no_tune, steps=args.split_steps)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, u0)
+        out["cpu_baseline"] = cpu_baseline(w, u0, I)
     print(json.dumps(out), flush=True)
+
+
+def copy_bandwidth(torch, mib=2048, reps=5):
+    """The achievable HBM bandwidth: a plain device-to-device copy of `mib` MiB
+    (read + write bytes / time, best of `reps`)."""
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n * 8 / (best * 1e-3) / 1e9
+
+
+def stage_timed_steps(C, torch, P, dt, sp, K):
+    """K RK4 steps driven stage by stage with HIP events on the launch stream:
+    (ms per step, mean stage-2/3 launch ms)."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
+    torch.cuda.synchronize()
+    for k in range(K):
+        ev[k][0].record(stream)
+        for s in (1, 2, 3, 4):
+            C.chemora_rk4_stage(P.params, P.patch, s, dt, sp, stream)
+            ev[k][s].record(stream)
+    torch.cuda.synchronize()
+    st = np.array([[ev[k][s - 1].elapsed_time(ev[k][s]) for s in (1, 2, 3, 4)] for k in range(K)])
+    return float(st.sum(axis=1).mean()), float(st[:, 1:3].mean())
+
+
+def order8_form(C, I, torch, no_tune, steps=5, warmup=1):
+    """The 8th-order workload (192^3, 5 ghosts, partially upwinded order-8
+    stencils, Kreiss-Oliger r=5, perturbed Brill-Lindquist data): rate and
+    the stage-2/3 kernel's HBM fraction at 960 algorithmic bytes per point."""
+    w = I.workload(3)
+    P = C.Patch(w.params, w.grid, w.make_state())
+    sp = P.scratch().data_ptr()
+    stream = torch.cuda.current_stream()
+    variant = C.chemora_tile_variant(P.params, P.patch) if no_tune else C.chemora_tune(P.params, P.patch, sp, None,
+                                                                                         stream)
+    tile = C.chemora_tile_variant_shape(variant)
+    stage_timed_steps(C, torch, P, w.dt, sp, warmup)
+    ms, t23 = stage_timed_steps(C, torch, P, w.dt, sp, steps)
+    npts = w.grid.npoints
+    gbs = 960 * npts / (t23 * 1e-3) / 1e9
+    traffic = measured_traffic(w.name, f"{tile[0]}x{tile[1]}")
+    del P
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "interior": list(w.grid.n), "fd_order": 8, "ghost": w.params.ghost,
+            "steps": steps, "ms_per_step": ms, "value": npts / (ms * 1e-3), "unit": "updates/s",
+            "tile": f"{tile[0]}x{tile[1]}",
+            "stage23": {"avg_launch_ms": t23, "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                        "traffic": traffic},
+            "step_hbm_frac": npts / (ms * 1e-3) * 3072 / (HBM_PEAK_GBS * 1e9),
+            "fp64_frac": npts / (ms * 1e-3) * (4 * RHS_FLOPS[8] + RK4_FLOPS) / (FP64_PEAK_TFLOPS * 1e12)}
 
 
 def batched_form(C, I, torch, no_tune, steps=10, warmup=2):
@@ -257,6 +329,25 @@ def batched_form(C, I, torch, no_tune, steps=10, warmup=2):
     B.close()
     del B
     torch.cuda.empty_cache()
+    # the same patches and data stepped one chemora_rk4_step call each, with
+    # the tile variants the plan's tuner recorded for their classes
+    Ps = [C.Patch(params, g, s) for g, s in zip(grids, states)]
+    stream = torch.cuda.current_stream()
+    sps = [P.scratch().data_ptr() for P in Ps]
+
+    def per_patch(n):
+        for _ in range(n):
+            for P, g, sp in zip(Ps, grids, sps):
+                C.chemora_rk4_step(P.params, P.patch, 0.25 * g.h, sp, stream)
+    per_patch(warmup)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    per_patch(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_pp = e0.elapsed_time(e1) / steps
+    del Ps
+    torch.cuda.empty_cache()
     # the same plan with the third-order SSP Runge-Kutta step captured
     B3 = C.Batch(params, grids, states, 0.25, tune_cache_path=None if no_tune else _tune_cache(), integrator="rk3")
     B3.step(warmup)
@@ -270,6 +361,10 @@ def batched_form(C, I, torch, no_tune, steps=10, warmup=2):
     return {"workload": "64 patches, 24-96 points per edge, order 4 upwind (batched plan)", "patches": len(grids),
             "points": npts, "steps": steps, "ms_per_step": ms, "value": npts / (ms * 1e-3),
             "unit": "updates/s", "tile_variants": [f"{a}x{b}" for a, b in map(C.chemora_tile_variant_shape, variants)],
+            "hbm_frac": npts / (ms * 1e-3) * 3072 / (HBM_PEAK_GBS * 1e9),
+            "per_patch": {"ms_per_step": ms_pp, "value": npts / (ms_pp * 1e-3),
+                          "calls": "one chemora_rk4_step per patch and step, same tile variants"},
+            "speedup_vs_per_patch": ms_pp / ms,
             "rk3": {"ms_per_step": ms3, "value": npts / (ms3 * 1e-3)}}
 
 
@@ -326,19 +421,22 @@ def rk3_form(C, I, torch, w, u0, steps=20, warmup=2):
             "hbm_frac": npts / (ms * 1e-3) * 8 * 24 * 8 / (HBM_PEAK_GBS * 1e9)}
 
 
-def split_form(C, I, torch, no_tune, steps=20, warmup=2):
+def split_form(C, I, torch, no_tune, steps=100, warmup=2):
     """Split precision (FP32 stencil combinations and algebra, FP64 state,
     RK combination and near-puncture chi terms, chi_split = 0.1) against FP64
-    on the same 256^3 Brill-Lindquist data: throughput of each, and the
-    max-norm-normalised difference per GF after warmup + steps RK4 steps on
-    the central 64^3 of the grid."""
+    on the same 256^3 Brill-Lindquist data: throughput of each over `steps`
+    RK4 steps (after `warmup` untimed ones, both runs advancing the same
+    total), then on the 64^3 subsample i, j, k in {2, 6, ..., 254} the
+    max-norm-normalised difference per GF of split against FP64 and the RMS
+    of the Hamiltonian constraint of each state.  The FP64 reference is the
+    GPU FP64 path (the oracle would need hours for 100 steps at 256^3; the
+    parity tests hold the GPU FP64 path to the oracle)."""
     import numpy as np
     w = I.workload(5)
     u0 = w.make_state()
-    g, n = w.grid.ghost, w.grid.n[0]
-    c = n // 2 - 32
-    box = (slice(None),) + (slice(g + c, g + c + 64),) * 3
-    res, sub = {}, {}
+    g = w.grid.ghost
+    sub = np.arange(2, w.grid.n[0], 4)
+    res, st, ham = {}, {}, {}
     for name, prec in (("fp64", I.PREC_FP64), ("split", I.PREC_SPLIT)):
         p = I.Params(**vars(w.params))
         p.precision = prec
@@ -355,16 +453,28 @@ def split_form(C, I, torch, no_tune, steps=20, warmup=2):
         ms = e0.elapsed_time(e1) / steps
         tile = C.chemora_tile_variant_shape(variant)
         res[name] = {"ms_per_step": ms, "value": w.grid.npoints / (ms * 1e-3), "tile": f"{tile[0]}x{tile[1]}"}
-        sub[name] = P.u[box].cpu().numpy()
-        del P
+        ix = torch.as_tensor(g + sub, device=P.u.device)
+        st[name] = P.u.index_select(1, ix).index_select(2, ix).index_select(3, ix).cpu().numpy()
+        # H of the final state, evaluated in FP64 for both runs
+        hp = I.Params(**vars(w.params))
+        hp.precision = I.PREC_FP64
+        H = C.Patch(hp, w.grid, P.u).hamiltonian()
+        ham[name] = H.index_select(0, ix - g).index_select(1, ix - g).index_select(2, ix - g).cpu().numpy()
+        del P, H
         torch.cuda.empty_cache()
-    scale = np.max(np.abs(sub["fp64"]), axis=(1, 2, 3))
-    err = np.max(np.abs(sub["split"] - sub["fp64"]), axis=(1, 2, 3)) / np.where(scale > 0, scale, 1.0)
+    scale = np.max(np.abs(st["fp64"]), axis=(1, 2, 3))
+    err = np.max(np.abs(st["split"] - st["fp64"]), axis=(1, 2, 3)) / np.where(scale > 0, scale, 1.0)
     worst = int(np.argmax(err))
+    h64 = float(np.sqrt(np.mean(ham["fp64"] ** 2)))
+    hsp = float(np.sqrt(np.mean(ham["split"] ** 2)))
     return {"workload": w.name, "interior": list(w.grid.n), "chi_split": w.params.chi_split,
-            "steps": warmup + steps, "unit": "updates/s", "fp64": res["fp64"], "split": res["split"],
-            "speedup": res["fp64"]["ms_per_step"] / res["split"]["ms_per_step"],
-            "max_err_vs_fp64_central_64^3": float(err[worst]), "worst_gf": I.GF_NAMES[worst]}
+            "steps": warmup + steps, "timed_steps": steps, "unit": "updates/s", "fp64": res["fp64"],
+            "split": res["split"], "speedup": res["fp64"]["ms_per_step"] / res["split"]["ms_per_step"],
+            "subsample": "64^3 points i,j,k in {2,6,...,254}",
+            "reference": "GPU FP64 run on the same data and steps",
+            "max_err_vs_fp64": float(err[worst]), "worst_gf": I.GF_NAMES[worst],
+            "err_per_gf": {n: float(e) for n, e in zip(I.GF_NAMES, err)},
+            "h_rms_fp64": h64, "h_rms_split": hsp, "h_rms_ratio": hsp / h64 if h64 > 0 else None}
 
 
 def _tune_cache():
@@ -372,25 +482,30 @@ def _tune_cache():
     return os.path.join(tempfile.gettempdir(), f"chemora_tiles_{os.getpid()}.json")
 
 
-def cpu_baseline(w, u0, min_seconds=10.0, max_steps=20):
-    """The CPU oracle (plain C++, OpenMP on every host core) timed on this
-    host: RK4 steps of the same full-size workload, repeated until at least
-    min_seconds have passed (a bounded sample of the run)."""
+def cpu_baseline(w, u0, I, min_seconds=10.0, max_steps=20):
+    """The CPU oracle (plain C++, OpenMP) timed on this host.  All host
+    threads: RK4 steps of the same full-size workload; the first step (which
+    also pages the buffers in) is timed alone and sets how many steps fill
+    about min_seconds, and those are timed in one call whose step loop is
+    clocked inside the oracle, without the allocation of its stage vectors.
+    One thread: a 32^3 sample of the same workload (same data recipe,
+    parameters and dt) for a per-core rate."""
     root = os.path.dirname(os.path.abspath(__file__))
     if root not in sys.path:
         sys.path.insert(0, root)
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-    u = u0
-    steps = 0
-    t = time.perf_counter()
-    while steps < max_steps and (steps == 0 or time.perf_counter() - t < min_seconds):
-        u = oracle.rk4(w.params, w.grid, u, w.dt, 1, nthreads=threads)
-        steps += 1
-    dt = time.perf_counter() - t
-    return {"value": w.grid.npoints * steps / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+    u1, t1 = oracle.rk4_timed(w.params, w.grid, u0, w.dt, 1, nthreads=threads)
+    steps = int(max(1, min(max_steps, round(min_seconds / max(t1, 1e-3)))))
+    _, t = oracle.rk4_timed(w.params, w.grid, u1, w.dt, steps, nthreads=threads)
+    one = I.workload(2, n_override=32)
+    _, t_one = oracle.rk4_timed(one.params, one.grid, one.make_state(), one.dt, 1, nthreads=1)
+    return {"value": w.grid.npoints * steps / t, "unit": "updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{steps} RK4 steps of the same {w.grid.n[0]}x{w.grid.n[1]}x{w.grid.n[2]} workload "
-                      f"({w.grid.npoints * steps} point updates), {dt:.1f} s wall"}
+                      f"({w.grid.npoints * steps} point updates) in {t:.1f} s of step loop, after one "
+                      f"step ({t1:.1f} s) that sizes the sample",
+            "one_thread": {"value": one.grid.npoints / t_one, "unit": "updates/s", "cores": 1,
+                           "sample": f"1 RK4 step of the 32^3 Brill-Lindquist workload, {t_one:.2f} s"}}
 
 
 if __name__ == "__main__":

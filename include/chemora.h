@@ -71,8 +71,10 @@ enum { CHEMORA_SHIFT_GAMMA_DRIVER = 0, CHEMORA_SHIFT_FROZEN = 1 };
 enum { CHEMORA_BC_STATIC = 0, CHEMORA_BC_PERIODIC = 1 };
 enum { CHEMORA_PREC_FP64 = 0, CHEMORA_PREC_SPLIT = 1 };
 
-/* Discretisation and gauge parameters (the kernel "descriptor": stencil
- * extent, parameters).  */
+/* Discretisation and gauge parameters.  This is the kernel descriptor of
+ * section "Kernel Abstractions": the parameters a numerical kernel needs and
+ * the extent of its stencil (fd_order, upwind and ko_radius fix how far a
+ * point's neighbourhood reaches; ghost says how much of it is stored).  */
 typedef struct chemora_params {
   int32_t fd_order;   /* 4 or 8: centred first/second/mixed derivatives      */
   int32_t ghost;      /* g >= chemora_required_ghost(fd_order, upwind, ko)   */
@@ -97,7 +99,10 @@ typedef struct chemora_params {
                          allowed; EINVAL otherwise; ignored for FP64)       */
 } chemora_params;
 
-/* One Cartesian patch (a grid section with its ghost zones). */
+/* One Cartesian patch: a grid section with its ghost zones, holding the 24
+ * grid functions of the state (section "Grid Abstractions": a grid function
+ * is one variable of the application over the grid; the grid geometry gives
+ * its spacing and coordinates).  The library never allocates or frees u. */
 typedef struct chemora_patch {
   int32_t n[3];       /* interior points nx, ny, nz (>= 1; >= ghost when the
                          boundary is periodic)                              */
@@ -116,8 +121,20 @@ int chemora_required_ghost(int fd_order, int upwind, int ko_radius);
 /* Right-hand side of all 24 BSSN equations at every interior point
  * (moving-puncture BSSN with 1+log / harmonic / frozen lapse and the
  * advective Gamma-driver shift, Kreiss-Oliger dissipation added to every
- * evolved variable).  `rhs` has the patch's layout and strides; only its
- * interior entries are written.  `rhs` must not overlap the patch state. */
+ * evolved variable).  Defined by section "Scientific Motivation" (the BSSN
+ * form of the Einstein equations: thousands of terms per point, first,
+ * second and mixed derivatives of the evolved variables) and section
+ * "Binary Black Hole Simulations with Chemora" (the derivative, advection
+ * and evaluation kernels of the McLachlan code, partially upwinded
+ * stencils); it is the point-wise numerical kernel of section "Kernel
+ * Abstractions", applied to every interior point of a grid section whose
+ * ghost zones were filled outside the kernel.  Reads patch->u (ghosts
+ * included: the caller provides them), writes the interior entries of
+ * `rhs` (the patch's layout and strides; ghost and padding entries are not
+ * written).  `rhs` is caller-owned device memory and must not overlap the
+ * patch state.  Asynchronous on `stream`.  EINVAL (bad params, strides,
+ * NULL / misaligned / overlapping pointers) and EUNSUPPORTED are returned
+ * before any GPU work; EDEVICE if the launch fails. */
 int chemora_bssn_rhs(const chemora_params *params, const chemora_patch *patch, double *rhs,
                      void *stream);
 
@@ -125,7 +142,14 @@ int chemora_bssn_rhs(const chemora_params *params, const chemora_patch *patch, d
  * (two stage buffers and the RK accumulator). */
 size_t chemora_rk4_scratch_elems(const chemora_patch *patch);
 
-/* One classic RK4 step of size dt > 0 applied to patch->u in place.
+/* One classic RK4 step of size dt > 0 applied to patch->u in place: the
+ * method-of-lines update the paper's framework applies after each
+ * right-hand-side evaluation (section "Binary Black Hole Simulations with
+ * Chemora", timer rows "Time integrator data copy" and "Boundary
+ * condition"; the paper runs a third-order scheme, see chemora_rk3_step).
+ * Four stage launches; each evaluates the right-hand side of its stage input
+ * and applies the stage combination in the same pass (16 state transfers
+ * per point and step).
  * BC static: ghost points of u are left untouched and are the ghosts of every
  * stage.  BC periodic: ghosts of every stage input and of the result are
  * refilled with periodic images of the interior.  `scratch` is a device
@@ -229,6 +253,11 @@ int chemora_set_tile_variant(const chemora_params *params, const chemora_patch *
 int chemora_tile_variant_shape(int32_t variant, int32_t *tile_x, int32_t *tile_y);
 
 /* ---- batched form: many patches advanced together ------------------------
+ * Section "Cactus-Carpet Computational Infrastructure": block-structured
+ * grids with many patches (refinement levels, multi-block) per process;
+ * section "Grid Abstractions": the grid hierarchy of such patches; section
+ * "Stencils and Dynamic Tile Selection": the tile shape of each kernel
+ * launch chosen for the grid it runs on.
  * A plan records a list of patches (each with its own spacing h, extents and
  * strides; all share params) and their RK4 scratch buffers.  One RK4 step of
  * every patch is captured once into a HIP graph: per RK stage one launch
@@ -264,7 +293,11 @@ int chemora_plan_create_rk3(const chemora_params *params, const chemora_patch *p
                             chemora_plan **out);
 
 /* Advances every patch of the plan by nsteps steps of its integrator
- * (nsteps >= 0), by replaying the captured graph on `stream`. */
+ * (nsteps >= 0), by replaying the captured graph on `stream`: per step and
+ * RK stage, the right-hand side and stage combination of every patch
+ * (chemora_rk4_step's arithmetic, bitwise the same as per-patch calls with
+ * the same tile variant).  Asynchronous; EINVAL for a NULL plan or
+ * nsteps < 0, EDEVICE if a graph launch fails. */
 int chemora_batch_step(chemora_plan *plan, int32_t nsteps, void *stream);
 
 /* Total interior points of the plan's patches (0 for NULL). */

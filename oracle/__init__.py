@@ -57,6 +57,7 @@ def lib():
         L.oracle_rhs.argtypes = [P, G, dp, dp]
         L.oracle_rk4.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_rk3.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
+        L.oracle_rk4_timed.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp, dp]
         L.oracle_rk3_ext.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_enforce_algebraic.argtypes = [P, G, dp]
         L.oracle_momentum.argtypes = [P, G, dp, dp]
@@ -110,6 +111,16 @@ def rk4(params, grid, u: np.ndarray, dt: float, nsteps: int = 1, nthreads: int =
     _ok(lib().oracle_rk4(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), dt, nsteps,
                          _ptr(v)), "rk4")
     return v
+
+
+def rk4_timed(params, grid, u: np.ndarray, dt: float, nsteps: int = 1, nthreads: int = 0):
+    """(copy of u advanced by nsteps RK4 steps, wall seconds of the step loop
+    alone): the allocation of the oracle's stage vectors is not timed."""
+    v = np.ascontiguousarray(u.copy())
+    sec = np.zeros(1)
+    _ok(lib().oracle_rk4_timed(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), dt, nsteps,
+                               _ptr(v), _ptr(sec)), "rk4_timed")
+    return v, float(sec[0])
 
 
 def rk3(params, grid, u: np.ndarray, dt: float, nsteps: int = 1, nthreads: int = 0) -> np.ndarray:

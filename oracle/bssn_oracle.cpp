@@ -36,6 +36,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <chrono>
 #include <vector>
 #ifdef _OPENMP
 #include <omp.h>
@@ -689,11 +690,15 @@ void axpy_interior(const oracle_grid& g, const T* base, T c, const T* k, T* out)
 
 // nsteps classic RK4 steps, u advanced in place.  Stage inputs take their
 // ghosts from u (static) or from periodic images (periodic).
+// loop_seconds (may be null) receives the wall time of the step loop alone,
+// without the allocation of the stage vectors.
 template <class T>
-void rk4(const oracle_params& P, const oracle_grid& g, double dt_in, int nsteps, T* u) {
+void rk4(const oracle_params& P, const oracle_grid& g, double dt_in, int nsteps, T* u,
+         double* loop_seconds = nullptr) {
   const size_t N = (size_t)g.sf * NGF;
   const T dt = T(dt_in), half = T(0.5), two = T(2.0), sixth = dt / T(6.0);
   std::vector<T> k1(N, T(0.0)), k2(N, T(0.0)), k3(N, T(0.0)), k4(N, T(0.0)), s(u, u + N);
+  const auto t0 = std::chrono::steady_clock::now();
   for (int step = 0; step < nsteps; ++step) {
     rhs_grid<T>(P, g, u, k1.data());
     std::copy(u, u + N, s.begin());   // ghosts of the stage input
@@ -716,6 +721,8 @@ void rk4(const oracle_params& P, const oracle_grid& g, double dt_in, int nsteps,
           }
     if (P.bc == 1) fill_periodic<T>(g, u);
   }
+  if (loop_seconds)
+    *loop_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 // nsteps third-order Runge-Kutta steps, u advanced in place: the strong
@@ -784,6 +791,16 @@ int oracle_rk4(const oracle_params* P, const oracle_grid* g, double dt, int nste
   if (check(P, g) || !u || !(dt > 0.0) || nsteps < 0) return -1;
   set_threads(P);
   rk4<double>(*P, *g, dt, nsteps, u);
+  return 0;
+}
+
+// oracle_rk4, with the wall time of the step loop (allocation of the stage
+// vectors excluded) stored in *seconds: the timing of the CPU baseline.
+int oracle_rk4_timed(const oracle_params* P, const oracle_grid* g, double dt, int nsteps, double* u,
+                     double* seconds) {
+  if (check(P, g) || !u || !(dt > 0.0) || nsteps < 0 || !seconds) return -1;
+  set_threads(P);
+  rk4<double>(*P, *g, dt, nsteps, u, seconds);
   return 0;
 }
 

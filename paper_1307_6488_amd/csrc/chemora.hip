@@ -29,6 +29,7 @@
 
 #include "chemora.h"
 #include "fd_ops.hpp"
+#include "host_internal.hpp"
 #include "stage_common.hpp"
 
 namespace chemora {
@@ -631,6 +632,38 @@ int rk4_stage(const chemora_params* params, const chemora_patch* patch, int stag
 
 }  // namespace
 
+namespace chemora {
+namespace host {
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+void clear_error() { g_error.clear(); }
+
+int check_step(const chemora_params* params, const chemora_patch* patch, double dt) {
+  int rc = validate(params, patch);
+  if (rc) return rc;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return ::fail(CHEMORA_EINVAL, "dt must be finite and > 0");
+  return CHEMORA_OK;
+}
+
+int rk4_step(const chemora_params* params, const chemora_patch* patch, double dt, double* scratch, hipStream_t s) {
+  int rc;
+  for (int st = 1; st <= 4; ++st)
+    if ((rc = rk4_stage(params, patch, st, dt, scratch, s))) return rc;
+  return CHEMORA_OK;
+}
+
+}  // namespace host
+}  // namespace chemora
+
 extern "C" {
 
 int chemora_rk4_step(const chemora_params* params, const chemora_patch* patch, double dt, double* scratch,
@@ -638,9 +671,7 @@ int chemora_rk4_step(const chemora_params* params, const chemora_patch* patch, d
   g_error.clear();
   int rc = rk4_checks(params, patch, dt, scratch);
   if (rc) return rc;
-  for (int st = 1; st <= 4; ++st)
-    if ((rc = rk4_stage(params, patch, st, dt, scratch, (hipStream_t)stream))) return rc;
-  return CHEMORA_OK;
+  return chemora::host::rk4_step(params, patch, dt, scratch, (hipStream_t)stream);
 }
 
 size_t chemora_rk3_scratch_elems(const chemora_patch* patch) {
@@ -910,10 +941,6 @@ void plan_free(chemora_plan* pl) {
 
 }  // namespace
 
-extern "C" {
-
-}  // extern "C"
-
 namespace {
 
 // A plan capturing one step of RK4 (4 stages) or of the third-order SSP
@@ -935,6 +962,27 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
       return fail(rc, "patch %d: %s", p, m.c_str());
     }
     points += (int64_t)patches[p].n[0] * patches[p].n[1] * patches[p].n[2];
+  }
+  // every patch state and scratch buffer is its own memory: the stage
+  // launches of a plan write them concurrently
+  {
+    struct Range {
+      uintptr_t lo, hi;
+      int patch;
+      const char* what;
+    };
+    std::vector<Range> rs;
+    rs.reserve(2 * (size_t)npatch);
+    for (int p = 0; p < npatch; ++p) {
+      const size_t state = (size_t)CHEMORA_NGF * patches[p].sf * sizeof(double);
+      rs.push_back({(uintptr_t)patches[p].u, (uintptr_t)patches[p].u + state, p, "state"});
+      rs.push_back({(uintptr_t)scratch[p], (uintptr_t)scratch[p] + 3 * state, p, "scratch"});
+    }
+    std::sort(rs.begin(), rs.end(), [](const Range& x, const Range& y) { return x.lo < y.lo; });
+    for (size_t i = 1; i < rs.size(); ++i)
+      if (rs[i].lo < rs[i - 1].hi)
+        return fail(CHEMORA_EINVAL, "patch %d %s overlaps patch %d %s", rs[i].patch, rs[i].what, rs[i - 1].patch,
+                    rs[i - 1].what);
   }
   hipStream_t s = (hipStream_t)stream;
 

@@ -77,6 +77,7 @@ class Grid:
     h: float
     origin: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     row_align: int = 8          # sy is rounded up to a multiple of this
+    row_pad: int = 0            # ... then this many elements are added
 
     @property
     def ext(self) -> Tuple[int, int, int]:
@@ -86,7 +87,7 @@ class Grid:
     @property
     def sy(self) -> int:
         a = self.row_align
-        return (self.ext[0] + a - 1) // a * a
+        return (self.ext[0] + a - 1) // a * a + self.row_pad
 
     @property
     def sz(self) -> int:

@@ -255,6 +255,33 @@ def test_plan_argument_checks_on_host():
     assert L.chemora_plan_points(None) == 0
 
 
+def test_plan_rejects_aliased_buffers_on_host():
+    """Two patches sharing a state, or a scratch buffer reaching into another
+    patch's state or scratch, are rejected before any HIP call."""
+    p, g = _good()
+    P = C.make_params(p)
+    L = C.lib()
+    state = 24 * g.sf * 8
+    out = ctypes.c_void_p(0)
+
+    def create(us, scs):
+        arr = (C.chemora_patch * len(us))(*[C.make_patch(g, u) for u in us])
+        sc = (ctypes.c_void_p * len(scs))(*[ctypes.c_void_p(v) for v in scs])
+        return L.chemora_plan_create(ctypes.byref(P), arr, sc, len(us), 0.25, None, None, ctypes.byref(out))
+
+    base = FAKE
+    far = FAKE + (1 << 36)
+    # shared state
+    assert create([base, base], [far, far + 4 * state]) == C.EINVAL
+    assert "overlaps" in C.last_error()
+    # scratch of patch 0 runs into the state of patch 1
+    assert create([base, far + 2 * state], [far, far + 8 * state]) == C.EINVAL
+    assert "overlaps" in C.last_error()
+    # scratch buffers of two patches overlap by one element
+    assert create([base, base + state], [far, far + 3 * state - 8]) == C.EINVAL
+    assert out.value is None
+
+
 def test_tile_variant_shapes_and_table_on_host():
     assert [C.chemora_tile_variant_shape(v) for v in range(4)] == [(64, 4), (64, 8), (32, 8), (32, 16)]
     assert C.lib().chemora_tile_variant_shape(4, None, None) == C.EINVAL

@@ -3,7 +3,8 @@
 Error metric per grid function f (max-norm normalised, interior points):
     err_f = max |x_f - x_f^oracle| / max |x_f^oracle|
 and for a function the oracle gives as exactly zero, |x_f| <= 1e-14 times the
-largest magnitude over all functions.  Bars: 1e-12 after one right-hand side
+largest magnitude over all functions, whatever the bar of the others
+(tests/parity_metrics.py).  Bars: 1e-12 after one right-hand side
 or one RK4 step, 1e-10 after 100 RK4 steps.  The GPU is free to contract to
 FMA and to reorder sums; bitwise checks only compare the GPU with itself
 (translation, determinism) or exact zeros.
@@ -16,6 +17,7 @@ import pytest
 
 import oracle
 from paper_1307_6488_amd import inputs as I
+from parity_metrics import ZERO_BAR, gf_errors, parity_failures
 
 pytestmark = pytest.mark.gpu
 
@@ -35,23 +37,14 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def gf_errors(got, ref, grid):
-    s = (slice(None),) + grid.interior()
-    a, b = got[s], ref[s]
-    scale = np.max(np.abs(b), axis=(1, 2, 3))
-    diff = np.max(np.abs(a - b), axis=(1, 2, 3))
-    big = float(np.max(scale))
-    out = np.where(scale > 0, diff / np.where(scale > 0, scale, 1.0), diff / max(big, 1e-300) * 1e-2)
-    return out
-
-
-def assert_parity(got, ref, grid, tol, what):
+def assert_parity(got, ref, grid, tol, what, zero_tol=ZERO_BAR):
     e = gf_errors(got, ref, grid)
     worst = int(np.argmax(e))
     say(f"{what}: max err {e[worst]:.3e} ({I.GF_NAMES[worst]}); per GF: "
         + " ".join(f"{v:.1e}" for v in e))
     assert np.all(np.isfinite(got[(slice(None),) + grid.interior()])), what
-    assert e[worst] <= tol, (what, dict(zip(I.GF_NAMES, e.tolist())))
+    bad = parity_failures(got, ref, grid, tol, zero_tol)
+    assert not bad, (what, {I.GF_NAMES[f]: v for f, v in bad.items()})
 
 
 def assert_fp64_accuracy(got, orc, ext, grid, what, factor=4.0, floor=1e-14, cap=1e-10):
@@ -741,3 +734,62 @@ def test_full_size_evolution_against_oracle_samples(torch_cuda, name, index):
     say(f"{name}: max err {err.max():.3e} ({I.GF_NAMES[int(np.argmax(err))]})")
     assert np.all(np.isfinite(samp))
     assert err.max() <= 1e-10, dict(zip(I.GF_NAMES, err.tolist()))
+
+
+# The ABI's least strides: sy = nx + 2g (even nx; + 1 for odd nx), sz and sf
+# without padding, odd sy / sz / sf, and ghost wider than the stencils reach
+# (g - R odd), so that the staged pairs of doubles sit only 8-byte aligned.
+MIN_STRIDE_CASES = [
+    # (id, order, upwind, ko_radius, ghost, n, row_pad)
+    ("o4-upwind-g4-odd-strides", 4, 1, 3, 4, (22, 13, 9), 1),
+    ("o4-upwind-g3-odd-nx-least-sy", 4, 1, 3, 3, (21, 14, 11), 1),
+    ("o4-centred-r2-g3-even-nx", 4, 0, 2, 3, (26, 11, 8), 0),
+    ("o8-upwind-g6-odd-strides", 8, 1, 5, 6, (18, 11, 9), 1),
+]
+
+
+@pytest.mark.parametrize("case", MIN_STRIDE_CASES, ids=[c[0] for c in MIN_STRIDE_CASES])
+def test_least_strides_and_wide_ghosts_against_oracle(torch_cuda, case):
+    name, order, upwind, ko, ghost, n, pad = case
+    g = I.Grid(n, ghost, 1.0 / 8.0, tuple(-(v - 1) / 16.0 + 0.37 for v in n), row_align=1, row_pad=pad)
+    assert g.sy == n[0] + 2 * ghost + pad
+    if n[0] % 2:
+        assert g.sy >= n[0] + 2 * ghost + 1
+    p = I.config_params(order, upwind, ghost, ko, I.BC_STATIC)
+    u = I.brill_lindquist(g)
+    I.add_sinusoids(u, g, np.random.default_rng(1330 + order + ghost), 1e-4, range(I.NGF), periodic_ghosts=False)
+    I.poison_padding(u, g)
+    say(f"least strides {name}: n={n} g={ghost} sy={g.sy} sz={g.sz} sf={g.sf}")
+    got = gpu_rhs(torch_cuda, p, g, u)
+    ref = oracle.rhs(p, g, u, nthreads=NTHREADS)
+    assert_parity(got, ref, g, 1e-12, f"least strides rhs {name}")
+    dt = 0.25 * g.h
+    got = gpu_rk4(torch_cuda, p, g, u, dt, 2)
+    ref = oracle.rk4(p, g, u, dt, 2, nthreads=NTHREADS)
+    assert_parity(got, ref, g, 1e-10, f"least strides rk4 {name}")
+
+
+def test_split_precision_bar_against_fp64_oracle(torch_cuda):
+    """The split-precision bar at a small size of the 256^3 workload's data
+    (Brill-Lindquist, order 4 upwinded, chi_split = 0.1): after 20 RK4 steps
+    at 48^3 the split state is within 1e-5 of the FP64 oracle's per GF
+    (max-norm normalised), and the RMS of its Hamiltonian constraint (the
+    oracle's H of each final state) is at most twice that of the FP64
+    oracle's state."""
+    g = bl_grid((48, 48, 48), 3)
+    u = I.brill_lindquist(g)
+    p64 = I.workload(2).params
+    dt, nsteps = 0.25 * g.h, 20
+    say("split precision bar 48^3, 20 steps")
+    split = gpu_rk4(torch_cuda, _split_params(0.1), g, u, dt, nsteps)
+    fp64 = gpu_rk4(torch_cuda, p64, g, u, dt, nsteps)
+    ref = oracle.rk4(p64, g, u, dt, nsteps, nthreads=NTHREADS)
+    assert_parity(fp64, ref, g, 1e-10, "fp64 48^3 20 steps")
+    e = gf_errors(split, ref, g)
+    say(f"split vs FP64 oracle: max {e.max():.2e} ({I.GF_NAMES[int(np.argmax(e))]})")
+    assert np.all(np.isfinite(split[(slice(None),) + g.interior()]))
+    assert e.max() <= 1e-5, dict(zip(I.GF_NAMES, e.tolist()))
+    h_ref = float(np.sqrt(np.mean(oracle.hamiltonian(p64, g, ref, nthreads=NTHREADS) ** 2)))
+    h_split = float(np.sqrt(np.mean(oracle.hamiltonian(p64, g, split, nthreads=NTHREADS) ** 2)))
+    say(f"H rms: FP64 oracle {h_ref:.6e}, split {h_split:.6e}, ratio {h_split / h_ref:.6f}")
+    assert h_split <= 2.0 * h_ref
