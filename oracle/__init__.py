@@ -30,7 +30,8 @@ class _Params(ctypes.Structure):
 
 class _Grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("ghost", ctypes.c_int32), ("sy", ctypes.c_int64),
-                ("sz", ctypes.c_int64), ("sf", ctypes.c_int64), ("h", ctypes.c_double)]
+                ("sz", ctypes.c_int64), ("sf", ctypes.c_int64), ("h", ctypes.c_double),
+                ("origin", ctypes.c_double * 3)]
 
 
 def build(force: bool = True) -> str:
@@ -88,7 +89,8 @@ def _params(p, nthreads: int = 0) -> _Params:
 
 
 def _grid(g) -> _Grid:
-    return _Grid((ctypes.c_int32 * 3)(*g.n), g.ghost, g.sy, g.sz, g.sf, g.h)
+    return _Grid((ctypes.c_int32 * 3)(*g.n), g.ghost, g.sy, g.sz, g.sf, g.h,
+                 (ctypes.c_double * 3)(*getattr(g, "origin", (0.0, 0.0, 0.0))))
 
 
 def _ok(rc: int, what: str) -> None:
@@ -97,8 +99,9 @@ def _ok(rc: int, what: str) -> None:
 
 
 def rhs(params, grid, u: np.ndarray, nthreads: int = 0, out: Optional[np.ndarray] = None) -> np.ndarray:
-    """Right-hand side at the interior points (ghost entries of the result are NaN
-    unless ``out`` is given)."""
+    """Right-hand side at the interior points, and at the ghost points with the
+    radiative boundary (other entries of the result are NaN unless ``out`` is
+    given)."""
     out = np.full(grid.shape, np.nan) if out is None else out
     _ok(lib().oracle_rhs(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), _ptr(u),
                          _ptr(out)), "rhs")

@@ -53,7 +53,7 @@ typedef struct {
   int32_t lapse;      // 0 1+log, 1 harmonic, 2 frozen
   int32_t shift;      // 0 Gamma-driver, 1 frozen
   double eta;         // Gamma-driver damping
-  int32_t bc;         // 0 static ghosts, 1 periodic
+  int32_t bc;         // 0 static ghosts, 1 periodic, 2 radiative (Sommerfeld)
   int32_t nthreads;   // OpenMP threads (<= 0: runtime default)
 } oracle_params;
 
@@ -62,6 +62,7 @@ typedef struct {
   int32_t ghost;
   int64_t sy, sz, sf; // element strides (x stride 1)
   double h;           // grid spacing
+  double origin[3];   // coordinates of interior point (0, 0, 0) (radiative boundary)
 } oracle_grid;
 
 }  // extern "C"
@@ -618,6 +619,7 @@ void gather(const oracle_params& P, const oracle_grid& g, const WeightsT<typenam
 int check(const oracle_params* P, const oracle_grid* g) {
   if (!P || !g) return -1;
   if (P->fd_order != 4 && P->fd_order != 8) return -1;
+  if (P->bc < 0 || P->bc > 2) return -1;
   int need = P->fd_order / 2;
   if (P->upwind) need = need > P->fd_order / 2 + 1 ? need : P->fd_order / 2 + 1;
   if (P->ko_radius > need) need = P->ko_radius;
@@ -675,21 +677,93 @@ void fill_periodic(const oracle_grid& g, T* u) {
       }
 }
 
-// out = base + c * k on interior points
+// ---------------------------------------------------------------------------
+// Radiative (Sommerfeld) outer boundary.  With bc = 2 every ghost point is an
+// evolved boundary point whose right-hand side is the outgoing-wave condition
+//   d_t u = -v (x^i / r) d_i u - v (u - u_inf) / r,   r = |x| (at least h/2),
+// which every u = u_inf + f(t - r/v) / r satisfies exactly.  x are the point's
+// coordinates (origin + index * h), v = sqrt(2) for the lapse under 1+log
+// slicing (its gauge speed in the asymptotic region) and 1 otherwise, u_inf
+// the flat-space value (chi, alpha and gt_ii 1, all else 0).  d_i u is the
+// second-order centred difference where both neighbours are stored points,
+// else the second-order one-sided difference into the box.  Frozen gauge
+// variables get zero, as in the interior.
+// ---------------------------------------------------------------------------
 template <class T>
-void axpy_interior(const oracle_grid& g, const T* base, T c, const T* k, T* out) {
+T asymptotic_value(int f) {
+  return (f == CHI || f == ALPHA || f == GT + 0 || f == GT + 3 || f == GT + 5) ? T(1.0) : T(0.0);
+}
+
+template <class T>
+void boundary_rhs(const oracle_params& P, const oracle_grid& g, const T* u, T* rhs) {
+  const int G = g.ghost;
+  const long st[3] = {1, g.sy, g.sz};
+  const T h = T(g.h), inv2h = Exact<T>::quot(1.0, 2.0 * g.h), half_h = h / T(2.0);
+  const T root2 = std::sqrt(T(2.0));
 #pragma omp parallel for schedule(static)
-  for (int kz = 0; kz < g.n[2]; ++kz)
+  for (int k = -G; k < g.n[2] + G; ++k)
+    for (int j = -G; j < g.n[1] + G; ++j)
+      for (int i = -G; i < g.n[0] + G; ++i) {
+        const int c[3] = {i, j, k};
+        const bool inside = i >= 0 && i < g.n[0] && j >= 0 && j < g.n[1] && k >= 0 && k < g.n[2];
+        if (inside) continue;
+        T x[3];
+        for (int a = 0; a < 3; ++a) x[a] = T(g.origin[a]) + T(double(c[a])) * h;
+        T r = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        if (r < half_h) r = half_h;
+        const long idx = at(g, i, j, k);
+        for (int f = 0; f < NGF; ++f) {
+          const bool frozen = (f == ALPHA && P.lapse == 2) || (f >= BETA && P.shift == 1);
+          if (frozen) {
+            rhs[f * g.sf + idx] = T(0.0);
+            continue;
+          }
+          const T v = (f == ALPHA && P.lapse == 0) ? root2 : T(1.0);
+          const T* p = u + f * g.sf + idx;
+          T xd = T(0.0);
+          for (int a = 0; a < 3; ++a) {
+            const long s = st[a];
+            T d;
+            if (c[a] > -G && c[a] < g.n[a] + G - 1)
+              d = (p[s] - p[-s]) * inv2h;                                   // centred
+            else if (c[a] == -G)
+              d = (T(4.0) * (p[s] - p[0]) - (p[2 * s] - p[0])) * inv2h;     // forward
+            else
+              d = -(T(4.0) * (p[-s] - p[0]) - (p[-2 * s] - p[0])) * inv2h;  // backward
+            xd = xd + x[a] * d;
+          }
+          rhs[f * g.sf + idx] = -(v * xd) / r - v * (p[0] - asymptotic_value<T>(f)) / r;
+        }
+      }
+}
+
+// the semi-discrete right-hand side: the BSSN equations at the interior
+// points, and with the radiative boundary the boundary condition at the
+// ghost points
+template <class T>
+void rhs_full(const oracle_params& P, const oracle_grid& g, const T* u, T* rhs) {
+  rhs_grid<T>(P, g, u, rhs);
+  if (P.bc == 2) boundary_rhs<T>(P, g, u, rhs);
+}
+
+// out = base + c * k at the points a step advances: the interior, and with
+// the radiative boundary the ghost points too
+template <class T>
+void axpy_points(const oracle_params& P, const oracle_grid& g, const T* base, T c, const T* k, T* out) {
+  const int G = P.bc == 2 ? g.ghost : 0;
+#pragma omp parallel for schedule(static)
+  for (int kz = -G; kz < g.n[2] + G; ++kz)
     for (int f = 0; f < NGF; ++f)
-      for (int j = 0; j < g.n[1]; ++j)
-        for (int i = 0; i < g.n[0]; ++i) {
+      for (int j = -G; j < g.n[1] + G; ++j)
+        for (int i = -G; i < g.n[0] + G; ++i) {
           const long idx = f * g.sf + at(g, i, j, kz);
           out[idx] = base[idx] + c * k[idx];
         }
 }
 
 // nsteps classic RK4 steps, u advanced in place.  Stage inputs take their
-// ghosts from u (static) or from periodic images (periodic).
+// ghosts from u (static), from periodic images (periodic) or from their own
+// boundary evolution (radiative).
 // loop_seconds (may be null) receives the wall time of the step loop alone,
 // without the allocation of the stage vectors.
 template <class T>
@@ -699,23 +773,24 @@ void rk4(const oracle_params& P, const oracle_grid& g, double dt_in, int nsteps,
   const T dt = T(dt_in), half = T(0.5), two = T(2.0), sixth = dt / T(6.0);
   std::vector<T> k1(N, T(0.0)), k2(N, T(0.0)), k3(N, T(0.0)), k4(N, T(0.0)), s(u, u + N);
   const auto t0 = std::chrono::steady_clock::now();
+  const int G = P.bc == 2 ? g.ghost : 0;
   for (int step = 0; step < nsteps; ++step) {
-    rhs_grid<T>(P, g, u, k1.data());
+    rhs_full<T>(P, g, u, k1.data());
     std::copy(u, u + N, s.begin());   // ghosts of the stage input
-    axpy_interior<T>(g, u, half * dt, k1.data(), s.data());
+    axpy_points<T>(P, g, u, half * dt, k1.data(), s.data());
     if (P.bc == 1) fill_periodic<T>(g, s.data());
-    rhs_grid<T>(P, g, s.data(), k2.data());
-    axpy_interior<T>(g, u, half * dt, k2.data(), s.data());
+    rhs_full<T>(P, g, s.data(), k2.data());
+    axpy_points<T>(P, g, u, half * dt, k2.data(), s.data());
     if (P.bc == 1) fill_periodic<T>(g, s.data());
-    rhs_grid<T>(P, g, s.data(), k3.data());
-    axpy_interior<T>(g, u, dt, k3.data(), s.data());
+    rhs_full<T>(P, g, s.data(), k3.data());
+    axpy_points<T>(P, g, u, dt, k3.data(), s.data());
     if (P.bc == 1) fill_periodic<T>(g, s.data());
-    rhs_grid<T>(P, g, s.data(), k4.data());
+    rhs_full<T>(P, g, s.data(), k4.data());
 #pragma omp parallel for schedule(static)
-    for (int kz = 0; kz < g.n[2]; ++kz)
+    for (int kz = -G; kz < g.n[2] + G; ++kz)
       for (int f = 0; f < NGF; ++f)
-        for (int j = 0; j < g.n[1]; ++j)
-          for (int i = 0; i < g.n[0]; ++i) {
+        for (int j = -G; j < g.n[1] + G; ++j)
+          for (int i = -G; i < g.n[0] + G; ++i) {
             const long idx = f * g.sf + at(g, i, j, kz);
             u[idx] = u[idx] + sixth * (k1[idx] + two * k2[idx] + two * k3[idx] + k4[idx]);
           }
@@ -738,28 +813,29 @@ void rk3(const oracle_params& P, const oracle_grid& g, double dt_in, int nsteps,
   const T dt = T(dt_in), three = T(3.0), four = T(4.0), one = T(1.0), two = T(2.0);
   const T a2 = three / four, b2 = one / four, a3 = one / three, b3 = two / three;
   std::vector<T> k(N, T(0.0)), s1(u, u + N), s2(u, u + N);
+  const int G = P.bc == 2 ? g.ghost : 0;
   for (int step = 0; step < nsteps; ++step) {
     std::copy(u, u + N, s1.begin());   // ghosts of the stage inputs
     std::copy(u, u + N, s2.begin());
-    rhs_grid<T>(P, g, u, k.data());
-    axpy_interior<T>(g, u, dt, k.data(), s1.data());
+    rhs_full<T>(P, g, u, k.data());
+    axpy_points<T>(P, g, u, dt, k.data(), s1.data());
     if (P.bc == 1) fill_periodic<T>(g, s1.data());
-    rhs_grid<T>(P, g, s1.data(), k.data());
+    rhs_full<T>(P, g, s1.data(), k.data());
 #pragma omp parallel for schedule(static)
-    for (int kz = 0; kz < g.n[2]; ++kz)
+    for (int kz = -G; kz < g.n[2] + G; ++kz)
       for (int f = 0; f < NGF; ++f)
-        for (int j = 0; j < g.n[1]; ++j)
-          for (int i = 0; i < g.n[0]; ++i) {
+        for (int j = -G; j < g.n[1] + G; ++j)
+          for (int i = -G; i < g.n[0] + G; ++i) {
             const long idx = f * g.sf + at(g, i, j, kz);
             s2[idx] = a2 * u[idx] + b2 * (s1[idx] + dt * k[idx]);
           }
     if (P.bc == 1) fill_periodic<T>(g, s2.data());
-    rhs_grid<T>(P, g, s2.data(), k.data());
+    rhs_full<T>(P, g, s2.data(), k.data());
 #pragma omp parallel for schedule(static)
-    for (int kz = 0; kz < g.n[2]; ++kz)
+    for (int kz = -G; kz < g.n[2] + G; ++kz)
       for (int f = 0; f < NGF; ++f)
-        for (int j = 0; j < g.n[1]; ++j)
-          for (int i = 0; i < g.n[0]; ++i) {
+        for (int j = -G; j < g.n[1] + G; ++j)
+          for (int i = -G; i < g.n[0] + G; ++i) {
             const long idx = f * g.sf + at(g, i, j, kz);
             u[idx] = a3 * u[idx] + b3 * (s2[idx] + dt * k[idx]);
           }
@@ -777,11 +853,13 @@ int oracle_required_ghost(int order, int upwind, int ko_radius) {
   return ko_radius > need ? ko_radius : need;
 }
 
-// Right-hand side at every interior point; ghost entries of rhs are untouched.
+// Right-hand side at every interior point and, with the radiative boundary,
+// at every ghost point; other entries of rhs (static or periodic ghosts, row
+// padding) are untouched.
 int oracle_rhs(const oracle_params* P, const oracle_grid* g, const double* u, double* rhs) {
   if (check(P, g) || !u || !rhs) return -1;
   set_threads(P);
-  rhs_grid<double>(*P, *g, u, rhs);
+  rhs_full<double>(*P, *g, u, rhs);
   return 0;
 }
 
@@ -819,11 +897,12 @@ int oracle_rhs_ext(const oracle_params* P, const oracle_grid* g, const double* u
   set_threads(P);
   const size_t N = (size_t)g->sf * NGF;
   std::vector<long double> U(u, u + N), K(N, 0.0L);
-  rhs_grid<long double>(*P, *g, U.data(), K.data());
-  for (int kz = 0; kz < g->n[2]; ++kz)
+  rhs_full<long double>(*P, *g, U.data(), K.data());
+  const int G = P->bc == 2 ? g->ghost : 0;
+  for (int kz = -G; kz < g->n[2] + G; ++kz)
     for (int f = 0; f < NGF; ++f)
-      for (int j = 0; j < g->n[1]; ++j)
-        for (int i = 0; i < g->n[0]; ++i) {
+      for (int j = -G; j < g->n[1] + G; ++j)
+        for (int i = -G; i < g->n[0] + G; ++i) {
           const long idx = f * g->sf + at(*g, i, j, kz);
           rhs[idx] = (double)K[idx];
         }

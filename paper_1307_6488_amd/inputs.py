@@ -41,7 +41,7 @@ SYM = ((0, 1, 2), (1, 3, 4), (2, 4, 5))
 
 LAPSE_ONE_PLUS_LOG, LAPSE_HARMONIC, LAPSE_FROZEN = 0, 1, 2
 SHIFT_GAMMA_DRIVER, SHIFT_FROZEN = 0, 1
-BC_STATIC, BC_PERIODIC = 0, 1
+BC_STATIC, BC_PERIODIC, BC_RADIATIVE = 0, 1, 2
 PREC_FP64, PREC_SPLIT = 0, 1
 
 
