@@ -63,6 +63,8 @@ def lib():
         L.oracle_enforce_algebraic.argtypes = [P, G, dp]
         L.oracle_momentum.argtypes = [P, G, dp, dp]
         L.oracle_mom_point.argtypes = [dp, dp, dp]
+        L.oracle_psi4.argtypes = [P, G, dp, dp]
+        L.oracle_psi4_point.argtypes = [dp, dp, dp, dp, dp]
         L.oracle_rhs_ext.argtypes = [P, G, dp, dp]
         L.oracle_rk4_ext.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
         L.oracle_fill_periodic.argtypes = [G, dp]
@@ -199,6 +201,24 @@ def momentum(params, grid, u: np.ndarray, nthreads: int = 0) -> np.ndarray:
     _ok(lib().oracle_momentum(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), _ptr(u),
                               _ptr(M)), "momentum")
     return M[(slice(None),) + grid.interior()]
+
+
+def psi4(params, grid, u: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """Psi4 at interior points, shape (2, nz, ny, nx): real and imaginary part."""
+    out = np.full((2,) + grid.shape[1:], np.nan)
+    _ok(lib().oracle_psi4(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), _ptr(u),
+                          _ptr(out)), "psi4")
+    return out[(slice(None),) + grid.interior()]
+
+
+def psi4_point(u, d1, d2, xyz):
+    """(psi4 as complex, E 3x3, B 3x3, tetrad rows e_r, e_theta, e_phi) at one
+    point from exact values and derivatives."""
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (u, d1, d2, xyz)]
+    assert arrs[0].size == NGF and arrs[1].size == NGF * 3 and arrs[2].size == NGF * 6 and arrs[3].size == 3
+    res = np.zeros(29)
+    _ok(lib().oracle_psi4_point(*[_ptr(a) for a in arrs], _ptr(res)), "psi4_point")
+    return complex(res[0], res[1]), res[2:11].reshape(3, 3), res[11:20].reshape(3, 3), res[20:29].reshape(3, 3)
 
 
 def mom_point(u, d1) -> np.ndarray:

@@ -575,6 +575,175 @@ void mom_point(const R u[NGF], const R d1[NGF][3], R M[3]) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Psi4, the Newman-Penrose Weyl scalar of outgoing radiation, from the 3+1
+// data in vacuum (the paper's second GPU workload, section "Binary Black Hole
+// Simulations with Chemora": the WeylScal4 step, timer row "Compute Psi4";
+// the paper does not print it).  With the physical metric gamma_ij = gt_ij /
+// chi, the extrinsic curvature K_ij = (At_ij + gt_ij K / 3) / chi (the sign of
+// d_t gamma_ij = -2 alpha K_ij + ...), its Ricci tensor R_ij (the one the
+// evolution uses: the conformal Ricci with the evolved Gt^i in its d Gt term,
+// plus the chi terms) and covariant derivative D:
+//   E_ij = R_ij - K_ik K^k_j + K K_ij                 (electric Weyl part)
+//   B_ij = sym_ij eps_i^kl D_k K_lj                    (magnetic Weyl part)
+// with eps_ijk = sqrt(det gamma) [ijk].  Tetrad: the coordinate vectors
+//   v1 = (-y, x, 0) (phi-like; (0, 1, 0) on the z axis),
+//   v2 = (x, y, z)  (radial; (0, 0, 1) at the origin),
+//   v3^a = gamma^ad eps_dbc v1^b v2^c (theta-like)
+// orthonormalised by Gram-Schmidt in the order v2, v3, v1 with the physical
+// metric give e_r, e_theta, e_phi; l = (n + e_r)/sqrt2 is the outgoing null
+// vector, mbar = (e_theta - i e_phi)/sqrt2 and
+//   Psi4 = (E_ij - i B_ij) mbar^i mbar^j
+//        = [ (E_tt - E_pp)/2 - B_tp ] + i [ -E_tp - (B_tt - B_pp)/2 ]
+// (t = theta, p = phi components), so that an outgoing wave h(t - r) gives
+// Psi4 = -d_t^2 h_+ + i d_t^2 h_x to linear order (h_+ = (h_tt - h_pp)/2,
+// h_x = h_tp) and an ingoing one gives zero.  Coordinates x, y, z are the
+// point's (origin + index * h).
+// ---------------------------------------------------------------------------
+template <class R>
+struct Psi4Out {
+  R re, im;
+  R E[3][3], B[3][3];
+  R tet[3][3];    // e_r, e_theta, e_phi (contravariant components)
+};
+
+template <class R>
+void psi4_point(const R u[NGF], const R d1[NGF][3], const R d2[NGF][6], const R xyz[3], Psi4Out<R>& out) {
+  Geometry<R> G;
+  geometry<R>(u, d1, d2, G);
+  const R chi = u[CHI], K = u[TRK], third = Exact<R>::ratio(1, 3), half = R(0.5);
+  R gam[3][3], gamu[3][3], Kd[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      gam[i][j] = G.gt[i][j] / chi;
+      gamu[i][j] = chi * G.gtu[i][j];
+      Kd[i][j] = (u[AT + SYM[i][j]] + G.gt[i][j] * K * third) / chi;
+    }
+  // K^i_j and its trace
+  R Km[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      R s = R(0.0);
+      for (int k = 0; k < 3; ++k) s = s + gamu[i][k] * Kd[k][j];
+      Km[i][j] = s;
+    }
+  const R trK = Km[0][0] + Km[1][1] + Km[2][2];
+  // electric part
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      R kk = R(0.0);
+      for (int k = 0; k < 3; ++k) kk = kk + Kd[i][k] * Km[k][j];
+      out.E[i][j] = G.Ric[i][j] - kk + trK * Kd[i][j];
+    }
+  // physical Christoffel symbols Gamma^k_ij = Gt^k_ij + (gt_ij gt^kl d_l chi
+  // - delta^k_i d_j chi - delta^k_j d_i chi) / (2 chi)
+  R Gam[3][3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        R gd = R(0.0);
+        for (int l = 0; l < 3; ++l) gd = gd + G.gtu[k][l] * d1[CHI][l];
+        R c = G.gt[i][j] * gd;
+        if (k == i) c = c - d1[CHI][j];
+        if (k == j) c = c - d1[CHI][i];
+        Gam[k][i][j] = G.Gu[k][i][j] + c / (R(2.0) * chi);
+      }
+  // d_k K_ij of K_ij = (At_ij + gt_ij K / 3) / chi, then D_k K_ij
+  R DK[3][3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const int s = SYM[i][j];
+        R dK = (d1[AT + s][k] + d1[GT + s][k] * K * third + G.gt[i][j] * d1[TRK][k] * third) / chi -
+               Kd[i][j] * d1[CHI][k] / chi;
+        for (int m = 0; m < 3; ++m) dK = dK - Gam[m][k][i] * Kd[m][j] - Gam[m][k][j] * Kd[i][m];
+        DK[k][i][j] = dK;
+      }
+  // Levi-Civita tensor of the physical metric
+  R detg = gam[0][0] * (gam[1][1] * gam[2][2] - gam[1][2] * gam[2][1]) -
+           gam[0][1] * (gam[1][0] * gam[2][2] - gam[1][2] * gam[2][0]) +
+           gam[0][2] * (gam[1][0] * gam[2][1] - gam[1][1] * gam[2][0]);
+  const R sq = std::sqrt(detg);
+  auto perm = [](int a, int b, int c) -> int {
+    if (a == b || b == c || a == c) return 0;
+    return ((a == 0 && b == 1) || (a == 1 && b == 2) || (a == 2 && b == 0)) ? 1 : -1;
+  };
+  R eps[3][3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c) eps[a][b][c] = R(double(perm(a, b, c))) * sq;
+  // magnetic part: eps_i^kl D_k K_lj, symmetrised
+  R Bn[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      R s = R(0.0);
+      for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+          R e = R(0.0);   // eps_i^kl = gamma^ka gamma^lb eps_iab
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) e = e + gamu[k][a] * gamu[l][b] * eps[i][a][b];
+          s = s + e * DK[k][l][j];
+        }
+      Bn[i][j] = s;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) out.B[i][j] = half * (Bn[i][j] + Bn[j][i]);
+
+  // tetrad
+  const R x = xyz[0], y = xyz[1], z = xyz[2];
+  R v1[3] = {-y, x, R(0.0)}, v2[3] = {x, y, z};
+  if (x == R(0.0) && y == R(0.0)) { v1[0] = R(0.0); v1[1] = R(1.0); }
+  if (x == R(0.0) && y == R(0.0) && z == R(0.0)) v2[2] = R(1.0);
+  R v3[3];
+  for (int a = 0; a < 3; ++a) {
+    R s = R(0.0);
+    for (int d = 0; d < 3; ++d)
+      for (int b = 0; b < 3; ++b)
+        for (int c = 0; c < 3; ++c) s = s + gamu[a][d] * eps[d][b][c] * v1[b] * v2[c];
+    v3[a] = s;
+  }
+  auto dot = [&](const R* p, const R* q) {
+    R s = R(0.0);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) s = s + gam[a][b] * p[a] * q[b];
+    return s;
+  };
+  R er[3], et[3], ep[3];
+  {
+    const R n = std::sqrt(dot(v2, v2));
+    for (int a = 0; a < 3; ++a) er[a] = v2[a] / n;
+  }
+  {
+    const R c = dot(v3, er);
+    R w[3];
+    for (int a = 0; a < 3; ++a) w[a] = v3[a] - c * er[a];
+    const R n = std::sqrt(dot(w, w));
+    for (int a = 0; a < 3; ++a) et[a] = w[a] / n;
+  }
+  {
+    const R cr = dot(v1, er), ct = dot(v1, et);
+    R w[3];
+    for (int a = 0; a < 3; ++a) w[a] = v1[a] - cr * er[a] - ct * et[a];
+    const R n = std::sqrt(dot(w, w));
+    for (int a = 0; a < 3; ++a) ep[a] = w[a] / n;
+  }
+  for (int a = 0; a < 3; ++a) {
+    out.tet[0][a] = er[a];
+    out.tet[1][a] = et[a];
+    out.tet[2][a] = ep[a];
+  }
+  auto contract = [&](R (&T)[3][3], const R* p, const R* q) {
+    R s = R(0.0);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) s = s + T[a][b] * p[a] * q[b];
+    return s;
+  };
+  const R Ett = contract(out.E, et, et), Epp = contract(out.E, ep, ep), Etp = contract(out.E, et, ep);
+  const R Btt = contract(out.B, et, et), Bpp = contract(out.B, ep, ep), Btp = contract(out.B, et, ep);
+  out.re = half * (Ett - Epp) - Btp;
+  out.im = -Etp - half * (Btt - Bpp);
+}
+
 template <class R>
 struct Point {
   R u[NGF], d1[NGF][3], d2[NGF][6], adv[NGF], diss[NGF];
@@ -986,6 +1155,67 @@ int oracle_momentum(const oracle_params* P, const oracle_grid* g, const double* 
         for (int a = 0; a < 3; ++a) M[a * G.sf + idx] = m[a];
       }
   }
+  return 0;
+}
+
+// Psi4 at every interior point into out[0 * sf + idx] (real part) and
+// out[1 * sf + idx] (imaginary part), from centred first and second
+// derivatives of the patch's order (the right-hand side's stencils) of
+// chi, gt, K, At and Gt; coordinates from the grid's origin and spacing.
+int oracle_psi4(const oracle_params* P, const oracle_grid* g, const double* u, double* out) {
+  if (check(P, g) || !u || !out) return -1;
+  set_threads(P);
+  const Weights w = make_weights(P->fd_order);
+  const oracle_grid G = *g;
+  const long st[3] = {1, G.sy, G.sz};
+  const double inv_h = 1.0 / G.h, inv_h2 = 1.0 / (G.h * G.h);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k < G.n[2]; ++k) {
+    double v[NGF], d1[NGF][3], d2[NGF][6];
+    for (int j = 0; j < G.n[1]; ++j)
+      for (int i = 0; i < G.n[0]; ++i) {
+        const long idx = at(G, i, j, k);
+        for (int f = 0; f < NGF; ++f) {
+          const double* q = u + f * G.sf + idx;
+          v[f] = q[0];
+          for (int a = 0; a < 3; ++a) d1[f][a] = 0.0;
+          for (int sl = 0; sl < 6; ++sl) d2[f][sl] = 0.0;
+          if (f >= BETA || f == ALPHA) continue;   // the gauge does not enter
+          for (int a = 0; a < 3; ++a) d1[f][a] = op_d1<double>(q, st[a], w, inv_h);
+          if (f == CHI || (f >= GT && f < GT + 6))
+            for (int sl = 0; sl < 6; ++sl) {
+              const int a = PAIR[sl][0], b = PAIR[sl][1];
+              d2[f][sl] = (a == b) ? op_d2<double>(q, st[a], w, inv_h2) : op_d11<double>(q, st[a], st[b], w, inv_h);
+            }
+        }
+        const double xyz[3] = {G.origin[0] + i * G.h, G.origin[1] + j * G.h, G.origin[2] + k * G.h};
+        Psi4Out<double> o;
+        psi4_point<double>(v, d1, d2, xyz, o);
+        out[idx] = o.re;
+        out[G.sf + idx] = o.im;
+      }
+  }
+  return 0;
+}
+
+// Psi4 at one point from caller-supplied values and derivatives (d1: 24x3,
+// d2: 24x6 in slot order xx xy xz yy yz zz) and coordinates; res receives
+// re, im, E (9, row-major), B (9) and the tetrad e_r, e_theta, e_phi (9).
+int oracle_psi4_point(const double* u, const double* d1, const double* d2, const double* xyz, double* res) {
+  if (!u || !d1 || !d2 || !xyz || !res) return -1;
+  double D1[NGF][3], D2[NGF][6];
+  std::memcpy(D1, d1, sizeof D1);
+  std::memcpy(D2, d2, sizeof D2);
+  Psi4Out<double> o;
+  psi4_point<double>(u, D1, D2, xyz, o);
+  res[0] = o.re;
+  res[1] = o.im;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      res[2 + 3 * a + b] = o.E[a][b];
+      res[11 + 3 * a + b] = o.B[a][b];
+      res[20 + 3 * a + b] = o.tet[a][b];
+    }
   return 0;
 }
 
