@@ -64,6 +64,10 @@ def lib():
         L.oracle_momentum.argtypes = [P, G, dp, dp]
         L.oracle_mom_point.argtypes = [dp, dp, dp]
         L.oracle_psi4.argtypes = [P, G, dp, dp]
+        pdp = ctypes.POINTER(dp)
+        L.oracle_sync_ghosts.argtypes = [P, G, pdp, ctypes.c_int]
+        L.oracle_restrict.argtypes = [P, G, pdp, ctypes.c_int]
+        L.oracle_steps_synced.argtypes = [P, G, pdp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int]
         L.oracle_psi4_point.argtypes = [dp, dp, dp, dp, dp]
         L.oracle_rhs_ext.argtypes = [P, G, dp, dp]
         L.oracle_rk4_ext.argtypes = [P, G, ctypes.c_double, ctypes.c_int, dp]
@@ -201,6 +205,35 @@ def momentum(params, grid, u: np.ndarray, nthreads: int = 0) -> np.ndarray:
     _ok(lib().oracle_momentum(ctypes.byref(_params(params, nthreads)), ctypes.byref(_grid(grid)), _ptr(u),
                               _ptr(M)), "momentum")
     return M[(slice(None),) + grid.interior()]
+
+
+def _many(grids, states):
+    gs = (_Grid * len(grids))(*[_grid(g) for g in grids])
+    ptrs = (ctypes.POINTER(ctypes.c_double) * len(states))(*[_ptr(s) for s in states])
+    return gs, ptrs
+
+
+def sync_ghosts(params, grids, states, nthreads: int = 0) -> None:
+    """Refill the ghost points of several patches in place from the patches of
+    the same and the next coarser refinement level."""
+    gs, ptrs = _many(grids, states)
+    _ok(lib().oracle_sync_ghosts(ctypes.byref(_params(params, nthreads)), gs, ptrs, len(grids)), "sync_ghosts")
+
+
+def restrict(params, grids, states) -> None:
+    """Finer interior values injected into coincident coarse interior points, in place."""
+    gs, ptrs = _many(grids, states)
+    _ok(lib().oracle_restrict(ctypes.byref(_params(params)), gs, ptrs, len(grids)), "restrict")
+
+
+def steps_synced(params, grids, states, dt: float, nsteps: int, integrator: int = 4, nthreads: int = 0):
+    """Copies of the patch states advanced together by nsteps RK4 (integrator
+    4) or SSP RK3 (3) steps with one dt, ghosts refilled after every stage."""
+    out = [np.ascontiguousarray(s.copy()) for s in states]
+    gs, ptrs = _many(grids, out)
+    _ok(lib().oracle_steps_synced(ctypes.byref(_params(params, nthreads)), gs, ptrs, len(grids), dt, nsteps,
+                                  integrator), "steps_synced")
+    return out
 
 
 def psi4(params, grid, u: np.ndarray, nthreads: int = 0) -> np.ndarray:

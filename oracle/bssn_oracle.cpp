@@ -1012,6 +1012,281 @@ void rk3(const oracle_params& P, const oracle_grid& g, double dt_in, int nsteps,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Several patches advanced together (the paper's framework owns ghost-zone
+// synchronisation between grid sections, refinement and multi-block,
+// section "Cactus-Carpet Computational Infrastructure"; its conclusion names
+// adaptive mesh refinement and multi-block as the next step).  Reading:
+//  * patches sit on refinement levels, h_L = h_0 / 2^L with h_0 the coarsest
+//    spacing, vertex-centred (a level-L point with even global index along an
+//    axis coincides with a level-(L-1) point); every origin lies on its
+//    level's lattice through the first coarsest patch's origin;
+//  * all patches take the same time step (no subcycling);
+//  * after every Runge-Kutta stage the ghost points of every stage output are
+//    refilled, level by level from the coarsest: a ghost point inside the
+//    interior of another patch of its level takes that value (the lowest
+//    such patch); otherwise on a refined level it is prolongated from the
+//    first patch of the next coarser level whose stored box holds the whole
+//    interpolation stencil -- per axis, the coincident coarse point, or for a
+//    midpoint the order-p Lagrange interpolation of the p coarse points
+//    around it (p = the finite-difference order; tensor product over the
+//    axes); otherwise (coarsest level only) it is an outer-boundary point
+//    and keeps the patch's own boundary treatment;
+//  * at the end of every step, and once before the first, coarse interior
+//    points that coincide with a finer level's interior point take its value
+//    (injection, finest level first), then the ghosts are refilled.
+// ---------------------------------------------------------------------------
+struct HPatch {
+  oracle_grid g;
+  int level;
+  long I0[3];   // global index of interior point (0,0,0) on its level's lattice
+};
+
+int make_hierarchy(const oracle_grid* gs, int np, std::vector<HPatch>& H) {
+  if (np < 1) return -1;
+  double h0 = 0.0;
+  for (int p = 0; p < np; ++p) h0 = std::max(h0, gs[p].h);
+  H.resize(np);
+  int first = -1;
+  for (int p = 0; p < np; ++p) {
+    const double ratio = h0 / gs[p].h;
+    const int L = (int)std::lround(std::log2(ratio));
+    if (L < 0 || L > 20 || std::fabs(std::ldexp(h0, -L) - gs[p].h) > 1e-12 * gs[p].h) return -1;
+    H[p].g = gs[p];
+    H[p].level = L;
+    if (L == 0 && first < 0) first = p;
+  }
+  for (int p = 0; p < np; ++p)
+    for (int a = 0; a < 3; ++a) {
+      const double q = (gs[p].origin[a] - gs[first].origin[a]) / gs[p].h;
+      const long I = std::lround(q);
+      if (std::fabs(q - (double)I) > 1e-9) return -1;
+      H[p].I0[a] = I;
+    }
+  return 0;
+}
+
+bool in_interior(const HPatch& q, const long* I) {
+  for (int a = 0; a < 3; ++a)
+    if (I[a] < q.I0[a] || I[a] >= q.I0[a] + q.g.n[a]) return false;
+  return true;
+}
+
+bool in_stored_box(const HPatch& q, long lo, long hi, int a) {
+  return lo >= q.I0[a] - q.g.ghost && hi < q.I0[a] + q.g.n[a] + q.g.ghost;
+}
+
+// Lagrange weights of the p points at offsets -p/2+1 .. p/2 for the midpoint
+// between offsets 0 and 1 (exact binary fractions: numerator and denominator
+// are formed exactly, then divided once)
+void midpoint_weights(int p, double* w) {
+  const int m = p / 2;
+  for (int k = -m + 1; k <= m; ++k) {
+    double num = 1.0, den = 1.0;
+    for (int j = -m + 1; j <= m; ++j) {
+      if (j == k) continue;
+      num *= 0.5 - j;
+      den *= (double)(k - j);
+    }
+    w[k + m - 1] = num / den;
+  }
+}
+
+// refill the ghost points of every patch (states: one state per patch)
+template <class T>
+int sync_ghosts(const std::vector<HPatch>& H, int order, T* const* st) {
+  int maxL = 0;
+  for (const HPatch& q : H) maxL = std::max(maxL, q.level);
+  double wmid[8];
+  midpoint_weights(order, wmid);
+  const int m = order / 2;
+  int bad = 0;
+  for (int L = 0; L <= maxL; ++L)
+    for (size_t p = 0; p < H.size(); ++p) {
+      const HPatch& P = H[p];
+      if (P.level != L) continue;
+      const oracle_grid& g = P.g;
+      const int G = g.ghost;
+      for (int k = -G; k < g.n[2] + G; ++k)
+        for (int j = -G; j < g.n[1] + G; ++j)
+          for (int i = -G; i < g.n[0] + G; ++i) {
+            if (i >= 0 && i < g.n[0] && j >= 0 && j < g.n[1] && k >= 0 && k < g.n[2]) continue;
+            const long gI[3] = {P.I0[0] + i, P.I0[1] + j, P.I0[2] + k};
+            T* dst = st[p] + at(g, i, j, k);
+            // same level
+            int src = -1;
+            for (size_t q = 0; q < H.size() && src < 0; ++q)
+              if (q != p && H[q].level == L && in_interior(H[q], gI)) src = (int)q;
+            if (src >= 0) {
+              const HPatch& Q = H[src];
+              const T* s = st[src] + at(Q.g, (int)(gI[0] - Q.I0[0]), (int)(gI[1] - Q.I0[1]), (int)(gI[2] - Q.I0[2]));
+              for (int f = 0; f < NGF; ++f) dst[f * g.sf] = s[f * Q.g.sf];
+              continue;
+            }
+            if (L == 0) continue;   // outer boundary
+            // prolongation from level L-1: per axis the coarse taps
+            long lo[3], hi[3];
+            bool mid[3];
+            for (int a = 0; a < 3; ++a) {
+              // even global index: the coincident coarse point; odd: the
+              // midpoint between coarse points (gI - 1)/2 and (gI + 1)/2
+              // (exact divisions of even numbers, negative ones included)
+              mid[a] = (gI[a] % 2 + 2) % 2 == 1;
+              if (mid[a]) {
+                const long left = (gI[a] - 1) / 2;
+                lo[a] = left - m + 1;
+                hi[a] = left + m;
+              } else {
+                lo[a] = hi[a] = gI[a] / 2;
+              }
+            }
+            int cq = -1;
+            for (size_t q = 0; q < H.size() && cq < 0; ++q) {
+              if (H[q].level != L - 1) continue;
+              bool ok = true;
+              for (int a = 0; a < 3; ++a) ok = ok && in_stored_box(H[q], lo[a], hi[a], a);
+              if (ok) cq = (int)q;
+            }
+            if (cq < 0) {
+              ++bad;
+              continue;
+            }
+            const HPatch& Q = H[cq];
+            for (int f = 0; f < NGF; ++f) {
+              T acc = T(0.0);
+              for (long c2 = lo[2]; c2 <= hi[2]; ++c2)
+                for (long c1 = lo[1]; c1 <= hi[1]; ++c1)
+                  for (long c0 = lo[0]; c0 <= hi[0]; ++c0) {
+                    const T w0 = mid[0] ? T(wmid[c0 - lo[0]]) : T(1.0);
+                    const T w1 = mid[1] ? T(wmid[c1 - lo[1]]) : T(1.0);
+                    const T w2 = mid[2] ? T(wmid[c2 - lo[2]]) : T(1.0);
+                    const T v = st[cq][f * Q.g.sf + at(Q.g, (int)(c0 - Q.I0[0]), (int)(c1 - Q.I0[1]),
+                                                      (int)(c2 - Q.I0[2]))];
+                    acc = acc + w0 * w1 * w2 * v;
+                  }
+              dst[f * g.sf] = acc;
+            }
+          }
+    }
+  return bad ? -1 : 0;
+}
+
+// coarse interior points that coincide with a finer level's interior point
+// take its value, finest level first
+template <class T>
+void restrict_levels(const std::vector<HPatch>& H, T* const* st) {
+  int maxL = 0;
+  for (const HPatch& q : H) maxL = std::max(maxL, q.level);
+  for (int L = maxL; L >= 1; --L)
+    for (size_t c = 0; c < H.size(); ++c) {
+      const HPatch& C = H[c];
+      if (C.level != L - 1) continue;
+      for (int k = 0; k < C.g.n[2]; ++k)
+        for (int j = 0; j < C.g.n[1]; ++j)
+          for (int i = 0; i < C.g.n[0]; ++i) {
+            const long fI[3] = {2 * (C.I0[0] + i), 2 * (C.I0[1] + j), 2 * (C.I0[2] + k)};
+            for (size_t q = 0; q < H.size(); ++q) {
+              if (H[q].level != L || !in_interior(H[q], fI)) continue;
+              const HPatch& F = H[q];
+              const T* s = st[q] + at(F.g, (int)(fI[0] - F.I0[0]), (int)(fI[1] - F.I0[1]), (int)(fI[2] - F.I0[2]));
+              T* d = st[c] + at(C.g, i, j, k);
+              for (int f = 0; f < NGF; ++f) d[f * C.g.sf] = s[f * F.g.sf];
+              break;
+            }
+          }
+    }
+}
+
+// nsteps RK4 (rk3 = false) or SSP RK3 steps of every patch with one dt,
+// ghosts refilled after every stage, restriction and refill after every step
+// (and once before the first)
+template <class T>
+int steps_synced(const oracle_params& P, const std::vector<HPatch>& H, T* const* u, double dt_in, int nsteps,
+                 bool rk3) {
+  const int np = (int)H.size();
+  restrict_levels<T>(H, u);
+  if (sync_ghosts<T>(H, P.fd_order, u)) return -1;
+  const T dt = T(dt_in), half = T(0.5), two = T(2.0), sixth = dt / T(6.0);
+  const T a2 = T(3.0) / T(4.0), b2 = T(1.0) / T(4.0), a3 = T(1.0) / T(3.0), b3 = T(2.0) / T(3.0);
+  std::vector<std::vector<T>> k1(np), k2(np), k3(np), k4(np), s(np), s2(np);
+  std::vector<T*> sp(np), s2p(np);
+  for (int p = 0; p < np; ++p) {
+    const size_t N = (size_t)H[p].g.sf * NGF;
+    k1[p].assign(N, T(0.0));
+    k2[p].assign(N, T(0.0));
+    k3[p].assign(N, T(0.0));
+    k4[p].assign(N, T(0.0));
+    s[p].assign(N, T(0.0));
+    s2[p].assign(N, T(0.0));
+    sp[p] = s[p].data();
+    s2p[p] = s2[p].data();
+  }
+  for (int step = 0; step < nsteps; ++step) {
+    for (int p = 0; p < np; ++p) {
+      const oracle_grid& g = H[p].g;
+      const size_t N = (size_t)g.sf * NGF;
+      std::copy(u[p], u[p] + N, s[p].begin());   // static ghosts of the stage inputs
+      std::copy(u[p], u[p] + N, s2[p].begin());
+      rhs_full<T>(P, g, u[p], k1[p].data());
+      axpy_points<T>(P, g, u[p], rk3 ? dt : half * dt, k1[p].data(), s[p].data());
+    }
+    if (sync_ghosts<T>(H, P.fd_order, sp.data())) return -1;
+    if (!rk3) {
+      for (int p = 0; p < np; ++p) {
+        rhs_full<T>(P, H[p].g, s[p].data(), k2[p].data());
+        axpy_points<T>(P, H[p].g, u[p], half * dt, k2[p].data(), s[p].data());
+      }
+      if (sync_ghosts<T>(H, P.fd_order, sp.data())) return -1;
+      for (int p = 0; p < np; ++p) {
+        rhs_full<T>(P, H[p].g, s[p].data(), k3[p].data());
+        axpy_points<T>(P, H[p].g, u[p], dt, k3[p].data(), s[p].data());
+      }
+      if (sync_ghosts<T>(H, P.fd_order, sp.data())) return -1;
+      for (int p = 0; p < np; ++p) {
+        const oracle_grid& g = H[p].g;
+        rhs_full<T>(P, g, s[p].data(), k4[p].data());
+        const int G = P.bc == 2 ? g.ghost : 0;
+        for (int kz = -G; kz < g.n[2] + G; ++kz)
+          for (int f = 0; f < NGF; ++f)
+            for (int j = -G; j < g.n[1] + G; ++j)
+              for (int i = -G; i < g.n[0] + G; ++i) {
+                const long idx = f * g.sf + at(g, i, j, kz);
+                u[p][idx] = u[p][idx] + sixth * (k1[p][idx] + two * k2[p][idx] + two * k3[p][idx] + k4[p][idx]);
+              }
+      }
+    } else {
+      for (int p = 0; p < np; ++p) {
+        const oracle_grid& g = H[p].g;
+        rhs_full<T>(P, g, s[p].data(), k2[p].data());
+        const int G = P.bc == 2 ? g.ghost : 0;
+        for (int kz = -G; kz < g.n[2] + G; ++kz)
+          for (int f = 0; f < NGF; ++f)
+            for (int j = -G; j < g.n[1] + G; ++j)
+              for (int i = -G; i < g.n[0] + G; ++i) {
+                const long idx = f * g.sf + at(g, i, j, kz);
+                s2[p][idx] = a2 * u[p][idx] + b2 * (s[p][idx] + dt * k2[p][idx]);
+              }
+      }
+      if (sync_ghosts<T>(H, P.fd_order, s2p.data())) return -1;
+      for (int p = 0; p < np; ++p) {
+        const oracle_grid& g = H[p].g;
+        rhs_full<T>(P, g, s2[p].data(), k3[p].data());
+        const int G = P.bc == 2 ? g.ghost : 0;
+        for (int kz = -G; kz < g.n[2] + G; ++kz)
+          for (int f = 0; f < NGF; ++f)
+            for (int j = -G; j < g.n[1] + G; ++j)
+              for (int i = -G; i < g.n[0] + G; ++i) {
+                const long idx = f * g.sf + at(g, i, j, kz);
+                u[p][idx] = a3 * u[p][idx] + b3 * (s2[p][idx] + dt * k3[p][idx]);
+              }
+      }
+    }
+    restrict_levels<T>(H, u);
+    if (sync_ghosts<T>(H, P.fd_order, u)) return -1;
+  }
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1099,6 +1374,44 @@ int oracle_rk3_ext(const oracle_params* P, const oracle_grid* g, double dt, int 
   rk3<long double>(*P, *g, dt, nsteps, U.data());
   for (size_t i = 0; i < N; ++i) u[i] = (double)U[i];
   return 0;
+}
+
+// Several patches (grids[p], states[p]): refill every ghost point from the
+// patches of the same or the next coarser level (see sync_ghosts).  -1 if
+// the spacings or origins do not form a hierarchy, or a refined patch has a
+// ghost point neither source covers.
+int oracle_sync_ghosts(const oracle_params* P, const oracle_grid* grids, double* const* states, int npatch) {
+  if (!P || !grids || !states || npatch < 1) return -1;
+  std::vector<HPatch> H;
+  if (make_hierarchy(grids, npatch, H)) return -1;
+  for (int p = 0; p < npatch; ++p)
+    if (check(P, &grids[p]) || !states[p]) return -1;
+  return sync_ghosts<double>(H, P->fd_order, states);
+}
+
+// Injection of finer interior points into coincident coarse interior points.
+int oracle_restrict(const oracle_params* P, const oracle_grid* grids, double* const* states, int npatch) {
+  if (!P || !grids || !states || npatch < 1) return -1;
+  std::vector<HPatch> H;
+  if (make_hierarchy(grids, npatch, H)) return -1;
+  restrict_levels<double>(H, states);
+  return 0;
+}
+
+// nsteps RK4 (integrator 4) or SSP RK3 (integrator 3) steps of all patches
+// together with one dt: ghosts refilled after every stage, restriction and
+// refill after every step and once before the first.  Periodic boundaries
+// are not combined with several patches (-1).
+int oracle_steps_synced(const oracle_params* P, const oracle_grid* grids, double* const* states, int npatch,
+                        double dt, int nsteps, int integrator) {
+  if (!P || !grids || !states || npatch < 1 || !(dt > 0.0) || nsteps < 0) return -1;
+  if (P->bc == 1 || (integrator != 3 && integrator != 4)) return -1;
+  std::vector<HPatch> H;
+  if (make_hierarchy(grids, npatch, H)) return -1;
+  for (int p = 0; p < npatch; ++p)
+    if (check(P, &grids[p]) || !states[p]) return -1;
+  set_threads(P);
+  return steps_synced<double>(*P, H, states, dt, nsteps, integrator == 3);
 }
 
 int oracle_fill_periodic(const oracle_grid* g, double* u) {
