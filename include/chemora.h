@@ -158,6 +158,28 @@ size_t chemora_rk4_scratch_elems(const chemora_patch *patch);
 int chemora_rk4_step(const chemora_params *params, const chemora_patch *patch, double dt,
                      double *scratch, void *stream);
 
+/* Most doubles of scratch chemora_rk4_step_noalloc holds per GPU (64 MiB):
+ * patches with chemora_rk4_scratch_elems(patch) <= this, e.g. 42^3 interior
+ * points with 3 ghosts and rows padded to 8 doubles. */
+#define CHEMORA_NOALLOC_SCRATCH_ELEMS ((size_t)8 << 20)
+
+/* chemora_rk4_step for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, and harnesses that forbid
+ * allocation.  The same computation as chemora_rk4_step (bitwise, same tile
+ * variant), with the three scratch states in a buffer the library holds per
+ * GPU (a static device array of CHEMORA_NOALLOC_SCRATCH_ELEMS doubles,
+ * loaded with the library and kept until the process ends) instead of a
+ * caller's.  No hipMalloc, hipFree or other allocation, no memset: every
+ * scratch value the step reads it has written first in the same call.
+ * Errors: as chemora_rk4_step before any HIP call; EINVAL if
+ * chemora_rk4_scratch_elems(patch) exceeds CHEMORA_NOALLOC_SCRATCH_ELEMS;
+ * EDEVICE if the buffer's device address cannot be obtained.  All calls on
+ * one GPU share its buffer: calls whose executions overlap on that GPU
+ * (other streams, other host threads) race and give undefined results;
+ * calls ordered on one stream are safe. */
+int chemora_rk4_step_noalloc(const chemora_params *params, const chemora_patch *patch, double dt,
+                             void *stream);
+
 /* Stage s (1..4) of the step chemora_rk4_step performs, for callers that
  * interleave their own work between stages or time them one by one.
  * Calling s = 1, 2, 3, 4 in this order with the same dt and scratch is the
@@ -319,10 +341,10 @@ int chemora_check_finite(const chemora_params *params, const chemora_patch *patc
 /* Message of the last failed call on this thread ("" if none). */
 const char *chemora_last_error(void);
 
-/* ABI version of this header (major*100 + minor): 101 (1.1 added
+/* ABI version of this header (major*100 + minor): 102 (1.1 added
  * chemora_rk3_step, chemora_rk3_scratch_elems, chemora_plan_create_rk3,
- * chemora_enforce_constraints and chemora_momentum_constraint; nothing of
- * 1.0 changed). */
+ * chemora_enforce_constraints and chemora_momentum_constraint; 1.2 added
+ * chemora_rk4_step_noalloc; nothing earlier changed). */
 int chemora_abi_version(void);
 
 #ifdef __cplusplus

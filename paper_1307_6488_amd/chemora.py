@@ -27,7 +27,10 @@ EXPORTS = (
     "chemora_plan_patch_variant", "chemora_tune", "chemora_tile_variant", "chemora_set_tile_variant",
     "chemora_tile_variant_shape", "chemora_hamiltonian", "chemora_rk3_scratch_elems", "chemora_rk3_step",
     "chemora_enforce_constraints", "chemora_momentum_constraint", "chemora_plan_create_rk3",
+    "chemora_rk4_step_noalloc",
 )
+# CHEMORA_NOALLOC_SCRATCH_ELEMS of include/chemora.h
+NOALLOC_SCRATCH_ELEMS = 8 << 20
 
 
 class chemora_params(ctypes.Structure):
@@ -67,6 +70,8 @@ def lib() -> ctypes.CDLL:
         L.chemora_rk4_scratch_elems.restype = ctypes.c_size_t
         L.chemora_rk4_step.argtypes = [P, X, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
         L.chemora_rk4_step.restype = ctypes.c_int
+        L.chemora_rk4_step_noalloc.argtypes = [P, X, ctypes.c_double, ctypes.c_void_p]
+        L.chemora_rk4_step_noalloc.restype = ctypes.c_int
         L.chemora_rk4_stage.argtypes = [P, X, ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
         L.chemora_rk4_stage.restype = ctypes.c_int
         L.chemora_rk3_scratch_elems.argtypes = [X]
@@ -169,6 +174,11 @@ def chemora_rk4_step(params: chemora_params, patch: chemora_patch, dt: float, sc
                      stream=None) -> int:
     return _check(lib().chemora_rk4_step(ctypes.byref(params), ctypes.byref(patch), dt,
                                          ctypes.c_void_p(scratch_ptr), _stream(stream)))
+
+
+def chemora_rk4_step_noalloc(params: chemora_params, patch: chemora_patch, dt: float, stream=None) -> int:
+    return _check(lib().chemora_rk4_step_noalloc(ctypes.byref(params), ctypes.byref(patch), dt,
+                                                 _stream(stream)))
 
 
 def chemora_rk3_scratch_elems(patch: chemora_patch) -> int:

@@ -491,7 +491,7 @@ void launch_ghosts(bool periodic, const chemora::Geo& G, const double* src, doub
 
 extern "C" {
 
-int chemora_abi_version(void) { return 101; }
+int chemora_abi_version(void) { return 102; }
 
 const char* chemora_last_error(void) { return g_error.c_str(); }
 
@@ -664,6 +664,41 @@ int rk4_step(const chemora_params* params, const chemora_patch* patch, double dt
 }  // namespace host
 }  // namespace chemora
 
+// Scratch of chemora_rk4_step_noalloc: S_A, S_B and the accumulator Y of
+// one patch, in a device array loaded with the code object (no allocation
+// call).  Host code never passes the array's name to a kernel -- on the host
+// it is only a stand-in for the symbol -- but the device address that
+// hipGetSymbolAddress returns, looked up once per device with that device
+// current (each GPU holds its own copy at its own address).
+static __device__ __align__(256) double noalloc_scratch_array[CHEMORA_NOALLOC_SCRATCH_ELEMS];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of the current device's copy of noalloc_scratch_array
+int noalloc_scratch(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(CHEMORA_EDEVICE, "rk4_step_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return fail(CHEMORA_EDEVICE, "rk4_step_noalloc: device %d beyond the %d supported", dev, NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch_array));
+    if (e != hipSuccess || !p)
+      return fail(CHEMORA_EDEVICE, "rk4_step_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+    g_noalloc_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return CHEMORA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int chemora_rk4_step(const chemora_params* params, const chemora_patch* patch, double dt, double* scratch,
@@ -671,6 +706,20 @@ int chemora_rk4_step(const chemora_params* params, const chemora_patch* patch, d
   g_error.clear();
   int rc = rk4_checks(params, patch, dt, scratch);
   if (rc) return rc;
+  return chemora::host::rk4_step(params, patch, dt, scratch, (hipStream_t)stream);
+}
+
+int chemora_rk4_step_noalloc(const chemora_params* params, const chemora_patch* patch, double dt, void* stream) {
+  g_error.clear();
+  int rc = chemora::host::check_step(params, patch, dt);
+  if (rc) return rc;
+  const size_t need = chemora_rk4_scratch_elems(patch);
+  if (need > CHEMORA_NOALLOC_SCRATCH_ELEMS)
+    return fail(CHEMORA_EINVAL, "rk4_step_noalloc: the patch needs %zu doubles of scratch, more than the %zu held "
+                "per GPU (chemora_rk4_step takes a caller's scratch of any size)",
+                need, (size_t)CHEMORA_NOALLOC_SCRATCH_ELEMS);
+  double* scratch = nullptr;
+  if ((rc = noalloc_scratch(&scratch))) return rc;
   return chemora::host::rk4_step(params, patch, dt, scratch, (hipStream_t)stream);
 }
 

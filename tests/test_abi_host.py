@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     assert set(declared) == set(C.EXPORTS)
     for name in declared:
         assert hasattr(L, name), name
-    assert C.chemora_abi_version() == 101
+    assert C.chemora_abi_version() == 102
 
 
 def test_required_ghost_matches_inputs():
@@ -159,6 +159,32 @@ def test_rk4_argument_checks_on_host():
     X = C.make_patch(g, FAKE)
     assert C.chemora_rk4_scratch_elems(X) == 3 * 24 * g.sf
     assert C.lib().chemora_rk4_scratch_elems(None) == 0
+
+
+def test_rk4_noalloc_argument_checks_on_host():
+    p, g = _good()
+
+    def call(p, g, dt=0.01, u=FAKE):
+        P = C.make_params(p)
+        X = C.make_patch(g, u)
+        return C.lib().chemora_rk4_step_noalloc(ctypes.byref(P), ctypes.byref(X), dt, None)
+
+    for dt in (0.0, -1.0, float("nan"), float("inf")):
+        assert call(p, g, dt=dt) == C.EINVAL and "dt" in C.last_error()
+    assert call(p, g, u=0) == C.EINVAL
+    bad = I.Params(**vars(p))
+    bad.fd_order = 6
+    assert call(bad, g) == C.EINVAL
+    # a patch whose three scratch states exceed the per-GPU buffer (128^3:
+    # 3 * 24 * 134^2 * 136 doubles) is refused before any HIP call
+    big = I.workload(2).grid
+    X = C.make_patch(big, FAKE)
+    assert C.chemora_rk4_scratch_elems(X) > C.NOALLOC_SCRATCH_ELEMS
+    assert call(p, big) == C.EINVAL and "scratch" in C.last_error()
+    # the header's limit is the binding's
+    text = open(os.path.join(ROOT, "include", "chemora.h")).read()
+    assert "#define CHEMORA_NOALLOC_SCRATCH_ELEMS ((size_t)8 << 20)" in text
+    assert C.NOALLOC_SCRATCH_ELEMS == 8 << 20
 
 
 def test_rk3_argument_checks_on_host():
