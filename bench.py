@@ -235,6 +235,11 @@ def main():
         out["batched"] = batched_form(C, I, torch, args.no_tune)
     if not args.no_split:
         out["split"] = split_form(C, I, torch, args.no_tune, steps=args.split_steps)
+    if not args.no_rk3:
+        out["bbh_share"] = bbh_share_form(C, I, torch, args.no_tune)
+    if not args.no_batched:
+        out["synced"] = synced_form(C, I, torch)
+    out["boundary_and_psi4"] = boundary_psi4_form(C, I, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, u0, I)
     print(json.dumps(out), flush=True)
@@ -475,6 +480,120 @@ def split_form(C, I, torch, no_tune, steps=100, warmup=2):
             "max_err_vs_fp64": float(err[worst]), "worst_gf": I.GF_NAMES[worst],
             "err_per_gf": {n: float(e) for n, e in zip(I.GF_NAMES, err)},
             "h_rms_fp64": h64, "h_rms_split": hsp, "h_rms_ratio": hsp / h64 if h64 > 0 else None}
+
+
+def bbh_share_form(C, I, torch, no_tune, steps=20, warmup=2):
+    """One GPU's share of the paper's production run: 90^3 interior points,
+    5 ghost zones, 8th-order partially upwinded stencils, third-order
+    Runge-Kutta (3 stage launches, 8 state transfers = 1536 algorithmic
+    bytes per update), the share holding a puncture."""
+    w = I.bbh_share()
+    P = C.Patch(w.params, w.grid, w.make_state())
+    stream = torch.cuda.current_stream()
+    variant = C.chemora_tile_variant(P.params, P.patch) if no_tune else P.tune(None, stream)
+    P.rk3_step(w.dt, warmup)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    P.rk3_step(w.dt, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    npts = w.grid.npoints
+    tile = C.chemora_tile_variant_shape(variant)
+    del P
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "interior": list(w.grid.n), "ghost": w.params.ghost, "fd_order": 8,
+            "integrator": "SSP RK3", "steps": steps, "ms_per_step": ms, "value": npts / (ms * 1e-3),
+            "unit": "updates/s", "tile": f"{tile[0]}x{tile[1]}", "algorithmic_bytes_per_update": 1536,
+            "hbm_frac": npts / (ms * 1e-3) * 1536 / (HBM_PEAK_GBS * 1e9)}
+
+
+def _hierarchy(I, n0=48, nf=48, ghost=3):
+    """A two-level grid hierarchy: the coarse level (h = 1/4) as a 2 x 2 x 2
+    block split of a (2 n0)^3 grid, and one refined patch (h = 1/8) of nf^3
+    points round each puncture of the Brill-Lindquist data (punctures at
+    x = +-3)."""
+    hc, hf = 0.25, 0.125
+    L = 2 * n0 * hc
+    o = -L / 2 + hc / 2
+    grids = []
+    for bz in range(2):
+        for by in range(2):
+            for bx in range(2):
+                grids.append(I.Grid((n0, n0, n0), ghost, hc, (o + bx * n0 * hc, o + by * n0 * hc, o + bz * n0 * hc)))
+    for cx in (3.0, -3.0):
+        # fine origin on the fine lattice through the coarse origin
+        k = round((cx - (nf - 1) * hf / 2 - o) / hf)
+        ky = round((0.0 - (nf - 1) * hf / 2 - o) / hf)
+        grids.append(I.Grid((nf, nf, nf), ghost, hf, (o + k * hf, o + ky * hf, o + ky * hf)))
+    return grids
+
+
+def synced_form(C, I, torch, steps=10, warmup=2):
+    """A synchronised plan over a two-level hierarchy (8 coarse blocks of
+    48^3 at h = 1/4, two refined 48^3 patches at h = 1/8 round the punctures;
+    order 4 upwind, static outer ghosts, one dt = h_fine / 4): ghost exchange,
+    prolongation after every RK4 stage and restriction after every step, all
+    inside the captured graph.  Reported beside the same patches as an
+    independent plan (no exchange) to show the synchronisation's cost."""
+    grids = _hierarchy(I)
+    params = I.workload(2).params
+    states = [I.brill_lindquist(g) for g in grids]
+    npts = sum(g.npoints for g in grids)
+    dt = 0.25 * 0.125
+    out = {"workload": "two-level hierarchy: 8 x 48^3 (h 1/4) + 2 x 48^3 (h 1/8), order 4 upwind, RK4",
+           "patches": len(grids), "points": npts, "steps": steps}
+    for name, kw in (("synced", {"synced_dt": dt}), ("independent", {"courant": dt / 0.125})):
+        B = C.Batch(params, grids, states, **kw)
+        B.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        B.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        B.close()
+        out[name] = {"ms_per_step": ms, "value": npts / (ms * 1e-3)}
+    out["unit"] = "updates/s"
+    out["sync_overhead"] = out["synced"]["ms_per_step"] / out["independent"]["ms_per_step"] - 1.0
+    torch.cuda.empty_cache()
+    return out
+
+
+def boundary_psi4_form(C, I, torch, reps=10):
+    """The 128^3 workload's RK4 step with the radiative outer boundary (one
+    extra launch per stage evolving the ghost points) against static ghosts,
+    and the Psi4 diagnostic on the same state (ms per call)."""
+    w = I.workload(2)
+    u0 = w.make_state()
+    out = {"workload": w.name}
+    for name, bc in (("static", I.BC_STATIC), ("radiative", I.BC_RADIATIVE)):
+        p = I.Params(**vars(w.params))
+        p.bc = bc
+        P = C.Patch(p, w.grid, u0)
+        P.rk4_step(w.dt, 1)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        P.rk4_step(w.dt, reps)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_step": e0.elapsed_time(e1) / reps}
+        if bc == I.BC_STATIC:
+            P.psi4()
+            e0.record()
+            for _ in range(reps):
+                P.psi4()
+            e1.record()
+            torch.cuda.synchronize()
+            out["psi4_ms_per_call"] = e0.elapsed_time(e1) / reps
+        del P
+        torch.cuda.empty_cache()
+    out["radiative_overhead"] = out["radiative"]["ms_per_step"] / out["static"]["ms_per_step"] - 1.0
+    return out
 
 
 def _tune_cache():

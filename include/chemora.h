@@ -40,8 +40,10 @@
  *     stencil staging moves pairs of doubles and may read one element of
  *     row padding), sz >= sy*(n[1] + 2g), sf >= sz*(n[2] + 2g),
  *     24*sf*8 + 64 bytes <= 4 GiB (32-bit byte offsets), every pointer
- *     8-byte aligned.  Row padding and the 3-D ghost corners never affect a
- *     result (they may be read, never written; NaN there is harmless).
+ *     8-byte aligned.  Row padding never affects a result, nor do the 3-D
+ *     ghost corners with static or periodic boundaries (they may be read,
+ *     never written; NaN there is harmless).  With the radiative boundary
+ *     every ghost point, corners included, is an evolved point.
  * GF order: 0 chi | 1-6 gt_xx gt_xy gt_xz gt_yy gt_yz gt_zz | 7 K |
  *           8-13 At_xx..At_zz | 14-16 Gt^x Gt^y Gt^z | 17 alpha |
  *           18-20 beta^x beta^y beta^z | 21-23 B^x B^y B^z.
@@ -68,7 +70,7 @@ typedef enum {
 enum { CHEMORA_NGF = 24 };
 enum { CHEMORA_LAPSE_ONE_PLUS_LOG = 0, CHEMORA_LAPSE_HARMONIC = 1, CHEMORA_LAPSE_FROZEN = 2 };
 enum { CHEMORA_SHIFT_GAMMA_DRIVER = 0, CHEMORA_SHIFT_FROZEN = 1 };
-enum { CHEMORA_BC_STATIC = 0, CHEMORA_BC_PERIODIC = 1 };
+enum { CHEMORA_BC_STATIC = 0, CHEMORA_BC_PERIODIC = 1, CHEMORA_BC_RADIATIVE = 2 };
 enum { CHEMORA_PREC_FP64 = 0, CHEMORA_PREC_SPLIT = 1 };
 
 /* Discretisation and gauge parameters.  This is the kernel descriptor of
@@ -86,7 +88,19 @@ typedef struct chemora_params {
   int32_t lapse;      /* CHEMORA_LAPSE_*                                     */
   int32_t shift;      /* CHEMORA_SHIFT_*                                     */
   double eta;         /* Gamma-driver damping                                */
-  int32_t bc;         /* CHEMORA_BC_*: ghost treatment inside rk4_step       */
+  int32_t bc;         /* CHEMORA_BC_*: ghost treatment inside the steps.
+                         STATIC: ghosts hold their values; PERIODIC: images
+                         of the interior; RADIATIVE: every ghost point
+                         evolves by the outgoing-wave (Sommerfeld) condition
+                         d_t u = -v (x^i/r) d_i u - v (u - u_inf)/r, r = |x|
+                         from the coordinates (origin), at least h/2, with
+                         second-order centred differences (one-sided into
+                         the box at its faces), v = sqrt 2 for the 1+log
+                         lapse and 1 otherwise, u_inf the flat-space value,
+                         frozen gauge variables held -- the boundary step of
+                         section "Binary Black Hole Simulations with
+                         Chemora" (timer row "Boundary condition"), which
+                         the paper does not spell out                       */
   int32_t precision;  /* CHEMORA_PREC_FP64, or CHEMORA_PREC_SPLIT (order 4
                          only, else EUNSUPPORTED): stencil inputs are FP64
                          differences rounded to FP32, combined with FP32
@@ -109,7 +123,8 @@ typedef struct chemora_patch {
   int32_t reserved;   /* must be 0                                            */
   int64_t sy, sz, sf; /* element strides of y, z and the GF index            */
   double h;           /* grid spacing (> 0)                                   */
-  double origin[3];   /* coordinates of interior point (0,0,0) (metadata)    */
+  double origin[3];   /* coordinates of interior point (0,0,0): metadata,
+                         except for the radiative boundary (finite there)  */
   double *u;          /* device pointer: 24 GFs, caller-owned                */
 } chemora_patch;
 
@@ -131,7 +146,8 @@ int chemora_required_ghost(int fd_order, int upwind, int ko_radius);
  * ghost zones were filled outside the kernel.  Reads patch->u (ghosts
  * included: the caller provides them), writes the interior entries of
  * `rhs` (the patch's layout and strides; ghost and padding entries are not
- * written).  `rhs` is caller-owned device memory and must not overlap the
+ * written), and with the radiative boundary also every ghost entry (the
+ * boundary condition's right-hand side).  `rhs` is caller-owned device memory and must not overlap the
  * patch state.  Asynchronous on `stream`.  EINVAL (bad params, strides,
  * NULL / misaligned / overlapping pointers) and EUNSUPPORTED are returned
  * before any GPU work; EDEVICE if the launch fails. */
@@ -152,7 +168,9 @@ size_t chemora_rk4_scratch_elems(const chemora_patch *patch);
  * per point and step).
  * BC static: ghost points of u are left untouched and are the ghosts of every
  * stage.  BC periodic: ghosts of every stage input and of the result are
- * refilled with periodic images of the interior.  `scratch` is a device
+ * refilled with periodic images of the interior.  BC radiative: the ghost
+ * points are advanced by the same stages with the boundary condition's
+ * right-hand side (one extra launch per stage).  `scratch` is a device
  * buffer of at least chemora_rk4_scratch_elems(patch) doubles that must not
  * overlap u; its content on entry is ignored and on return is unspecified. */
 int chemora_rk4_step(const chemora_params *params, const chemora_patch *patch, double dt,
@@ -203,6 +221,28 @@ size_t chemora_rk3_scratch_elems(const chemora_patch *patch);
  * chemora_rk4_step. */
 int chemora_rk3_step(const chemora_params *params, const chemora_patch *patch, double dt,
                      double *scratch, void *stream);
+
+/* Psi4, the Newman-Penrose Weyl scalar of outgoing gravitational radiation,
+ * at every interior point: the paper's second GPU workload beside the
+ * evolution (section "Binary Black Hole Simulations with Chemora", timer row
+ * "Compute Psi4"), which it does not spell out.  From the 3+1 data in
+ * vacuum -- gamma_ij = gt_ij / chi, K_ij = (At_ij + gt_ij K / 3) / chi --
+ * the electric and magnetic parts of the Weyl tensor
+ *   E_ij = R_ij - K_ik K^k_j + K K_ij,   B_ij = sym_ij eps_i^kl D_k K_lj
+ * (R_ij the evolution's Ricci tensor, eps_ijk = sqrt(det gamma) [ijk]) are
+ * projected on mbar = (e_theta - i e_phi)/sqrt 2 of the radial tetrad
+ * obtained by Gram-Schmidt in gamma from (x, y, z), the theta-like vector
+ * gamma^ad eps_dbc v1^b (x, y, z)^c and v1 = (-y, x, 0) (v1 = (0, 1, 0) on
+ * the z axis, (0, 0, 1) replacing (x, y, z) at the origin):
+ *   Psi4 = (E_ij - i B_ij) mbar^i mbar^j,
+ * which is -d_t^2 h_+ + i d_t^2 h_x for an outgoing wave.  Coordinates come
+ * from patch.origin and h (must be finite); centred first and second
+ * derivatives of the patch's order.  psi4 holds two grid functions with the
+ * patch's strides (2 * patch.sf doubles): the real part at psi4[0 .. sf),
+ * the imaginary part at psi4[sf .. 2 sf); ghost entries are not written;
+ * psi4 must not overlap the state.  Errors as chemora_bssn_rhs, EINVAL for
+ * a NULL, misaligned or overlapping psi4 or a non-finite origin. */
+int chemora_psi4(const chemora_params *params, const chemora_patch *patch, double *psi4, void *stream);
 
 /* Momentum constraint M_i = gt^jk (d_j At_ki - Gt^l_jk At_li - Gt^l_ji At_kl)
  * - 3/(2 chi) gt^kl At_il d_k chi - 2/3 d_i K of the state at every interior
@@ -314,6 +354,34 @@ int chemora_plan_create_rk3(const chemora_params *params, const chemora_patch *p
                             int32_t npatch, double courant, const char *tune_cache_path, void *stream,
                             chemora_plan **out);
 
+/* A synchronised plan: the patches form one grid hierarchy instead of being
+ * independent -- the framework services the paper delegates to its driver
+ * (section "Cactus-Carpet Computational Infrastructure": ghost-zone
+ * synchronisation, mesh refinement, multi-block; section "Conclusion" names
+ * them as the next step).  Patches sit on vertex-centred refinement levels
+ * h_L = h_0 / 2^L (h_0 the largest spacing); every origin must lie on its
+ * level's lattice through the first coarsest patch's origin.  Every patch
+ * advances with the same dt (no subcycling) by RK4 (integrator 4) or the
+ * SSP RK3 step (integrator 3).  After every stage the ghost points of every
+ * stage output are refilled level by level, coarsest first: a ghost point
+ * inside the interior of another patch of its level takes that value (the
+ * lowest-numbered such patch); else, on a refined level, the order-p
+ * Lagrange interpolation (p = fd_order, tensor product, per axis the
+ * coincident coarse point or the p coarse points around a midpoint) from
+ * the lowest-numbered patch of the next coarser level whose stored box holds
+ * every tap; else (coarsest level only) it is an outer-boundary point with
+ * the params' boundary treatment (static or radiative; periodic is
+ * EUNSUPPORTED).  After the last stage, and once here before the first step,
+ * coarse interior points that coincide with a finer level's interior point
+ * take its value (finest level first), then the ghosts are refilled.  The
+ * point maps are built here on the host; EINVAL if spacings or origins do
+ * not form such a hierarchy or a refined patch's ghost point has no source.
+ * Otherwise as chemora_plan_create (scratch, tuning, errors); dt must be
+ * finite and > 0. */
+int chemora_plan_create_synced(const chemora_params *params, const chemora_patch *patches,
+                               double *const *scratch, int32_t npatch, double dt, int32_t integrator,
+                               const char *tune_cache_path, void *stream, chemora_plan **out);
+
 /* Advances every patch of the plan by nsteps steps of its integrator
  * (nsteps >= 0), by replaying the captured graph on `stream`: per step and
  * RK stage, the right-hand side and stage combination of every patch
@@ -344,7 +412,8 @@ const char *chemora_last_error(void);
 /* ABI version of this header (major*100 + minor): 102 (1.1 added
  * chemora_rk3_step, chemora_rk3_scratch_elems, chemora_plan_create_rk3,
  * chemora_enforce_constraints and chemora_momentum_constraint; 1.2 added
- * chemora_rk4_step_noalloc; nothing earlier changed). */
+ * chemora_rk4_step_noalloc, chemora_psi4, chemora_plan_create_synced and
+ * CHEMORA_BC_RADIATIVE; nothing earlier changed). */
 int chemora_abi_version(void);
 
 #ifdef __cplusplus

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libchemora.so")
-SOURCES = ["chemora.hip", "stage_o4.hip", "stage_o8.hip"]
+SOURCES = ["chemora.hip", "stage_o4.hip", "stage_o8.hip", "sync.hip"]
 ARCH = os.environ.get("CHEMORA_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -27,7 +27,7 @@ EXPORTS = (
     "chemora_plan_patch_variant", "chemora_tune", "chemora_tile_variant", "chemora_set_tile_variant",
     "chemora_tile_variant_shape", "chemora_hamiltonian", "chemora_rk3_scratch_elems", "chemora_rk3_step",
     "chemora_enforce_constraints", "chemora_momentum_constraint", "chemora_plan_create_rk3",
-    "chemora_rk4_step_noalloc",
+    "chemora_rk4_step_noalloc", "chemora_psi4", "chemora_plan_create_synced",
 )
 # CHEMORA_NOALLOC_SCRATCH_ELEMS of include/chemora.h
 NOALLOC_SCRATCH_ELEMS = 8 << 20
@@ -82,6 +82,8 @@ def lib() -> ctypes.CDLL:
         L.chemora_enforce_constraints.restype = ctypes.c_int
         L.chemora_momentum_constraint.argtypes = [P, X, ctypes.c_void_p, ctypes.c_void_p]
         L.chemora_momentum_constraint.restype = ctypes.c_int
+        L.chemora_psi4.argtypes = [P, X, ctypes.c_void_p, ctypes.c_void_p]
+        L.chemora_psi4.restype = ctypes.c_int
         L.chemora_check_finite.argtypes = [P, X, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
         L.chemora_check_finite.restype = ctypes.c_int
         L.chemora_last_error.argtypes = []
@@ -91,6 +93,10 @@ def lib() -> ctypes.CDLL:
         L.chemora_plan_create.restype = ctypes.c_int
         L.chemora_plan_create_rk3.argtypes = L.chemora_plan_create.argtypes
         L.chemora_plan_create_rk3.restype = ctypes.c_int
+        L.chemora_plan_create_synced.argtypes = [P, X, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                                 ctypes.c_double, ctypes.c_int32, ctypes.c_char_p, ctypes.c_void_p,
+                                                 ctypes.POINTER(ctypes.c_void_p)]
+        L.chemora_plan_create_synced.restype = ctypes.c_int
         L.chemora_batch_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
         L.chemora_batch_step.restype = ctypes.c_int
         L.chemora_plan_points.argtypes = [ctypes.c_void_p]
@@ -196,6 +202,11 @@ def chemora_momentum_constraint(params: chemora_params, patch: chemora_patch, M_
                                                     _stream(stream)))
 
 
+def chemora_psi4(params: chemora_params, patch: chemora_patch, psi4_ptr: int, stream=None) -> int:
+    return _check(lib().chemora_psi4(ctypes.byref(params), ctypes.byref(patch), ctypes.c_void_p(psi4_ptr),
+                                     _stream(stream)))
+
+
 def chemora_enforce_constraints(params: chemora_params, patch: chemora_patch, stream=None) -> int:
     return _check(lib().chemora_enforce_constraints(ctypes.byref(params), ctypes.byref(patch), _stream(stream)))
 
@@ -227,6 +238,20 @@ def chemora_plan_create(params: chemora_params, patches, scratch_ptrs, courant: 
     path = tune_cache_path.encode() if tune_cache_path else None
     fn = lib().chemora_plan_create_rk3 if rk3 else lib().chemora_plan_create
     _check(fn(ctypes.byref(params), arr, sc, n, courant, path, _stream(stream), ctypes.byref(out)))
+    return out.value
+
+
+def chemora_plan_create_synced(params: chemora_params, patches, scratch_ptrs, dt: float, integrator: int = 4,
+                               tune_cache_path=None, stream=None) -> int:
+    """A synchronised plan (one dt, ghosts exchanged between the patches and
+    refinement levels); returns the opaque plan handle."""
+    n = len(patches)
+    arr = (chemora_patch * n)(*patches)
+    sc = (ctypes.c_void_p * n)(*[ctypes.c_void_p(p) for p in scratch_ptrs])
+    out = ctypes.c_void_p(0)
+    path = tune_cache_path.encode() if tune_cache_path else None
+    _check(lib().chemora_plan_create_synced(ctypes.byref(params), arr, sc, n, dt, integrator, path, _stream(stream),
+                                            ctypes.byref(out)))
     return out.value
 
 
@@ -332,6 +357,18 @@ class Patch:
                                                                                   self.grid.sy)
         return v[:, g:g + n[2], g:g + n[1], g:g + n[0]]
 
+    def psi4(self, stream=None):
+        """Psi4 at the interior points, as a (2, nz, ny, nx) torch tensor view
+        (real and imaginary part)."""
+        import torch
+        m = torch.full((2 * self.grid.sf,), float("nan"), dtype=torch.float64, device=self.u.device)
+        chemora_psi4(self.params, self.patch, m.data_ptr(), stream or torch.cuda.current_stream())
+        g = self.grid.ghost
+        n = self.grid.n
+        v = m.view(2, self.grid.sf)[:, : self.grid.sz * (n[2] + 2 * g)].reshape(2, n[2] + 2 * g, n[1] + 2 * g,
+                                                                                  self.grid.sy)
+        return v[:, g:g + n[2], g:g + n[1], g:g + n[0]]
+
     def tune(self, cache_path=None, stream=None) -> int:
         import torch
         return chemora_tune(self.params, self.patch, self.scratch().data_ptr(), cache_path,
@@ -364,16 +401,24 @@ class Patch:
 class Batch:
     """Several device-resident patches advanced together through a plan."""
 
-    def __init__(self, params, grids, states, courant: float, device="cuda", tune_cache_path=None,
-                 integrator: str = "rk4"):
+    def __init__(self, params, grids, states, courant: float = 0.0, device="cuda", tune_cache_path=None,
+                 integrator: str = "rk4", synced_dt: float = 0.0):
+        """Independent patches with dt = courant * h each, or (synced_dt > 0)
+        one synchronised grid hierarchy stepped with synced_dt."""
         import torch
         if integrator not in ("rk4", "rk3"):
             raise ValueError(f"integrator {integrator!r} is neither 'rk4' nor 'rk3'")
+        self.plan = 0
         self.patches = [Patch(params, g, s, device=device) for g, s in zip(grids, states)]
         self.params = make_params(params)
         scr = [p.scratch().data_ptr() for p in self.patches]
-        self.plan = chemora_plan_create(self.params, [p.patch for p in self.patches], scr, courant,
-                                        tune_cache_path, torch.cuda.current_stream(), rk3=integrator == "rk3")
+        if synced_dt > 0.0:
+            self.plan = chemora_plan_create_synced(self.params, [p.patch for p in self.patches], scr, synced_dt,
+                                                   3 if integrator == "rk3" else 4, tune_cache_path,
+                                                   torch.cuda.current_stream())
+        else:
+            self.plan = chemora_plan_create(self.params, [p.patch for p in self.patches], scr, courant,
+                                            tune_cache_path, torch.cuda.current_stream(), rk3=integrator == "rk3")
 
     def variants(self):
         return [chemora_plan_patch_variant(self.plan, p) for p in range(len(self.patches))]

@@ -31,6 +31,7 @@
 #include "fd_ops.hpp"
 #include "host_internal.hpp"
 #include "stage_common.hpp"
+#include "sync.hpp"
 
 namespace chemora {
 
@@ -69,6 +70,63 @@ __global__ __launch_bounds__(GHOST_THREADS) void ghost_kernel(const double* __re
       dst0[at] = v;
       dst1[at] = v;
     }
+  }
+}
+
+// Radiative (Sommerfeld) outer boundary: at every ghost point of the stage
+// input a.in, the right-hand side of the outgoing-wave condition
+//   d_t u = -v (x^i / r) d_i u - v (u - u_inf) / r,   r = |x| (at least h/2),
+// with d_i u the second-order centred difference where both neighbours are
+// stored points and the second-order one-sided difference into the box
+// otherwise; v = rb.vlapse for the lapse and 1 for the rest, u_inf the
+// flat-space value, frozen gauge variables 0.  The right-hand side k goes
+// through the same stage combination as at interior points:
+// out = fma(cs, k, fma(cyo, Y, cu U)), and y = Y + cy k in RK4 stages 1-3.
+// One work-group per stored row (j, k), as ghost_kernel.
+struct Radiative {
+  double origin[3];
+  double h;
+  double vlapse;
+  int frozen_lapse, frozen_shift;
+};
+
+__device__ __forceinline__ double rad_diff(const double* p, int64_t s, int c, int e, double inv2h) {
+  if (c > 0 && c < e - 1) return (p[s] - p[-s]) * inv2h;
+  if (c == 0) return (4.0 * (p[s] - p[0]) - (p[2 * s] - p[0])) * inv2h;
+  return -(4.0 * (p[-s] - p[0]) - (p[-2 * s] - p[0])) * inv2h;
+}
+
+__global__ __launch_bounds__(GHOST_THREADS) void radiative_kernel(StageArgs a, Radiative rb) {
+  const Geo G = a.geo;
+  const int j = blockIdx.x, k = blockIdx.y;
+  const int ex = G.nx + 2 * G.g, ey = G.ny + 2 * G.g, ez = G.nz + 2 * G.g;
+  const bool ghost_row = j < G.g || j >= G.ny + G.g || k < G.g || k >= G.nz + G.g;
+  const int per_f = ghost_row ? ex : 2 * G.g;
+  const double inv2h = 1.0 / (2.0 * rb.h), half_h = rb.h / 2.0;
+  const double y = rb.origin[1] + (double)(j - G.g) * rb.h, z = rb.origin[2] + (double)(k - G.g) * rb.h;
+  const int64_t row = (int64_t)k * G.sz + (int64_t)j * G.sy;
+  const bool store_y = a.mode == MODE_STAGE1 || a.mode == MODE_STAGE23;
+  for (int t = threadIdx.x; t < 24 * per_f; t += GHOST_THREADS) {
+    const int f = t / per_f, c = t - f * per_f;
+    const int i = ghost_row ? c : (c < G.g ? c : G.nx + c);
+    const int64_t at = f * G.sf + row + i;
+    const double x = rb.origin[0] + (double)(i - G.g) * rb.h;
+    double r = sqrt(x * x + y * y + z * z);
+    if (r < half_h) r = half_h;
+    const bool frozen = (f == gALPHA && rb.frozen_lapse) || (f >= gBETA && rb.frozen_shift);
+    double kf = 0.0;
+    if (!frozen) {
+      const double* p = a.in + at;
+      const double v = f == gALPHA ? rb.vlapse : 1.0;
+      const double uinf = (f == gCHI || f == gALPHA || f == gGT || f == gGT + 3 || f == gGT + 5) ? 1.0 : 0.0;
+      double xd = x * rad_diff(p, 1, i, ex, inv2h);
+      xd += y * rad_diff(p, G.sy, j, ey, inv2h);
+      xd += z * rad_diff(p, G.sz, k, ez, inv2h);
+      kf = -(v * xd) / r - v * (p[0] - uinf) / r;
+    }
+    const double Y = a.yin[at], U = a.un[at];
+    if (store_y) a.y[at] = Y + a.cy * kf;
+    a.out[at] = __builtin_fma(a.cs, kf, __builtin_fma(a.cyo, Y, a.cu * U));
   }
 }
 
@@ -181,6 +239,268 @@ __global__ __launch_bounds__(256) void momentum_kernel(const double* __restrict_
   }
 }
 
+// Psi4, the Newman-Penrose Weyl scalar of outgoing radiation (a diagnostic
+// beside the step: the paper's "Compute Psi4" kernel), one work-item per
+// interior point (64 x 4 work-groups), stencils read straight from the state
+// (neighbours come from L2).  From the 3+1 data in vacuum:
+//   gamma_ij = gt_ij / chi,   K_ij = (At_ij + gt_ij K / 3) / chi,
+//   E_ij = R_ij - K_ik K^k_j + K K_ij,   B_ij = sym_ij eps_i^kl D_k K_lj,
+// R_ij the physical Ricci tensor of the evolution (conformal Ricci with the
+// evolved Gt^i in its d Gt term, plus the chi terms), eps_ijk =
+// sqrt(det gamma) [ijk].  Tetrad: Gram-Schmidt in the physical metric of
+// v2 = (x, y, z), v3^a = gamma^ad eps_dbc v1^b v2^c, v1 = (-y, x, 0) (in that
+// order; v1 = (0, 1, 0) on the z axis, v2 = (0, 0, 1) at the origin) gives
+// e_r, e_theta, e_phi, and with mbar = (e_theta - i e_phi)/sqrt 2
+//   Psi4 = (E_ij - i B_ij) mbar^i mbar^j
+//        = (E_tt - E_pp)/2 - B_tp + i (-E_tp - (B_tt - B_pp)/2),
+// stored as out[point] (real part) and out[sf + point] (imaginary part).
+// Coordinates: origin + (index - ghost) h.
+template <int ORDER>
+__global__ __launch_bounds__(256) void psi4_kernel(const double* __restrict__ u, double* __restrict__ out, Geo G,
+                                                   double h, double ox, double oy, double oz) {
+  using St = Stencil<ORDER>;
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= G.nx || j >= G.ny) return;
+  const int64_t at = (int64_t)(k + G.g) * G.sz + (int64_t)(j + G.g) * G.sy + (i + G.g);
+  const int64_t st[3] = {1, G.sy, G.sz};
+  const double d1s = 1.0 / (St::D1 * h), d2s = 1.0 / (St::D2 * h * h), d11s = d1s * d1s;
+  auto val = [&](int f) { return u[f * G.sf + at]; };
+  auto D1 = [&](int f, int a) {
+    const double* p = u + f * G.sf + at;
+    const int64_t s = st[a];
+    return St::first([&](int o) { return p[o * s]; }) * d1s;
+  };
+  // second derivative of slot q (xx xy xz yy yz zz)
+  auto D2 = [&](int f, int q) {
+    const double* p = u + f * G.sf + at;
+    const int a = SI(q), b = SJ(q);
+    if (a == b) return St::second([&](int o) { return p[o * st[a]]; }) * d2s;
+    return St::first([&](int oa) {
+             return St::first([&](int ob) { return p[oa * st[a] + ob * st[b]]; });
+           }) * d11s;
+  };
+  double g[6], A[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    g[q] = val(gGT + q);
+    A[q] = val(gAT + q);
+  }
+  const double chi = val(gCHI), K = val(gK);
+  const double c00 = g[3] * g[5] - g[4] * g[4], c01 = g[2] * g[4] - g[1] * g[5], c02 = g[1] * g[4] - g[2] * g[3];
+  const double c11 = g[0] * g[5] - g[2] * g[2], c12 = g[1] * g[2] - g[0] * g[4], c22 = g[0] * g[3] - g[1] * g[1];
+  const double detg = g[0] * c00 + g[1] * c01 + g[2] * c02;
+  const double idet = 1.0 / detg;
+  const double gu[6] = {c00 * idet, c01 * idet, c02 * idet, c11 * idet, c12 * idet, c22 * idet};
+
+  // conformal Christoffel symbols: Gl[k][ij] = Gt_{k,ij}, Gu[k][ij] = Gt^k_ij
+  double Gl[3][6];
+  {
+    double dg[3][6];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) dg[m][q] = D1(gGT + q, m);
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const int a = SI(q), b = SJ(q);
+        Gl[kk][q] = 0.5 * (dg[b][S(kk, a)] + dg[a][S(kk, b)] - dg[kk][q]);
+      }
+  }
+  double Gu[3][6];
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) Gu[kk][q] = gu[S(kk, 0)] * Gl[0][q] + gu[S(kk, 1)] * Gl[1][q] + gu[S(kk, 2)] * Gl[2][q];
+  double Gd[3];
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc += W(q) * gu[q] * Gu[kk][q];
+    Gd[kk] = acc;
+  }
+  double dchi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) dchi[a] = D1(gCHI, a);
+
+  // physical Ricci tensor
+  double Ric[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int a = SI(q), b = SJ(q);
+    double r = 0.0;
+#pragma unroll
+    for (int s2 = 0; s2 < 6; ++s2) r -= 0.5 * W(s2) * gu[s2] * D2(gGT + q, s2);
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+      r += 0.5 * (g[S(kk, a)] * D1(gXT + kk, b) + g[S(kk, b)] * D1(gXT + kk, a));
+      r += 0.5 * Gd[kk] * (Gl[a][S(b, kk)] + Gl[b][S(a, kk)]);
+    }
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk)
+          r += gu[S(l, m)] * (Gu[kk][S(l, a)] * Gl[b][S(kk, m)] + Gu[kk][S(l, b)] * Gl[a][S(kk, m)] +
+                              Gu[kk][S(a, m)] * Gl[kk][S(l, b)]);
+    Ric[q] = r;
+  }
+  {
+    double cdd[6], trc = 0.0, dchi2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      cdd[q] = D2(gCHI, q) - (Gu[0][q] * dchi[0] + Gu[1][q] * dchi[1] + Gu[2][q] * dchi[2]);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      trc += W(q) * gu[q] * cdd[q];
+      dchi2 += W(q) * gu[q] * dchi[SI(q)] * dchi[SJ(q)];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      Ric[q] += (cdd[q] + g[q] * trc) / (2.0 * chi) -
+                (dchi[SI(q)] * dchi[SJ(q)] + 3.0 * g[q] * dchi2) / (4.0 * chi * chi);
+  }
+
+  // physical metric, curvature, electric part
+  const double ichi = 1.0 / chi;
+  double gam[6], gamu[6], Kd[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    gam[q] = g[q] * ichi;
+    gamu[q] = chi * gu[q];
+    Kd[q] = (A[q] + g[q] * K * (1.0 / 3.0)) * ichi;
+  }
+  double Km[3][3];   // K^a_b
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      Km[a][b] = gamu[S(a, 0)] * Kd[S(0, b)] + gamu[S(a, 1)] * Kd[S(1, b)] + gamu[S(a, 2)] * Kd[S(2, b)];
+  const double trK = Km[0][0] + Km[1][1] + Km[2][2];
+  double Ew[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int a = SI(q), b = SJ(q);
+    Ew[q] = Ric[q] - (Kd[S(a, 0)] * Km[0][b] + Kd[S(a, 1)] * Km[1][b] + Kd[S(a, 2)] * Km[2][b]) + trK * Kd[q];
+  }
+
+  // magnetic part: D_k K_ij with the physical Christoffel symbols
+  // Gamma^m_ij = Gt^m_ij + (gt_ij gt^mn d_n chi - delta^m_i d_j chi - delta^m_j d_i chi) / (2 chi)
+  double gudchi[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) gudchi[m] = gu[S(m, 0)] * dchi[0] + gu[S(m, 1)] * dchi[1] + gu[S(m, 2)] * dchi[2];
+  auto Gam = [&](int m, int a, int b) {
+    double c = g[S(a, b)] * gudchi[m];
+    if (m == a) c -= dchi[b];
+    if (m == b) c -= dchi[a];
+    return Gu[m][S(a, b)] + c * (0.5 * ichi);
+  };
+  double dK[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) dK[a] = D1(gK, a);
+  const double sq = sqrt(detg * ichi * ichi * ichi);   // sqrt(det gamma)
+  double Bn[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Bn[a][b] = 0.0;
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk) {
+    // D_k K_lj for this k
+    double DK[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int l = SI(q), jj = SJ(q);
+      double d = (D1(gAT + q, kk) + D1(gGT + q, kk) * K * (1.0 / 3.0) + g[q] * dK[kk] * (1.0 / 3.0)) * ichi -
+                 Kd[q] * dchi[kk] * ichi;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) d -= Gam(m, kk, l) * Kd[S(m, jj)] + Gam(m, kk, jj) * Kd[S(l, m)];
+      DK[q] = d;
+    }
+    // eps_a^{kl} = gamma^{kc} gamma^{ld} eps_acd, eps_acd = sq [acd]
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        double e = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const int pm = (c == d || a == c || a == d) ? 0 : (((c - a + 3) % 3 == 1) ? 1 : -1);
+            if (pm) e += double(pm) * gamu[S(kk, c)] * gamu[S(l, d)];
+          }
+        e *= sq;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Bn[a][b] += e * DK[S(l, b)];
+      }
+  }
+  double Bw[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) Bw[q] = 0.5 * (Bn[SI(q)][SJ(q)] + Bn[SJ(q)][SI(q)]);
+
+  // tetrad
+  const double x = ox + (double)i * h, y = oy + (double)j * h, z = oz + (double)k * h;
+  double v1[3] = {-y, x, 0.0}, v2[3] = {x, y, z};
+  if (x == 0.0 && y == 0.0) {
+    v1[0] = 0.0;
+    v1[1] = 1.0;
+    if (z == 0.0) v2[2] = 1.0;
+  }
+  auto dot = [&](const double* p, const double* q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) acc += gam[S(a, b)] * p[a] * q[b];
+    return acc;
+  };
+  double v3[3];
+  {
+    // eps_dbc v1^b v2^c = sq (v1 x v2)_d, then raised
+    const double c0 = sq * (v1[1] * v2[2] - v1[2] * v2[1]);
+    const double c1 = sq * (v1[2] * v2[0] - v1[0] * v2[2]);
+    const double c2 = sq * (v1[0] * v2[1] - v1[1] * v2[0]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v3[a] = gamu[S(a, 0)] * c0 + gamu[S(a, 1)] * c1 + gamu[S(a, 2)] * c2;
+  }
+  double er[3], et[3], ep[3];
+  {
+    const double n = 1.0 / sqrt(dot(v2, v2));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) er[a] = v2[a] * n;
+    const double c = dot(v3, er);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) et[a] = v3[a] - c * er[a];
+    const double nt = 1.0 / sqrt(dot(et, et));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) et[a] *= nt;
+    const double cr = dot(v1, er), ct = dot(v1, et);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ep[a] = v1[a] - cr * er[a] - ct * et[a];
+    const double np = 1.0 / sqrt(dot(ep, ep));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ep[a] *= np;
+  }
+  auto contract = [&](const double* T, const double* p, const double* q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) acc += T[S(a, b)] * p[a] * q[b];
+    return acc;
+  };
+  const double Ett = contract(Ew, et, et), Epp = contract(Ew, ep, ep), Etp = contract(Ew, et, ep);
+  const double Btt = contract(Bw, et, et), Bpp = contract(Bw, ep, ep), Btp = contract(Bw, et, ep);
+  out[at] = 0.5 * (Ett - Epp) - Btp;
+  out[G.sf + at] = -Etp - 0.5 * (Btt - Bpp);
+}
+
 __global__ __launch_bounds__(256) void finite_kernel(const double* __restrict__ u, Geo G,
                                                      unsigned long long* count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -237,7 +557,7 @@ int validate(const chemora_params* P, const chemora_patch* X) {
   if (P->lapse < 0 || P->lapse > 2) return fail(CHEMORA_EINVAL, "lapse %d unknown", P->lapse);
   if (P->shift < 0 || P->shift > 1) return fail(CHEMORA_EINVAL, "shift %d unknown", P->shift);
   if (!std::isfinite(P->eta)) return fail(CHEMORA_EINVAL, "eta must be finite");
-  if (P->bc != 0 && P->bc != 1) return fail(CHEMORA_EINVAL, "bc %d unknown", P->bc);
+  if (P->bc < CHEMORA_BC_STATIC || P->bc > CHEMORA_BC_RADIATIVE) return fail(CHEMORA_EINVAL, "bc %d unknown", P->bc);
   if (P->precision != CHEMORA_PREC_FP64 && P->precision != CHEMORA_PREC_SPLIT)
     return fail(CHEMORA_EUNSUPPORTED, "precision %d unknown", P->precision);
   if (P->precision == CHEMORA_PREC_SPLIT) {
@@ -268,6 +588,9 @@ int validate(const chemora_params* P, const chemora_patch* X) {
   if (P->fd_order == 4 && P->ko_radius > 3)
     return fail(CHEMORA_EUNSUPPORTED, "order 4 supports ko_radius <= 3");
   if (!(X->h > 0.0) || !std::isfinite(X->h)) return fail(CHEMORA_EINVAL, "h must be finite and > 0");
+  if (P->bc == CHEMORA_BC_RADIATIVE)
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(X->origin[a])) return fail(CHEMORA_EINVAL, "radiative boundary needs a finite origin");
   if (!X->u) return fail(CHEMORA_EINVAL, "patch.u is NULL");
   if (((uintptr_t)X->u) % 8) return fail(CHEMORA_EINVAL, "patch.u not 8-byte aligned");
   return CHEMORA_OK;
@@ -487,6 +810,19 @@ void launch_ghosts(bool periodic, const chemora::Geo& G, const double* src, doub
     hipLaunchKernelGGL((chemora::ghost_kernel<false>), grid, dim3(chemora::GHOST_THREADS), 0, s, src, d0, d1, G);
 }
 
+// the radiative boundary of a stage whose arguments are a (bc RADIATIVE only)
+void launch_radiative(const chemora_params* P, const chemora_patch* X, const chemora::StageArgs& a,
+                      hipStream_t s) {
+  chemora::Radiative rb;
+  for (int d = 0; d < 3; ++d) rb.origin[d] = X->origin[d];
+  rb.h = X->h;
+  rb.vlapse = P->lapse == CHEMORA_LAPSE_ONE_PLUS_LOG ? std::sqrt(2.0) : 1.0;
+  rb.frozen_lapse = P->lapse == CHEMORA_LAPSE_FROZEN;
+  rb.frozen_shift = P->shift == CHEMORA_SHIFT_FROZEN;
+  dim3 grid(a.geo.ny + 2 * a.geo.g, a.geo.nz + 2 * a.geo.g, 1);
+  hipLaunchKernelGGL(chemora::radiative_kernel, grid, dim3(chemora::GHOST_THREADS), 0, s, a, rb);
+}
+
 }  // namespace
 
 extern "C" {
@@ -519,6 +855,7 @@ int chemora_bssn_rhs(const chemora_params* params, const chemora_patch* patch, d
   a.cs = 1.0;
   a.mode = chemora::MODE_RHS;
   dispatch_stage(params, a, choose_variant(params, patch), (hipStream_t)stream);
+  if (params->bc == CHEMORA_BC_RADIATIVE) launch_radiative(params, patch, a, (hipStream_t)stream);
   return check_launch("bssn_rhs");
 }
 
@@ -623,10 +960,11 @@ int rk4_stage(const chemora_params* params, const chemora_patch* patch, int stag
   double* Y = scratch + 2 * state;
   const bool periodic = params->bc == CHEMORA_BC_PERIODIC;
   chemora::StageArgs a = base_args(params, patch);
-  if (stage == 1 && !periodic) launch_ghosts(false, a.geo, u, SA, SB, s);
+  if (stage == 1 && params->bc == CHEMORA_BC_STATIC) launch_ghosts(false, a.geo, u, SA, SB, s);
   double* written = stage_args(a, stage, dt, u, SA, SB, Y);
   dispatch_stage(params, a, choose_variant(params, patch), s);
   if (periodic) launch_ghosts(true, a.geo, nullptr, written, nullptr, s);
+  if (params->bc == CHEMORA_BC_RADIATIVE) launch_radiative(params, patch, a, s);
   return check_launch("rk4 stage");
 }
 
@@ -742,10 +1080,11 @@ int chemora_rk3_step(const chemora_params* params, const chemora_patch* patch, d
   const int v = choose_variant(params, patch);
   for (int st = 1; st <= 3; ++st) {
     chemora::StageArgs a = base_args(params, patch);
-    if (st == 1 && !periodic) launch_ghosts(false, a.geo, u, SA, SB, s);
+    if (st == 1 && params->bc == CHEMORA_BC_STATIC) launch_ghosts(false, a.geo, u, SA, SB, s);
     double* written = rk3_stage_args(a, st, dt, u, SA, SB);
     dispatch_stage(params, a, v, s);
     if (periodic) launch_ghosts(true, a.geo, nullptr, written, nullptr, s);
+    if (params->bc == CHEMORA_BC_RADIATIVE) launch_radiative(params, patch, a, s);
     if ((rc = check_launch("rk3 stage"))) return rc;
   }
   return CHEMORA_OK;
@@ -778,6 +1117,30 @@ int chemora_momentum_constraint(const chemora_params* params, const chemora_patc
   else
     hipLaunchKernelGGL(chemora::momentum_kernel<4>, grid, dim3(64, 4), 0, s, patch->u, M, G, d1s);
   return check_launch("momentum_constraint");
+}
+
+int chemora_psi4(const chemora_params* params, const chemora_patch* patch, double* psi4, void* stream) {
+  g_error.clear();
+  int rc = validate(params, patch);
+  if (rc) return rc;
+  if (!psi4) return fail(CHEMORA_EINVAL, "psi4 is NULL");
+  if (((uintptr_t)psi4) % 8) return fail(CHEMORA_EINVAL, "psi4 not 8-byte aligned");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(patch->origin[a])) return fail(CHEMORA_EINVAL, "psi4 needs a finite origin");
+  const size_t bytes = (size_t)CHEMORA_NGF * patch->sf * sizeof(double);
+  if (overlap(psi4, 2 * patch->sf * sizeof(double), patch->u, bytes))
+    return fail(CHEMORA_EINVAL, "psi4 overlaps patch.u");
+  const chemora::Geo G = make_geo(params, patch);
+  hipStream_t s = (hipStream_t)stream;
+  dim3 grid((G.nx + 63) / 64, (G.ny + 3) / 4, G.nz);
+  const double* o = patch->origin;
+  if (params->fd_order == 8)
+    hipLaunchKernelGGL(chemora::psi4_kernel<8>, grid, dim3(64, 4), 0, s, patch->u, psi4, G, patch->h, o[0], o[1],
+                       o[2]);
+  else
+    hipLaunchKernelGGL(chemora::psi4_kernel<4>, grid, dim3(64, 4), 0, s, patch->u, psi4, G, patch->h, o[0], o[1],
+                       o[2]);
+  return check_launch("psi4");
 }
 
 int chemora_enforce_constraints(const chemora_params* params, const chemora_patch* patch, void* stream) {
@@ -971,6 +1334,13 @@ struct chemora_plan {
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // synchronised plans: ghost refill / restriction maps and their buffers
+  bool synced = false;
+  std::vector<int> fill_start, restr_start;
+  chemora::SyncItem* d_fill = nullptr;
+  chemora::SyncItem* d_restr = nullptr;
+  chemora::SyncGeo* d_geo = nullptr;
+  double** d_bufs = nullptr;                      // per stage, npatch state pointers (caller's order); then u
 };
 
 namespace {
@@ -985,6 +1355,10 @@ void plan_free(chemora_plan* pl) {
   }
   if (pl->d_args) (void)hipFree(pl->d_args);
   if (pl->d_tile_start) (void)hipFree(pl->d_tile_start);
+  if (pl->d_fill) (void)hipFree(pl->d_fill);
+  if (pl->d_restr) (void)hipFree(pl->d_restr);
+  if (pl->d_geo) (void)hipFree(pl->d_geo);
+  if (pl->d_bufs) (void)hipFree(pl->d_bufs);
   delete pl;
 }
 
@@ -995,18 +1369,38 @@ namespace {
 // A plan capturing one step of RK4 (4 stages) or of the third-order SSP
 // scheme (3 stages); scratch holds 3 states per patch either way (the
 // tuner times RK4 stage-2 launches in it).
+// Restriction (if asked, finest level pair first) and the ghost refill of
+// every level, coarsest first, of the states bufs[0 .. npatch) (device table).
+void plan_restrict_and_fill(const chemora_plan* pl, double* const* bufs, bool restrict_first, hipStream_t s) {
+  const int order = pl->params.fd_order;
+  if (restrict_first)
+    for (size_t q = 0; q + 1 < pl->restr_start.size(); ++q)
+      chemora::launch_sync(order, pl->d_restr + pl->restr_start[q], pl->restr_start[q + 1] - pl->restr_start[q], bufs,
+                           pl->d_geo, s);
+  for (size_t L = 0; L + 1 < pl->fill_start.size(); ++L)
+    chemora::launch_sync(order, pl->d_fill + pl->fill_start[L], pl->fill_start[L + 1] - pl->fill_start[L], bufs,
+                         pl->d_geo, s);
+}
+
+// dt_all > 0: a synchronised plan -- every patch steps with dt_all and the
+// ghosts are exchanged between patches (sync.hpp); else dt = courant * h per
+// patch and the patches are independent.
 int plan_create(const chemora_params* params, const chemora_patch* patches, double* const* scratch, int32_t npatch,
-                double courant, const char* tune_cache_path, void* stream, chemora_plan** out, bool rk3) {
+                double courant, const char* tune_cache_path, void* stream, chemora_plan** out, bool rk3,
+                double dt_all = 0.0) {
   const int nst = rk3 ? 3 : 4;
+  const bool synced = dt_all > 0.0;
   if (!out) return fail(CHEMORA_EINVAL, "out is NULL");
   *out = nullptr;
   if (!patches || !scratch) return fail(CHEMORA_EINVAL, "patches or scratch is NULL");
   if (npatch < 1) return fail(CHEMORA_EINVAL, "npatch %d < 1", npatch);
-  if (!(courant > 0.0) || !std::isfinite(courant)) return fail(CHEMORA_EINVAL, "courant must be finite and > 0");
+  if (!synced && (!(courant > 0.0) || !std::isfinite(courant)))
+    return fail(CHEMORA_EINVAL, "courant must be finite and > 0");
+  auto dt_of = [&](int p) { return synced ? dt_all : courant * patches[p].h; };
   int rc;
   int64_t points = 0;
   for (int p = 0; p < npatch; ++p) {
-    if ((rc = rk4_checks(params, &patches[p], courant * patches[p].h, scratch[p]))) {
+    if ((rc = rk4_checks(params, &patches[p], dt_of(p), scratch[p]))) {
       const std::string m = g_error;
       return fail(rc, "patch %d: %s", p, m.c_str());
     }
@@ -1032,6 +1426,13 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
       if (rs[i].lo < rs[i - 1].hi)
         return fail(CHEMORA_EINVAL, "patch %d %s overlaps patch %d %s", rs[i].patch, rs[i].what, rs[i - 1].patch,
                     rs[i - 1].what);
+  }
+  chemora::SyncMaps maps;
+  if (synced) {
+    if (params->bc == CHEMORA_BC_PERIODIC)
+      return fail(CHEMORA_EUNSUPPORTED, "a synchronised plan does not combine with periodic ghosts");
+    std::string why;
+    if (chemora::build_sync_maps(params, patches, npatch, &maps, &why)) return fail(CHEMORA_EINVAL, "%s", why.c_str());
   }
   hipStream_t s = (hipStream_t)stream;
 
@@ -1085,9 +1486,9 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
       for (int st = 0; st < nst; ++st) {
         chemora::StageArgs sa = a;
         if (rk3)
-          rk3_stage_args(sa, st + 1, courant * X->h, X->u, sc, sc + state);
+          rk3_stage_args(sa, st + 1, dt_of(order[r]), X->u, sc, sc + state);
         else
-          stage_args(sa, st + 1, courant * X->h, X->u, sc, sc + state, sc + 2 * state);
+          stage_args(sa, st + 1, dt_of(order[r]), X->u, sc, sc + state, sc + 2 * state);
         args[st * (size_t)npatch + r] = sa;
       }
       ++g.count;
@@ -1102,9 +1503,51 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
     (void)hipGetLastError();
     return fail(CHEMORA_ENOMEM, "device allocation of plan tables failed");
   }
+  // synchronised plans: maps, per-patch strides and the state pointers of
+  // every stage output (caller's patch order), then u
+  std::vector<chemora::SyncGeo> geo;
+  std::vector<double*> bufs;
+  if (synced) {
+    pl->synced = true;
+    pl->fill_start = maps.fill_start;
+    pl->restr_start = maps.restr_start;
+    for (int p = 0; p < npatch; ++p) geo.push_back({patches[p].sy, patches[p].sz, patches[p].sf});
+    bufs.assign((size_t)(nst + 1) * npatch, nullptr);
+    for (int st = 0; st < nst; ++st)
+      for (int r = 0; r < npatch; ++r) bufs[st * (size_t)npatch + order[r]] = args[st * (size_t)npatch + r].out;
+    for (int p = 0; p < npatch; ++p) bufs[nst * (size_t)npatch + p] = patches[p].u;
+    if (e == hipSuccess && !maps.fill.empty())
+      e = hipMalloc((void**)&pl->d_fill, maps.fill.size() * sizeof(chemora::SyncItem));
+    if (e == hipSuccess && !maps.restr.empty())
+      e = hipMalloc((void**)&pl->d_restr, maps.restr.size() * sizeof(chemora::SyncItem));
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->d_geo, geo.size() * sizeof(chemora::SyncGeo));
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->d_bufs, bufs.size() * sizeof(double*));
+    if (e != hipSuccess) {
+      plan_free(pl);
+      (void)hipGetLastError();
+      return fail(CHEMORA_ENOMEM, "device allocation of the plan's synchronisation maps failed");
+    }
+  }
   e = hipMemcpyAsync(pl->d_args, args.data(), args.size() * sizeof(chemora::StageArgs), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(pl->d_tile_start, starts.data(), starts.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (synced) {
+    if (e == hipSuccess && !maps.fill.empty())
+      e = hipMemcpyAsync(pl->d_fill, maps.fill.data(), maps.fill.size() * sizeof(chemora::SyncItem),
+                         hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !maps.restr.empty())
+      e = hipMemcpyAsync(pl->d_restr, maps.restr.data(), maps.restr.size() * sizeof(chemora::SyncItem),
+                         hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(pl->d_geo, geo.data(), geo.size() * sizeof(chemora::SyncGeo), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(pl->d_bufs, bufs.data(), bufs.size() * sizeof(double*), hipMemcpyHostToDevice, s);
+    // the state made consistent once: restriction, then the ghost refill of u
+    if (e == hipSuccess) {
+      plan_restrict_and_fill(pl, pl->d_bufs + nst * (size_t)npatch, true, s);
+      e = hipGetLastError();
+    }
+  }
   // static ghosts of the stage buffers, once
   if (e == hipSuccess && params->bc == CHEMORA_BC_STATIC) {
     for (int p = 0; p < npatch && e == hipSuccess; ++p) {
@@ -1142,6 +1585,12 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
         launch_ghosts(true, make_geo(params, &patches[order[r]]), nullptr, const_cast<double*>(wr), nullptr,
                       pl->capture);
       }
+    if (params->bc == CHEMORA_BC_RADIATIVE)
+      for (int r = 0; r < npatch; ++r)
+        launch_radiative(params, &patches[order[r]], args[st * (size_t)npatch + r], pl->capture);
+    // ghost exchange of the stage outputs; after the last stage (which
+    // writes u) restriction first
+    if (synced) plan_restrict_and_fill(pl, pl->d_bufs + st * (size_t)npatch, st == nst - 1, pl->capture);
   }
   hipError_t le = hipGetLastError();
   e = hipStreamEndCapture(pl->capture, &pl->graph);
@@ -1174,6 +1623,15 @@ int chemora_plan_create_rk3(const chemora_params* params, const chemora_patch* p
                             chemora_plan** out) {
   g_error.clear();
   return plan_create(params, patches, scratch, npatch, courant, tune_cache_path, stream, out, true);
+}
+
+int chemora_plan_create_synced(const chemora_params* params, const chemora_patch* patches, double* const* scratch,
+                               int32_t npatch, double dt, int32_t integrator, const char* tune_cache_path,
+                               void* stream, chemora_plan** out) {
+  g_error.clear();
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CHEMORA_EINVAL, "dt must be finite and > 0");
+  if (integrator != 3 && integrator != 4) return fail(CHEMORA_EINVAL, "integrator %d not 3 or 4", integrator);
+  return plan_create(params, patches, scratch, npatch, 0.0, tune_cache_path, stream, out, integrator == 3, dt);
 }
 
 int chemora_plan_patch_variant(const chemora_plan* plan, int32_t p) {

@@ -330,6 +330,22 @@ def workload(index: int, n_override: Optional[int] = None) -> Workload:
     raise ValueError(f"no single-patch workload {index}")
 
 
+def bbh_share(n_override: Optional[int] = None) -> Workload:
+    """One GPU's share of the paper's production binary-black-hole run: 90^3
+    interior points with 5 ghost zones, 8th-order partially upwinded stencils
+    (Kreiss-Oliger r = 5) and the third-order Runge-Kutta integrator (section
+    "Binary Black Hole Simulations with Chemora": 270^3 over 27 GPUs on
+    [-6.75, 6.75]^3).  h = 13.5 / 270; the share is the block x in
+    [2.25, 6.75) of a 3 x 3 x 3 split, which holds the puncture at x = +3 of
+    the Brill-Lindquist data standing in for the paper's QC-0 initial data;
+    static ghosts, dt = h / 4."""
+    n = n_override or 90
+    h = 13.5 / 270.0
+    grid = Grid((n, n, n), 5, h, (2.25 + h / 2, -2.25 + h / 2, -2.25 + h / 2))
+    p = config_params(8, 1, 5, 5, BC_STATIC)
+    return Workload(f"bbh-share-{n}^3-o8-upwind-rk3", p, grid, lambda: brill_lindquist(grid), 0.25 * h, 100)
+
+
 def patch_list(seed: int = 1311, npatch: int = 64, nmin: int = 24, nmax: int = 96,
                refine: bool = True) -> List[Grid]:
     """Uneven patch set of the batched workload: even patches are cubes with

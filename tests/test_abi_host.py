@@ -161,6 +161,17 @@ def test_rk4_argument_checks_on_host():
     assert C.lib().chemora_rk4_scratch_elems(None) == 0
 
 
+def test_radiative_boundary_needs_finite_origin_on_host():
+    p, g = _good()
+    p.bc = I.BC_RADIATIVE
+    bad = I.Grid(g.n, g.ghost, g.h, (0.0, float("nan"), 0.0))
+    assert _call_rhs(p, bad) == C.EINVAL and "origin" in C.last_error()
+    assert _call_rk4(p, bad) == C.EINVAL and "origin" in C.last_error()
+    # the same origin is metadata for the other boundaries
+    p.bc = I.BC_STATIC
+    assert _call_rhs(p, bad, u=0) == C.EINVAL and "origin" not in C.last_error()
+
+
 def test_rk4_noalloc_argument_checks_on_host():
     p, g = _good()
 
@@ -305,6 +316,43 @@ def test_plan_rejects_aliased_buffers_on_host():
     assert "overlaps" in C.last_error()
     # scratch buffers of two patches overlap by one element
     assert create([base, base + state], [far, far + 3 * state - 8]) == C.EINVAL
+    assert out.value is None
+
+
+def test_synced_plan_checks_on_host():
+    """Bad dt / integrator, periodic ghosts, spacings that are not a
+    power-of-two hierarchy, origins off their lattice and refined patches
+    whose ghosts no coarser patch covers are refused before any HIP call."""
+    p, _ = _good()
+    L = C.lib()
+    out = ctypes.c_void_p(0)
+
+    def create(params, grids, dt=0.01, integ=4):
+        P = C.make_params(params)
+        state = max(24 * g.sf * 8 for g in grids)
+        us = [FAKE + q * 4 * state for q in range(len(grids))]
+        scs = [FAKE + (1 << 36) + q * 4 * state for q in range(len(grids))]
+        arr = (C.chemora_patch * len(grids))(*[C.make_patch(g, u) for g, u in zip(grids, us)])
+        sc = (ctypes.c_void_p * len(grids))(*[ctypes.c_void_p(v) for v in scs])
+        return L.chemora_plan_create_synced(ctypes.byref(P), arr, sc, len(grids), dt, integ, None, None,
+                                            ctypes.byref(out))
+
+    coarse = I.Grid((8, 8, 8), 3, 0.5, (0.0, 0.0, 0.0))
+    fine_ok = I.Grid((6, 6, 6), 3, 0.25, (1.0, 1.0, 1.0))
+    for dt in (0.0, -1.0, float("nan")):
+        assert create(p, [coarse, fine_ok], dt=dt) == C.EINVAL and "dt" in C.last_error()
+    assert create(p, [coarse, fine_ok], integ=5) == C.EINVAL and "integrator" in C.last_error()
+    per = I.Params(**vars(p))
+    per.bc = I.BC_PERIODIC
+    assert create(per, [coarse, fine_ok]) == C.EUNSUPPORTED
+    # a fine patch reaching past the coarse stored box
+    assert create(p, [coarse, I.Grid((20, 6, 6), 3, 0.25, (1.0, 1.0, 1.0))]) == C.EINVAL
+    assert "no patch" in C.last_error()
+    # origin off the fine lattice; spacing ratio 3
+    assert create(p, [coarse, I.Grid((4, 4, 4), 3, 0.25, (1.1, 1.0, 1.0))]) == C.EINVAL
+    assert "lattice" in C.last_error()
+    assert create(p, [coarse, I.Grid((4, 4, 4), 3, 0.5 / 3, (1.0, 1.0, 1.0))]) == C.EINVAL
+    assert "spacing" in C.last_error()
     assert out.value is None
 
 

@@ -793,3 +793,216 @@ def test_split_precision_bar_against_fp64_oracle(torch_cuda):
     h_split = float(np.sqrt(np.mean(oracle.hamiltonian(p64, g, split, nthreads=NTHREADS) ** 2)))
     say(f"H rms: FP64 oracle {h_ref:.6e}, split {h_split:.6e}, ratio {h_split / h_ref:.6f}")
     assert h_split <= 2.0 * h_ref
+
+
+# ---- radiative (Sommerfeld) outer boundary: every ghost point evolves ------
+
+class _WholeBox:
+    """A grid view whose 'interior' is every stored point of the box (ghosts
+    included, row padding not): the points the radiative boundary evolves."""
+
+    def __init__(self, g):
+        self.g = g
+
+    def interior(self):
+        e = self.g.ext
+        return (slice(0, e[2]), slice(0, e[1]), slice(0, e[0]))
+
+
+RADIATIVE_CASES = [
+    # (id, order, upwind, ko, ghost, n, lapse, shift)
+    ("o4-upwind-1+log", 4, 1, 3, 3, (37, 22, 15), I.LAPSE_ONE_PLUS_LOG, I.SHIFT_GAMMA_DRIVER),
+    ("o8-upwind-1+log", 8, 1, 5, 5, (20, 14, 11), I.LAPSE_ONE_PLUS_LOG, I.SHIFT_GAMMA_DRIVER),
+    ("o4-centred-harmonic-frozen-shift", 4, 0, 2, 2, (17, 19, 9), I.LAPSE_HARMONIC, I.SHIFT_FROZEN),
+]
+
+
+def _radiative_case(case):
+    name, order, upwind, ko, ghost, n, lapse, shift = case
+    h = 1.0 / 8.0
+    # off-centre and off every axis: all gradient components, both face ends
+    g = I.Grid(n, ghost, h, (0.9, -1.7, 0.6))
+    p = I.config_params(order, upwind, ghost, ko, I.BC_RADIATIVE)
+    p.lapse, p.shift = lapse, shift
+    u = I.brill_lindquist(g)
+    I.add_sinusoids(u, g, np.random.default_rng(1360 + order + ghost), 1e-3, range(I.NGF), periodic_ghosts=False)
+    return p, g, u
+
+
+@pytest.mark.parametrize("case", RADIATIVE_CASES, ids=[c[0] for c in RADIATIVE_CASES])
+def test_radiative_boundary_rhs_and_steps_against_oracle(torch_cuda, case):
+    """Right-hand side at interior and ghost points, 3 RK4 steps and 3 RK3
+    steps (ghosts evolved by the boundary condition), per GF over every stored
+    point, against the oracle."""
+    p, g, u = _radiative_case(case)
+    box = _WholeBox(g)
+    say(f"radiative {case[0]}: n={g.n} g={g.ghost}")
+    got = gpu_rhs(torch_cuda, p, g, u)
+    ref = oracle.rhs(p, g, u, nthreads=NTHREADS)
+    assert np.all(np.isfinite(ref[(slice(None),) + box.interior()]))
+    assert_parity(got, ref, box, 1e-12, f"radiative rhs {case[0]}")
+    dt = 0.25 * g.h
+    got = gpu_rk4(torch_cuda, p, g, u, dt, 3)
+    ref = oracle.rk4(p, g, u, dt, 3, nthreads=NTHREADS)
+    assert_parity(got, ref, box, 1e-10, f"radiative rk4 {case[0]}")
+    got = gpu_rk3(torch_cuda, p, g, u, dt, 3)
+    ref = oracle.rk3(p, g, u, dt, 3, nthreads=NTHREADS)
+    assert_parity(got, ref, box, 1e-10, f"radiative rk3 {case[0]}")
+
+
+def test_radiative_plan_equals_per_patch_steps(torch_cuda):
+    """Plans launch the boundary kernel per patch and stage: the same state
+    as per-patch RK4 and RK3 steps, bitwise."""
+    from paper_1307_6488_amd import chemora as C
+    torch = torch_cuda
+    p = I.config_params(4, 1, 3, 3, I.BC_RADIATIVE)
+    grids = _small_patches(count=3, seed=11, off_axis=True)
+    states = []
+    for q, g in enumerate(grids):
+        u = I.brill_lindquist(g)
+        I.add_sinusoids(u, g, np.random.default_rng(60 + q), 1e-3, range(24), periodic_ghosts=False)
+        states.append(u)
+    say("radiative plans: " + " ".join(str(g.n) for g in grids))
+    for integ, step in (("rk4", gpu_rk4), ("rk3", gpu_rk3)):
+        B = C.Batch(p, grids, states, 0.25, integrator=integ)
+        B.step(2)
+        torch.cuda.synchronize()
+        got = [q.u.cpu().numpy() for q in B.patches]
+        B.close()
+        for g, u0, a in zip(grids, states, got):
+            ref = step(torch, p, g, u0, 0.25 * g.h, 2)
+            assert np.array_equal(a, ref, equal_nan=True), integ
+            assert not np.array_equal(a[:, :3], u0[:, :3]), integ     # ghost planes moved
+
+
+# ---- Psi4 (Weyl scalar of outgoing radiation) ------------------------------
+
+PSI4_CASES = [
+    # (id, order, ghost, n, origin): odd extents of a grid centred on the
+    # coordinate origin put points on the z axis and at the origin itself
+    ("o4-ragged-offcentre", 4, 3, (37, 22, 15), (0.9, -1.7, 0.6)),
+    ("o4-through-origin-and-z-axis", 4, 3, (21, 19, 17), None),
+    ("o8-ragged", 8, 5, (20, 14, 11), (1.3, 0.4, -0.9)),
+]
+
+
+@pytest.mark.parametrize("case", PSI4_CASES, ids=[c[0] for c in PSI4_CASES])
+def test_psi4_against_oracle(torch_cuda, case):
+    """Psi4 (real and imaginary part) at every interior point of perturbed
+    Brill-Lindquist data with nonzero K and At, against the oracle, per part
+    (max-norm normalised, bar 1e-12)."""
+    from paper_1307_6488_amd import chemora as C
+    name, order, ghost, n, origin = case
+    h = 1.0 / 8.0
+    g = I.centred_grid(n, ghost, h) if origin is None else I.Grid(n, ghost, h, origin)
+    p = I.config_params(order, 1, ghost, ghost, I.BC_STATIC)
+    u = I.brill_lindquist(g, centres=((2.05, 0.3, -0.2), (-2.1, -0.25, 0.15)))
+    I.add_sinusoids(u, g, np.random.default_rng(1370 + order), 1e-3, range(I.NGF), periodic_ghosts=False)
+    say(f"psi4 {name}: n={g.n} order={order}")
+    P = C.Patch(p, g, u)
+    got = P.psi4().cpu().numpy()
+    torch_cuda.cuda.synchronize()
+    ref = oracle.psi4(p, g, u, nthreads=NTHREADS)
+    assert np.all(np.isfinite(ref)) and np.all(np.isfinite(got))
+    for part, what in ((0, "re"), (1, "im")):
+        scale = np.max(np.abs(ref[part]))
+        err = np.max(np.abs(got[part] - ref[part])) / scale
+        say(f"psi4 {name} {what}: max |ref| {scale:.3e}, err {err:.2e}")
+        assert scale > 1e-6 and err <= 1e-12, (what, err)
+
+
+# ---- synchronised plans: ghost exchange, prolongation, restriction ---------
+
+def _split_x(g, cut):
+    a = I.Grid((cut, g.n[1], g.n[2]), g.ghost, g.h, g.origin)
+    b = I.Grid((g.n[0] - cut, g.n[1], g.n[2]), g.ghost, g.h, (g.origin[0] + cut * g.h, g.origin[1], g.origin[2]))
+    return a, b
+
+
+def _sub_state(u, sub, off):
+    v = I.alloc_state(sub)
+    e = sub.ext
+    v[:, :, :, :e[0]] = u[:, :, :, off:off + e[0]]
+    return v
+
+
+@pytest.mark.parametrize("integ", ["rk4", "rk3"])
+def test_synced_plan_two_patch_split_equals_single_grid(torch_cuda, integ):
+    """One grid split into two abutting patches in a synchronised plan is
+    bitwise the single grid stepped alone (same kernels, ghost exchange after
+    every stage)."""
+    from paper_1307_6488_amd import chemora as C
+    torch = torch_cuda
+    p = I.config_params(4, 1, 3, 3, I.BC_STATIC)
+    g = I.Grid((45, 20, 14), 3, 0.125, (1.1, -1.3, 0.4))
+    u = I.brill_lindquist(g)
+    I.add_sinusoids(u, g, np.random.default_rng(1400), 1e-3, range(I.NGF), periodic_ghosts=False)
+    a, b = _split_x(g, 19)
+    dt = 0.25 * g.h
+    say(f"synced split {integ}: {g.n} -> {a.n} + {b.n}")
+    B = C.Batch(p, [a, b], [_sub_state(u, a, 0), _sub_state(u, b, 19)], integrator=integ, synced_dt=dt)
+    B.step(3)
+    torch.cuda.synchronize()
+    got = [q.u.cpu().numpy() for q in B.patches]
+    B.close()
+    ref = (gpu_rk4 if integ == "rk4" else gpu_rk3)(torch, p, g, u, dt, 3)
+    assert np.array_equal(got[0][:, :, :, :a.ext[0]], ref[:, :, :, :a.ext[0]])
+    assert np.array_equal(got[1][:, :, :, :b.ext[0]], ref[:, :, :, 19:19 + b.ext[0]])
+
+
+def _two_level(order, ghost, bc):
+    """Two abutting coarse patches (h = 1/4) and one refined patch (h = 1/8)
+    straddling their interface: Brill-Lindquist data (punctures outside the
+    patches, so that the FP64 evolution bar applies) plus 1e-3 sinusoids."""
+    hc = 0.25
+    c0 = I.Grid((14, 22, 20), ghost, hc, (-3.5, -2.75, -2.5))
+    c1 = I.Grid((12, 22, 20), ghost, hc, (-3.5 + 14 * hc, -2.75, -2.5))
+    hf = hc / 2
+    f = I.Grid((21, 18, 15), ghost, hf, (-3.5 + 19 * hf, -2.75 + 13 * hf, -2.5 + 17 * hf))
+    grids = [c0, c1, f]
+    p = I.config_params(order, 1, ghost, ghost, bc)
+    states = []
+    for q, g in enumerate(grids):
+        u = I.brill_lindquist(g, centres=((4.5, 0.3, -0.2), (-5.0, -0.25, 0.15)))
+        I.add_sinusoids(u, g, np.random.default_rng(1410 + q), 1e-3, range(I.NGF), periodic_ghosts=False)
+        states.append(u)
+    return p, grids, states
+
+
+@pytest.mark.parametrize("order,ghost,bc,integ", [(4, 3, I.BC_STATIC, 4), (4, 3, I.BC_RADIATIVE, 4),
+                                                  (4, 3, I.BC_STATIC, 3), (8, 5, I.BC_STATIC, 4)],
+                         ids=["o4-static-rk4", "o4-radiative-rk4", "o4-static-rk3", "o8-static-rk4"])
+def test_synced_plan_two_levels_against_oracle(torch_cuda, order, ghost, bc, integ):
+    """A refined patch across the interface of two coarse patches, stepped in
+    a synchronised plan, against the oracle's synchronised steps: every stored
+    point of every patch (evolution bar)."""
+    from paper_1307_6488_amd import chemora as C
+    torch = torch_cuda
+    p, grids, states = _two_level(order, ghost, bc)
+    dt = 0.25 * grids[2].h
+    say(f"synced two-level order {order} bc {bc} integrator {integ}: " + " ".join(str(g.n) for g in grids))
+    B = C.Batch(p, grids, states, integrator="rk4" if integ == 4 else "rk3", synced_dt=dt)
+    B.step(3)
+    torch.cuda.synchronize()
+    got = [q.u.cpu().numpy() for q in B.patches]
+    B.close()
+    ref = oracle.steps_synced(p, grids, states, dt, 3, integ, nthreads=NTHREADS)
+    for q, (g, a, r) in enumerate(zip(grids, got, ref)):
+        assert_parity(a, r, _WholeBox(g), 1e-10, f"synced patch {q}")
+
+
+def test_bbh_share_rk3_step_against_oracle(torch_cuda):
+    """The paper's production shape on one GPU -- 90^3 interior points, 5
+    ghost zones, 8th-order partially upwinded stencils, third-order
+    Runge-Kutta, the share holding a puncture -- in the launch configuration
+    the benchmark times: one step against the oracle (evolution bar) and the
+    FP64-accuracy bar against the extended-precision oracle (near the puncture
+    the FP64 oracle itself is off by up to ~3e-12 after one step)."""
+    w = I.bbh_share()
+    u = w.make_state()
+    say(f"bbh share {w.name}: one RK3 step")
+    got = gpu_rk3(torch_cuda, w.params, w.grid, u, w.dt, 1)
+    orc = oracle.rk3(w.params, w.grid, u, w.dt, 1, nthreads=NTHREADS)
+    assert_parity(got, orc, w.grid, 1e-10, "bbh share rk3")
+    ext = oracle.rk3_ext(w.params, w.grid, u, w.dt, 1, nthreads=NTHREADS)
+    assert_fp64_accuracy(got, orc, ext, w.grid, "bbh share rk3 fp64 accuracy")
