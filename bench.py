@@ -50,6 +50,13 @@ MEASURED_TRAFFIC = {
 KERNEL_SOURCES = ["stage_kernel.hpp", "stage_common.hpp", "fd_ops.hpp", "stage_o4.hip", "stage_o8.hip"]
 
 
+def tile_name(C, variant):
+    """A tile variant as 'TXxTY' (one plane) or 'TXxTYxTZ'."""
+    tx, ty = C.chemora_tile_variant_shape(variant)
+    tz = C.chemora_tile_variant_depth(variant)
+    return f"{tx}x{ty}" + (f"x{tz}" if tz > 1 else "")
+
+
 def kernel_sources_sha256():
     import hashlib
     root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1307_6488_amd", "csrc")
@@ -124,7 +131,7 @@ def main():
     # timed region; it times stage-2 launches of this patch)
     variant = C.chemora_tile_variant(P.params, P.patch) if args.no_tune else \
         C.chemora_tune(P.params, P.patch, sp, None, stream)
-    tile = C.chemora_tile_variant_shape(variant)
+    tile = tile_name(C, variant)
 
     def step():
         for s in (1, 2, 3, 4):
@@ -174,7 +181,7 @@ def main():
     bytes23 = 5 * 24 * 8 * npts
     achieved = bytes23 / t23 / 1e9
     flops_update = 4 * RHS_FLOPS[w.params.fd_order] + RK4_FLOPS
-    traffic = measured_traffic(w.name, f"{tile[0]}x{tile[1]}")
+    traffic = measured_traffic(w.name, tile)
     out = {
         "metric": METRIC,
         "value": value,
@@ -197,7 +204,7 @@ def main():
             "ko_radius": w.params.ko_radius,
             "dt": w.dt,
             "boundary": "static",
-            "tile": f"{tile[0]}x{tile[1]}",
+            "tile": tile,
             "tuned": not args.no_tune,
         },
         "roofline": {
@@ -294,17 +301,17 @@ def order8_form(C, I, torch, no_tune, steps=5, warmup=1):
     stream = torch.cuda.current_stream()
     variant = C.chemora_tile_variant(P.params, P.patch) if no_tune else C.chemora_tune(P.params, P.patch, sp, None,
                                                                                          stream)
-    tile = C.chemora_tile_variant_shape(variant)
+    tile = tile_name(C, variant)
     stage_timed_steps(C, torch, P, w.dt, sp, warmup)
     ms, t23 = stage_timed_steps(C, torch, P, w.dt, sp, steps)
     npts = w.grid.npoints
     gbs = 960 * npts / (t23 * 1e-3) / 1e9
-    traffic = measured_traffic(w.name, f"{tile[0]}x{tile[1]}")
+    traffic = measured_traffic(w.name, tile)
     del P
     torch.cuda.empty_cache()
     return {"workload": w.name, "interior": list(w.grid.n), "fd_order": 8, "ghost": w.params.ghost,
             "steps": steps, "ms_per_step": ms, "value": npts / (ms * 1e-3), "unit": "updates/s",
-            "tile": f"{tile[0]}x{tile[1]}",
+            "tile": tile,
             "stage23": {"avg_launch_ms": t23, "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
                         "traffic": traffic},
             "step_hbm_frac": npts / (ms * 1e-3) * 3072 / (HBM_PEAK_GBS * 1e9),
@@ -365,7 +372,7 @@ def batched_form(C, I, torch, no_tune, steps=10, warmup=2):
     B3.close()
     return {"workload": "64 patches, 24-96 points per edge, order 4 upwind (batched plan)", "patches": len(grids),
             "points": npts, "steps": steps, "ms_per_step": ms, "value": npts / (ms * 1e-3),
-            "unit": "updates/s", "tile_variants": [f"{a}x{b}" for a, b in map(C.chemora_tile_variant_shape, variants)],
+            "unit": "updates/s", "tile_variants": [tile_name(C, v) for v in variants],
             "hbm_frac": npts / (ms * 1e-3) * 3072 / (HBM_PEAK_GBS * 1e9),
             "per_patch": {"ms_per_step": ms_pp, "value": npts / (ms_pp * 1e-3),
                           "calls": "one chemora_rk4_step per patch and step, same tile variants"},
@@ -456,8 +463,7 @@ def split_form(C, I, torch, no_tune, steps=100, warmup=2):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
-        tile = C.chemora_tile_variant_shape(variant)
-        res[name] = {"ms_per_step": ms, "value": w.grid.npoints / (ms * 1e-3), "tile": f"{tile[0]}x{tile[1]}"}
+        res[name] = {"ms_per_step": ms, "value": w.grid.npoints / (ms * 1e-3), "tile": tile_name(C, variant)}
         ix = torch.as_tensor(g + sub, device=P.u.device)
         st[name] = P.u.index_select(1, ix).index_select(2, ix).index_select(3, ix).cpu().numpy()
         # H of the final state, evaluated in FP64 for both runs
@@ -500,12 +506,12 @@ def bbh_share_form(C, I, torch, no_tune, steps=20, warmup=2):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     npts = w.grid.npoints
-    tile = C.chemora_tile_variant_shape(variant)
+    tile = tile_name(C, variant)
     del P
     torch.cuda.empty_cache()
     return {"workload": w.name, "interior": list(w.grid.n), "ghost": w.params.ghost, "fd_order": 8,
             "integrator": "SSP RK3", "steps": steps, "ms_per_step": ms, "value": npts / (ms * 1e-3),
-            "unit": "updates/s", "tile": f"{tile[0]}x{tile[1]}", "algorithmic_bytes_per_update": 1536,
+            "unit": "updates/s", "tile": tile, "algorithmic_bytes_per_update": 1536,
             "hbm_frac": npts / (ms * 1e-3) * 1536 / (HBM_PEAK_GBS * 1e9)}
 
 

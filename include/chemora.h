@@ -277,8 +277,9 @@ int chemora_hamiltonian(const chemora_params *params, const chemora_patch *patch
 
 /* ---- autotuner: tile variants per size class -----------------------------
  * The stage kernel runs in one of several tile shapes ("variants": 0 = 64x4,
- * 1 = 64x8, 2 = 32x8, 3 = 32x16 points per work-group, x by y; order 8
- * builds 0 and 2).  In FP64 all variants compute bit-identical results; in
+ * 1 = 64x8, 2 = 32x8, 3 = 32x16 points per work-group, x by y, one z plane;
+ * 4 = 32x8x2 and 5 = 32x4x4, x by y by z, whose work-groups share the
+ * z halo of their planes; order 8 builds 0 and 2).  In FP64 all variants compute bit-identical results; in
  * split precision they agree to FP32 rounding (their FP32 kernels are
  * compiled separately).  They differ in lane use on ragged extents, halo
  * overhead, staging depth and occupancy.  The choice is
@@ -313,6 +314,10 @@ int chemora_set_tile_variant(const chemora_params *params, const chemora_patch *
 
 /* Tile extent of a variant in x and y (either pointer may be NULL). */
 int chemora_tile_variant_shape(int32_t variant, int32_t *tile_x, int32_t *tile_y);
+
+/* Tile depth of a variant: the z planes one work-group evaluates (>= 1; the
+ * tuner's z-sweep dimension), or a negative status for an unknown id. */
+int chemora_tile_variant_depth(int32_t variant);
 
 /* ---- batched form: many patches advanced together ------------------------
  * Section "Cactus-Carpet Computational Infrastructure": block-structured

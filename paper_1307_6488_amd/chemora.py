@@ -27,7 +27,7 @@ EXPORTS = (
     "chemora_plan_patch_variant", "chemora_tune", "chemora_tile_variant", "chemora_set_tile_variant",
     "chemora_tile_variant_shape", "chemora_hamiltonian", "chemora_rk3_scratch_elems", "chemora_rk3_step",
     "chemora_enforce_constraints", "chemora_momentum_constraint", "chemora_plan_create_rk3",
-    "chemora_rk4_step_noalloc", "chemora_psi4", "chemora_plan_create_synced",
+    "chemora_rk4_step_noalloc", "chemora_psi4", "chemora_plan_create_synced", "chemora_tile_variant_depth",
 )
 # CHEMORA_NOALLOC_SCRATCH_ELEMS of include/chemora.h
 NOALLOC_SCRATCH_ELEMS = 8 << 20
@@ -117,6 +117,8 @@ def lib() -> ctypes.CDLL:
         L.chemora_tile_variant_shape.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                                  ctypes.POINTER(ctypes.c_int32)]
         L.chemora_tile_variant_shape.restype = ctypes.c_int
+        L.chemora_tile_variant_depth.argtypes = [ctypes.c_int32]
+        L.chemora_tile_variant_depth.restype = ctypes.c_int
         L.chemora_abi_version.argtypes = []
         L.chemora_abi_version.restype = ctypes.c_int
         _lib = L
@@ -298,6 +300,10 @@ def chemora_tile_variant_shape(variant: int):
     tx, ty = ctypes.c_int32(0), ctypes.c_int32(0)
     _check(lib().chemora_tile_variant_shape(variant, ctypes.byref(tx), ctypes.byref(ty)))
     return int(tx.value), int(ty.value)
+
+
+def chemora_tile_variant_depth(variant: int) -> int:
+    return _check_id(lib().chemora_tile_variant_depth(variant))
 
 
 def chemora_abi_version() -> int:

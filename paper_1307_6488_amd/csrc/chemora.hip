@@ -177,20 +177,28 @@ __global__ __launch_bounds__(256) void momentum_kernel(const double* __restrict_
   const int j = blockIdx.y * 4 + threadIdx.y;
   const int k = blockIdx.z;
   if (i >= G.nx || j >= G.ny) return;
-  const int64_t at = (int64_t)(k + G.g) * G.sz + (int64_t)(j + G.g) * G.sy + (i + G.g);
-  const int64_t st[3] = {1, G.sy, G.sz};
+  // loads as in psi4_kernel: one biased per-lane offset, the grid function
+  // and tap offsets in the scalar offset
+  const int at = (k + G.g) * (int)G.sz + (j + G.g) * (int)G.sy + (i + G.g);
+  const int st[3] = {1, (int)G.sy, (int)G.sz};
+  constexpr int R = Stencil<ORDER>::R;
+  const int bias = R * ((int)G.sz + (int)G.sy + 1);
+  const __amdgpu_buffer_rsrc_t rs = state_rsrc(u, G.sf);
+  const unsigned vat = (unsigned)(at - bias + XB) * 8u;
+  auto tap = [&](int f, int off) __attribute__((always_inline)) {
+    return bload(rs, vat, (unsigned)(f * (unsigned)G.sf + (unsigned)(bias + off)) * 8u);
+  };
   auto D = [&](int f, int a) {
-    const double* p = u + f * G.sf + at;
-    const int64_t s = st[a];
-    return Stencil<ORDER>::first([&](int o) { return p[o * s]; }) * d1s;
+    const int s = st[a];
+    return Stencil<ORDER>::first([&](int o) { return tap(f, o * s); }) * d1s;
   };
   double g[6], A[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    g[q] = u[(gGT + q) * G.sf + at];
-    A[q] = u[(gAT + q) * G.sf + at];
+    g[q] = tap(gGT + q, 0);
+    A[q] = tap(gAT + q, 0);
   }
-  const double chi = u[gCHI * G.sf + at];
+  const double chi = tap(gCHI, 0);
   const double c00 = g[3] * g[5] - g[4] * g[4], c01 = g[2] * g[4] - g[1] * g[5], c02 = g[1] * g[4] - g[2] * g[3];
   const double c11 = g[0] * g[5] - g[2] * g[2], c12 = g[1] * g[2] - g[0] * g[4], c22 = g[0] * g[3] - g[1] * g[1];
   const double idet = 1.0 / (g[0] * c00 + g[1] * c01 + g[2] * c02);
@@ -235,7 +243,7 @@ __global__ __launch_bounds__(256) void momentum_kernel(const double* __restrict_
     for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
       for (int l = 0; l < 3; ++l) acc -= 1.5 / chi * gu[S(kk, l)] * A[S(a, l)] * dchi[kk];
-    M[a * G.sf + at] = acc - (2.0 / 3.0) * dK[a];
+    (M + (int64_t)a * G.sf)[at] = acc - (2.0 / 3.0) * dK[a];
   }
 }
 
@@ -263,23 +271,53 @@ __global__ __launch_bounds__(256) void psi4_kernel(const double* __restrict__ u,
   const int j = blockIdx.y * 4 + threadIdx.y;
   const int k = blockIdx.z;
   if (i >= G.nx || j >= G.ny) return;
-  const int64_t at = (int64_t)(k + G.g) * G.sz + (int64_t)(j + G.g) * G.sy + (i + G.g);
-  const int64_t st[3] = {1, G.sy, G.sz};
+  // Loads through one buffer resource: the per-lane part of every address is
+  // the point (one register, biased by the stencils' reach so that it stays
+  // non-negative), the grid function and the tap offset are uniform (scalar
+  // offset), so no load needs address arithmetic of its own.
+  const int at = (k + G.g) * (int)G.sz + (j + G.g) * (int)G.sy + (i + G.g);
+  const int st[3] = {1, (int)G.sy, (int)G.sz};
+  const int bias = St::R * ((int)G.sz + (int)G.sy + 1);
+  const __amdgpu_buffer_rsrc_t rs = state_rsrc(u, G.sf);
+  const unsigned vat = (unsigned)(at - bias + XB) * 8u;
   const double d1s = 1.0 / (St::D1 * h), d2s = 1.0 / (St::D2 * h * h), d11s = d1s * d1s;
-  auto val = [&](int f) { return u[f * G.sf + at]; };
-  auto D1 = [&](int f, int a) {
-    const double* p = u + f * G.sf + at;
-    const int64_t s = st[a];
-    return St::first([&](int o) { return p[o * s]; }) * d1s;
+  auto tap = [&](int f, int off) __attribute__((always_inline)) {
+    return bload(rs, vat, (unsigned)(f * (unsigned)G.sf + (unsigned)(bias + off)) * 8u);
   };
-  // second derivative of slot q (xx xy xz yy yz zz)
-  auto D2 = [&](int f, int q) {
-    const double* p = u + f * G.sf + at;
+  auto val = [&](int f) { return tap(f, 0); };
+  // every derivative is materialised and fenced off by a scheduling barrier:
+  // hoisting the loads of all of them ahead (to hide latency) would keep
+  // hundreds of values live and spill
+  auto fence = [](double& v) __attribute__((always_inline)) {
+    keep(v);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto D1 = [&](int f, int a) __attribute__((always_inline)) {
+    const int s = st[a];
+    double v = St::first([&](int o) { return tap(f, o * s); }) * d1s;
+    fence(v);
+    return v;
+  };
+  // second derivative of slot q (xx xy xz yy yz zz); a mixed one is the
+  // outer first derivative of inner ones, fenced per inner derivative
+  auto D2 = [&](int f, int q) __attribute__((always_inline)) {
     const int a = SI(q), b = SJ(q);
-    if (a == b) return St::second([&](int o) { return p[o * st[a]]; }) * d2s;
-    return St::first([&](int oa) {
-             return St::first([&](int ob) { return p[oa * st[a] + ob * st[b]]; });
-           }) * d11s;
+    double v;
+    if (a == b) {
+      v = St::second([&](int o) { return tap(f, o * st[a]); }) * d2s;
+    } else {
+      double in[2 * St::R];
+#pragma unroll
+      for (int k = 1; k <= St::R; ++k) {
+        in[St::R - k] = St::first([&](int ob) { return tap(f, -k * st[a] + ob * st[b]); });
+        fence(in[St::R - k]);
+        in[St::R + k - 1] = St::first([&](int ob) { return tap(f, k * st[a] + ob * st[b]); });
+        fence(in[St::R + k - 1]);
+      }
+      v = St::first([&](int oa) { return oa < 0 ? in[St::R + oa] : in[St::R + oa - 1]; }) * d11s;
+    }
+    fence(v);
+    return v;
   };
   double g[6], A[6];
 #pragma unroll
@@ -348,6 +386,7 @@ __global__ __launch_bounds__(256) void psi4_kernel(const double* __restrict__ u,
         for (int kk = 0; kk < 3; ++kk)
           r += gu[S(l, m)] * (Gu[kk][S(l, a)] * Gl[b][S(kk, m)] + Gu[kk][S(l, b)] * Gl[a][S(kk, m)] +
                               Gu[kk][S(a, m)] * Gl[kk][S(l, b)]);
+    fence(r);
     Ric[q] = r;
   }
   {
@@ -420,6 +459,7 @@ __global__ __launch_bounds__(256) void psi4_kernel(const double* __restrict__ u,
                  Kd[q] * dchi[kk] * ichi;
 #pragma unroll
       for (int m = 0; m < 3; ++m) d -= Gam(m, kk, l) * Kd[S(m, jj)] + Gam(m, kk, jj) * Kd[S(l, m)];
+      fence(d);
       DK[q] = d;
     }
     // eps_a^{kl} = gamma^{kc} gamma^{ld} eps_acd, eps_acd = sq [acd]
@@ -498,7 +538,7 @@ __global__ __launch_bounds__(256) void psi4_kernel(const double* __restrict__ u,
   const double Ett = contract(Ew, et, et), Epp = contract(Ew, ep, ep), Etp = contract(Ew, et, ep);
   const double Btt = contract(Bw, et, et), Bpp = contract(Bw, ep, ep), Btp = contract(Bw, et, ep);
   out[at] = 0.5 * (Ett - Epp) - Btp;
-  out[G.sf + at] = -Etp - 0.5 * (Btt - Bpp);
+  (out + G.sf)[at] = -Etp - 0.5 * (Btt - Bpp);
 }
 
 __global__ __launch_bounds__(256) void finite_kernel(const double* __restrict__ u, Geo G,
@@ -626,6 +666,9 @@ chemora::Scales make_scales(const chemora_params* P, double h) {
   return s;
 }
 
+// tile planes of tile variant v over nz planes
+int tile_planes(int nz, int v) { return (nz + chemora::variant_tz(v) - 1) / chemora::variant_tz(v); }
+
 // tile counts of tile variant v
 void set_tiles(chemora::StageArgs& a, int v) {
   a.tiles_x = (a.geo.nx + chemora::VARIANTS[v].tx - 1) / chemora::VARIANTS[v].tx;
@@ -637,7 +680,7 @@ void dispatch_stage(const chemora_params* P, chemora::StageArgs& a, int v, hipSt
   chemora::BatchTable none;
   std::memset(&none, 0, sizeof none);
   set_tiles(a, v);
-  const int tiles = a.tiles_x * a.tiles_y * a.geo.nz;
+  const int tiles = a.tiles_x * a.tiles_y * tile_planes(a.geo.nz, v);
   if (P->fd_order == 4)
     chemora::launch_stage_o4(v, P->precision == CHEMORA_PREC_SPLIT, P->upwind != 0, P->ko_radius, a, none, tiles,
                              s);
@@ -721,7 +764,9 @@ int choose_variant(const chemora_params* P, const chemora_patch* X) {
 }
 
 std::string variant_name(int v) {
-  return std::to_string(chemora::VARIANTS[v].tx) + "x" + std::to_string(chemora::variant_ty(v));
+  std::string n = std::to_string(chemora::VARIANTS[v].tx) + "x" + std::to_string(chemora::variant_ty(v));
+  if (chemora::variant_tz(v) > 1) n += "x" + std::to_string(chemora::variant_tz(v));
+  return n;
 }
 
 // Reads a cache file (the JSON save_cache writes, in any whitespace layout):
@@ -1308,6 +1353,12 @@ int chemora_tile_variant_shape(int32_t variant, int32_t* tile_x, int32_t* tile_y
   return CHEMORA_OK;
 }
 
+int chemora_tile_variant_depth(int32_t variant) {
+  g_error.clear();
+  if (variant < 0 || variant >= chemora::NVARIANT) return fail(CHEMORA_EINVAL, "tile variant %d unknown", variant);
+  return chemora::variant_tz(variant);
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -1477,7 +1528,7 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
       const size_t state = (size_t)CHEMORA_NGF * X->sf;
       chemora::StageArgs a = base_args(params, X);
       set_tiles(a, g.variant);
-      tiles += (int64_t)a.tiles_x * a.tiles_y * a.geo.nz;
+      tiles += (int64_t)a.tiles_x * a.tiles_y * tile_planes(a.geo.nz, g.variant);
       if (tiles > INT32_MAX) {
         plan_free(pl);
         return fail(CHEMORA_EINVAL, "too many tiles in the plan");

@@ -164,16 +164,18 @@ __device__ __forceinline__ int batch_patch(const BatchTable& bt, int t) {
 }
 
 // ---- tile variants: the launch shapes the tuner chooses among -----------
-// TX columns x WPG waves per work-group (a wave covers 64 / TX rows).
+// TX columns x WPG waves per work-group over TZ planes (a wave covers
+// 64 / TX rows of one plane): tiles of TX x TY x TZ points.
 struct TileVariant {
-  int tx, wpg;
+  int tx, wpg, tz;
 };
-constexpr int NVARIANT = 4;
-constexpr TileVariant VARIANTS[NVARIANT] = {{64, 4}, {64, 8}, {32, 4}, {32, 8}};
-inline int variant_ty(int v) { return VARIANTS[v].wpg * 64 / VARIANTS[v].tx; }
+constexpr int NVARIANT = 6;
+constexpr TileVariant VARIANTS[NVARIANT] = {{64, 4, 1}, {64, 8, 1}, {32, 4, 1}, {32, 8, 1}, {32, 8, 2}, {32, 8, 4}};
+inline int variant_ty(int v) { return VARIANTS[v].wpg / VARIANTS[v].tz * 64 / VARIANTS[v].tx; }
+inline int variant_tz(int v) { return VARIANTS[v].tz; }
 // order 8's staged neighbourhood is too large for the 8-wave shapes
 inline bool variant_supported(int order, int v) {
-  return v >= 0 && v < NVARIANT && (order == 4 || VARIANTS[v].wpg == 4);
+  return v >= 0 && v < NVARIANT && (order == 4 || (VARIANTS[v].wpg == 4 && VARIANTS[v].tz == 1));
 }
 
 // ---- host-side launchers, one per order (stage_o4.hip / stage_o8.hip) ----

@@ -60,21 +60,30 @@
 
 namespace chemora {
 
-// Tile shape: TX (32 or 64) columns, WPG waves per work-group; a wave covers
-// 64 / TX rows of TX points, so a tile is TX x TY with TY = WPG * 64 / TX.
-template <int TX_, int WPG_>
+// Tile shape: TX (32 or 64) columns, WPG waves per work-group, TZ planes; a
+// wave covers 64 / TX rows of TX points of one plane, WPG / TZ waves cover a
+// plane, so a tile is TX x TY x TZ with TY = (WPG / TZ) * 64 / TX.
+template <int TX_, int WPG_, int TZ_ = 1>
 struct Shape {
-  static constexpr int TX = TX_, WPG = WPG_;
+  static constexpr int TX = TX_, WPG = WPG_, TZ = TZ_;
   static constexpr int RPW = 64 / TX;          // rows per wave
-  static constexpr int TY = WPG * RPW;
+  static constexpr int WPP = WPG / TZ;         // waves per plane
+  static constexpr int TY = WPP * RPW;
   static constexpr int NT = 64 * WPG;          // work-items per work-group
   static_assert(TX == 32 || TX == 64, "tile width");
+  static_assert(TZ >= 1 && WPG % TZ == 0, "tile depth");
 };
 
+template <int R, int RM, class SH, int TZ = SH::TZ>
+struct LdsLayout;
+
+// One plane per tile: the neighbourhood is cut to what the stencils reach
+// (see the file header).
 template <int R, int RM, class SH>
-struct LdsLayout {
+struct LdsLayout<R, RM, SH, 1> {
   static constexpr int TX = SH::TX, TY = SH::TY;
   static constexpr int P = TX + 2 * R;
+  static constexpr int PLANE_STEP = 0;   // one plane: no per-plane anchor shift
   static constexpr int ROWS0 = TY + 2 * R, ROWS1 = TY + 2 * RM, ROWS2 = TY;
   static constexpr int SIZE = P * (ROWS0 + 2 * RM * ROWS1 + 2 * (R - RM) * ROWS2);
   static constexpr int CHUNK = 128;                          // doubles per LDS-DMA instruction
@@ -126,6 +135,45 @@ struct LdsLayout {
       a = RM + q / 2 + 1;
     }
     dz = (q & 1) ? -a : a;
+  }
+};
+
+// TZ planes per tile: the TZ + 2R planes dz = -R .. TZ-1+R are stored whole
+// (rows -R .. TY-1+R, columns -R .. TX-1+R) and in order, so that a tap of a
+// work-item on tile plane tz is at a compile-time offset from its anchor
+// tz * PLANE + y * P + x whatever tz is -- the z halo is shared by the TZ
+// planes instead of staged once per plane.
+template <int R, int RM, class SH, int TZ>
+struct LdsLayout {
+  static constexpr int TX = SH::TX, TY = SH::TY;
+  static constexpr int P = TX + 2 * R;
+  static constexpr int ROWS = TY + 2 * R;
+  static constexpr int PLANE = ROWS * P;
+  static constexpr int PLANE_STEP = PLANE;   // anchor shift per tile plane
+  static constexpr int NPL = TZ + 2 * R;
+  static constexpr int SIZE = NPL * PLANE;
+  static constexpr int CHUNK = 128;
+  static constexpr int NCHUNK = (SIZE + CHUNK - 1) / CHUNK;
+  static constexpr int SIZEP = NCHUNK * CHUNK;
+  static constexpr int CPW = (NCHUNK + SH::WPG - 1) / SH::WPG;
+  static constexpr int CMIN = NCHUNK / SH::WPG;
+  static_assert(P % 2 == 0, "a lane's pair of doubles must not straddle rows");
+  // offset of tap (dx, dy, dz) from the anchor of a work-item on plane 0
+  __host__ __device__ static constexpr int off(int dx, int dy, int dz) {
+    return (dz + R) * PLANE + (dy + R) * P + (dx + R);
+  }
+  // tile-relative point (x, y, dz) stored at LDS double idx (the padding
+  // past SIZE maps to (0, 0, 0))
+  __host__ __device__ static constexpr void decode(int idx, int& x, int& y, int& dz) {
+    if (idx >= SIZE) {
+      x = 0; y = 0; dz = 0;
+      return;
+    }
+    const int q = idx / PLANE, r = idx - q * PLANE;
+    const int row = r / P;
+    dz = q - R;
+    y = row - R;
+    x = r - row * P - R;
   }
 };
 
@@ -192,23 +240,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   constexpr int RM = ORDER / 2;
   using L = LdsLayout<R, RM, SH>;
   const Geo G = a.geo;
+  const int nzb = (G.nz + SH::TZ - 1) / SH::TZ;   // tile planes
   const int txi = t % a.tiles_x;
-  const int k = (t / a.tiles_x) % G.nz;
-  const int tyi = t / (a.tiles_x * G.nz);
+  const int kb = (t / a.tiles_x) % nzb;
+  const int tyi = t / (a.tiles_x * nzb);
   // threadIdx.y is the wave index: uniform across the wave, so keep it (and
   // everything the staging derives from it) in scalar registers
   const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
-  const int xr = lane % SH::TX, yr = wave * SH::RPW + lane / SH::TX;   // tile-relative point
-  const int i0 = txi * SH::TX, j0 = tyi * SH::TY;
-  const bool valid = (i0 + xr < G.nx) && (j0 + yr < G.ny);
+  const int tz = wave / SH::WPP;                                        // the wave's tile plane
+  const int xr = lane % SH::TX, yr = (wave % SH::WPP) * SH::RPW + lane / SH::TX;   // tile-relative point
+  const int i0 = txi * SH::TX, j0 = tyi * SH::TY, k0 = kb * SH::TZ;
+  const int k = k0 + tz;
+  const bool valid = (i0 + xr < G.nx) && (j0 + yr < G.ny) && (k < G.nz);
   // pointwise accesses of work-items outside the interior use a clamped point
-  const int ic = min(i0 + xr, G.nx - 1), jc = min(j0 + yr, G.ny - 1);
+  const int ic = min(i0 + xr, G.nx - 1), jc = min(j0 + yr, G.ny - 1), kc = min(k, G.nz - 1);
 
   // byte offsets are unsigned 32-bit (the host limits a state to 4 GiB)
   const unsigned sy = (unsigned)G.sy, sz = (unsigned)G.sz, sf = (unsigned)G.sf, gg = (unsigned)G.g;
   const __amdgpu_buffer_rsrc_t rin = state_rsrc(a.in, G.sf);
   const unsigned vpt = (jc * sy + ic + gg) * 8u + XB * 8u;       // the point (pointwise accesses)
-  const unsigned spt = ((k + gg) * sz + gg * sy) * 8u;          // its z plane / ghost offset
+  const unsigned spt = ((kc + gg) * sz + gg * sy) * 8u;         // its z plane / ghost offset
   auto val = [&](int f) __attribute__((always_inline)) { return bload(rin, vpt, spt + f * sf * 8u); };
 
   // ---- staging offsets of this tile.  Lane l of wave w moves LDS doubles
@@ -221,6 +272,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // biased by (R sz + R sy + R) so that it stays non-negative.
   const int xmax = G.nx - 1 + R - i0;       // last tile-relative column inside the box
   const int ymax = G.ny - 1 + R - j0;       // last tile-relative row inside the box
+  const int zmax = G.nz - 1 + R - k0;       // last tile-relative plane inside the box
   const unsigned bias = (unsigned)R * (sz + sy + 1u);
   unsigned voff[L::CPW];
   // opaque copies: the decode depends only on lane and wave, and hoisted out
@@ -234,13 +286,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     int x, y, dz;
     L::decode((wave_t + SH::WPG * q) * L::CHUNK + 2 * lane_t, x, y, dz);
     y = min(y, ymax);
+    dz = min(dz, zmax);
     if (x > xmax) x = xmax - 1;
     voff[q] = (unsigned)(dz * (int)sz + y * (int)sy + x + (int)bias) * 8u;
     // OFFS_LDS: park the offsets in LDS (each lane reads back only its own
     // slots, so no barrier is involved) and free their registers
     if (OFFS_LDS) offs[q * SH::NT + wave * 64 + lane] = voff[q];
   }
-  const unsigned tile_base = ((k + gg) * sz + (j0 + gg) * sy + i0 + gg + XB) * 8u - bias * 8u;
+  const unsigned tile_base = ((k0 + gg) * sz + (j0 + gg) * sy + i0 + gg + XB) * 8u - bias * 8u;
   auto issue = [&](int f, double* dst) __attribute__((always_inline)) {
     const unsigned so = tile_base + f * sf * 8u;
 #pragma unroll
@@ -252,7 +305,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     }
   };
 
-  const int anchor = yr * L::P + xr;
+  const int anchor = (SH::TZ > 1 ? tz * L::PLANE_STEP : 0) + yr * L::P + xr;
   // Stencil taps of the current phase's buffer.  Each phase addresses it from
   // an opaque copy of the anchor: LDS reads are merged in pairs (8-bit
   // offsets, +-2 KB), so a buffer needs a base register per 2 KB it spans,
@@ -936,10 +989,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
 // OCC waves share a SIMD (OCC * 4 / WPG work-groups per CU): their NB
 // staging buffers must fit the 160 KB LDS together, and the registers per
 // lane drop to 512 / OCC.
-template <int ORDER, bool UPWIND, int R, int NB, int OCC, int TX, int WPG, typename T>
+template <int ORDER, bool UPWIND, int R, int NB, int OCC, int TX, int WPG, typename T, int TZ = 1>
 __global__ __launch_bounds__(64 * WPG) __attribute__((amdgpu_waves_per_eu(OCC)))
 void stage_kernel(StageArgs a1, BatchTable bt) {
-  using SH = Shape<TX, WPG>;
+  using SH = Shape<TX, WPG, TZ>;
   using L = LdsLayout<R, ORDER / 2, SH>;
   static_assert(NB >= 2 && NB <= 5, "staging depth");
   // FP64 with two waves per SIMD keeps the per-lane staging offsets in LDS

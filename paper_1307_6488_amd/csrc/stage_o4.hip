@@ -20,9 +20,9 @@ namespace chemora {
 namespace {
 // LDS of one work-group: nb staging buffers, plus the parked staging
 // offsets where the kernel keeps them in LDS (FP64 at two waves per SIMD)
-template <int TX, int WPG, int R, typename T>
+template <int TX, int WPG, int R, typename T, int TZ>
 constexpr int lds_bytes(int nb, int occ) {
-  using L = LdsLayout<R, 2, Shape<TX, WPG>>;
+  using L = LdsLayout<R, 2, Shape<TX, WPG, TZ>>;
   return nb * L::SIZEP * 8 + ((occ == 2 && sizeof(T) == 8) ? L::CPW * 64 * WPG * 4 : 0);
 }
 template <int WPG>
@@ -36,36 +36,38 @@ constexpr int wgs_per_cu(int occ) {
 #ifndef CHEMORA_SPLIT_MAX_WAVES
 #define CHEMORA_SPLIT_MAX_WAVES 3
 #endif
-template <int TX, int WPG, int R, typename T>
+template <int TX, int WPG, int R, typename T, int TZ>
 constexpr int occupancy() {
   if (!std::is_same<T, float>::value) return CHEMORA_WAVES_O4;
-  return CHEMORA_SPLIT_MAX_WAVES >= 3 && wgs_per_cu<WPG>(3) * lds_bytes<TX, WPG, R, T>(2, 3) <= 160 * 1024 ? 3 : 2;
+  return CHEMORA_SPLIT_MAX_WAVES >= 3 && wgs_per_cu<WPG>(3) * lds_bytes<TX, WPG, R, T, TZ>(2, 3) <= 160 * 1024 ? 3
+                                                                                                           : 2;
 }
 
-template <int TX, int WPG, int R, typename T>
+template <int TX, int WPG, int R, typename T, int TZ>
 constexpr int depth() {
-  constexpr int occ = occupancy<TX, WPG, R, T>();
+  constexpr int occ = occupancy<TX, WPG, R, T, TZ>();
   int nb = 2;
-  while (nb < CHEMORA_MAX_DEPTH_O4 && wgs_per_cu<WPG>(occ) * lds_bytes<TX, WPG, R, T>(nb + 1, occ) <= 160 * 1024)
+  while (nb < CHEMORA_MAX_DEPTH_O4 &&
+         wgs_per_cu<WPG>(occ) * lds_bytes<TX, WPG, R, T, TZ>(nb + 1, occ) <= 160 * 1024)
     ++nb;
   return nb;
 }
 
-template <int TX, int WPG, bool UPWIND, int R, typename T>
+template <int TX, int WPG, int TZ, bool UPWIND, int R, typename T>
 void launch(const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(
-      (stage_kernel<4, UPWIND, R, depth<TX, WPG, R, T>(), occupancy<TX, WPG, R, T>(), TX, WPG, T>),
-      dim3(grid), dim3(64, WPG, 1), 0, s, a, bt);
+  hipLaunchKernelGGL((stage_kernel<4, UPWIND, R, depth<TX, WPG, R, T, TZ>(), occupancy<TX, WPG, R, T, TZ>(), TX,
+                                   WPG, T, TZ>),
+                     dim3(grid), dim3(64, WPG, 1), 0, s, a, bt);
 }
 
-template <int TX, int WPG, typename T>
+template <int TX, int WPG, typename T, int TZ = 1>
 void by_reach(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
   if (upwind)
-    launch<TX, WPG, true, 3, T>(a, bt, grid, s);
+    launch<TX, WPG, TZ, true, 3, T>(a, bt, grid, s);
   else if (ko_r > 2)
-    launch<TX, WPG, false, 3, T>(a, bt, grid, s);
+    launch<TX, WPG, TZ, false, 3, T>(a, bt, grid, s);
   else
-    launch<TX, WPG, false, 2, T>(a, bt, grid, s);
+    launch<TX, WPG, TZ, false, 2, T>(a, bt, grid, s);
 }
 
 template <typename T>
@@ -75,6 +77,8 @@ void by_variant(int variant, bool upwind, int ko_r, const StageArgs& a, const Ba
     case 1: by_reach<64, 8, T>(upwind, ko_r, a, bt, grid, s); break;
     case 2: by_reach<32, 4, T>(upwind, ko_r, a, bt, grid, s); break;
     case 3: by_reach<32, 8, T>(upwind, ko_r, a, bt, grid, s); break;
+    case 4: by_reach<32, 8, T, 2>(upwind, ko_r, a, bt, grid, s); break;
+    case 5: by_reach<32, 8, T, 4>(upwind, ko_r, a, bt, grid, s); break;
     default: by_reach<64, 4, T>(upwind, ko_r, a, bt, grid, s); break;
   }
 }

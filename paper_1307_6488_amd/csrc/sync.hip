@@ -216,6 +216,11 @@ int build_sync_maps(const chemora_params* P, const chemora_patch* X, int np, Syn
             M.fill.push_back(it);
           }
     }
+    // within the level, the items grouped by their stencil (copies first,
+    // then by the set of midpoint axes) and kept in destination order inside
+    // a group: a wave then runs one loop shape, without divergence
+    std::stable_sort(M.fill.begin() + M.fill_start.back(), M.fill.end(),
+                     [](const SyncItem& x, const SyncItem& y) { return x.mid < y.mid; });
     M.fill_start.push_back((int)M.fill.size());
   }
   // restriction, finest pair first

@@ -357,19 +357,23 @@ def test_synced_plan_checks_on_host():
 
 
 def test_tile_variant_shapes_and_table_on_host():
-    assert [C.chemora_tile_variant_shape(v) for v in range(4)] == [(64, 4), (64, 8), (32, 8), (32, 16)]
-    assert C.lib().chemora_tile_variant_shape(4, None, None) == C.EINVAL
+    assert [C.chemora_tile_variant_shape(v) for v in range(6)] == [(64, 4), (64, 8), (32, 8), (32, 16), (32, 8),
+                                                                   (32, 4)]
+    assert [C.chemora_tile_variant_depth(v) for v in range(6)] == [1, 1, 1, 1, 2, 4]
+    assert C.lib().chemora_tile_variant_shape(6, None, None) == C.EINVAL
+    assert C.lib().chemora_tile_variant_depth(6) == C.EINVAL and C.lib().chemora_tile_variant_depth(-1) == C.EINVAL
     p, g = _good()
     P, X = C.make_params(p), C.make_patch(g, FAKE)
     before = C.chemora_tile_variant(P, X)
     try:
-        for v in range(4):
+        for v in range(6):
             C.chemora_set_tile_variant(P, X, v)
             assert C.chemora_tile_variant(P, X) == v
         assert C.lib().chemora_set_tile_variant(ctypes.byref(P), ctypes.byref(X), 7) == C.EINVAL
         p8 = I.workload(3, n_override=16).params
         P8, X8 = C.make_params(p8), C.make_patch(I.workload(3, n_override=16).grid, FAKE)
-        assert C.lib().chemora_set_tile_variant(ctypes.byref(P8), ctypes.byref(X8), 1) == C.EUNSUPPORTED
+        for v in (1, 3, 4, 5):
+            assert C.lib().chemora_set_tile_variant(ctypes.byref(P8), ctypes.byref(X8), v) == C.EUNSUPPORTED
         assert "not built for order 8" in C.last_error()
         bad = C.make_params(p)
         bad.fd_order = 6

@@ -488,7 +488,7 @@ def test_tile_variants_are_bitwise_identical(torch_cuda, index, n):
     u = I.brill_lindquist(grid)
     I.add_sinusoids(u, grid, np.random.default_rng(77), 1e-4, range(24), periodic_ghosts=False)
     P, X = C.make_params(w.params), C.make_patch(grid, 0x7F0000001000)   # class key only
-    built = [v for v in range(4) if w.params.fd_order == 4 or v in (0, 2)]
+    built = [v for v in range(6) if w.params.fd_order == 4 or v in (0, 2)]
     before = C.chemora_tile_variant(P, X)
     ref = None
     try:
@@ -497,7 +497,7 @@ def test_tile_variants_are_bitwise_identical(torch_cuda, index, n):
             assert C.chemora_tile_variant(P, X) == v
             r = gpu_rhs(torch_cuda, w.params, grid, u)
             e = gpu_rk4(torch_cuda, w.params, grid, u, 0.25 * grid.h, 2)
-            say(f"variant {v} {C.chemora_tile_variant_shape(v)} on {n}: done")
+            say(f"variant {v} {C.chemora_tile_variant_shape(v)} x {C.chemora_tile_variant_depth(v)} on {n}: done")
             if ref is None:
                 ref = (r, e)
                 continue
@@ -525,7 +525,7 @@ def test_tuned_plan_matches_per_patch_steps_and_writes_cache(torch_cuda, tmp_pat
     for g, v in zip(grids, variants):
         P, X = C.make_params(params), C.make_patch(g, 0x7F0000001000)
         assert C.chemora_tile_variant(P, X) == v
-    assert all(e["variant"] in range(4) and "ms" in e for e in d["entries"].values() if e.get("ms") is not None)
+    assert all(e["variant"] in range(6) and "ms" in e for e in d["entries"].values() if e.get("ms") is not None)
     assert len(d["entries"]) >= len({tuple(v for v in (g.n[0] <= 32, g.n[1] <= 16)) for g in grids})
     B.step(2)
     torch.cuda.synchronize()
