@@ -56,6 +56,19 @@ struct Stencil<4> {
     const double c = at(0);
     return -3.0 * (at(-s) - c) + 18.0 * (at(s) - c) - 6.0 * (at(2 * s) - c) + (at(3 * s) - c);
   }
+  // The lopsided stencil toward +axis is (A + Q) / 2 and its mirror
+  // (A - Q) / 2, with the antisymmetric part A = 21 b1 - 6 b2 + b3
+  // (b_k = u_k - u_-k) and the symmetric part Q = 15 s1 - 6 s2 + s3
+  // (s_k = (u_k - u_0) + (u_-k - u_0)), the sixth difference that
+  // Kreiss-Oliger dissipation of radius 3 sums too.  So for either sign of
+  // the advecting velocity, beta * lopsided = UA beta A + UQ |beta| Q.
+  static constexpr int UR = 3;
+  static constexpr double UA = 0.5, UQ = 0.5;
+  static constexpr double USYM[5] = {15.0, -6.0, 1.0, 0.0, 0.0};
+  template <class F>
+  __device__ static __forceinline__ double upwind_anti(F&& at) {
+    return 21.0 * (at(1) - at(-1)) - 6.0 * (at(2) - at(-2)) + (at(3) - at(-3));
+  }
   // split precision: FP64 differences rounded to FP32, FP32 weights
   template <class F>
   __device__ static __forceinline__ float first_f(F&& at) {
@@ -98,6 +111,18 @@ struct Stencil<8> {
            1050.0 * (at(s) - c) - 420.0 * (at(2 * s) - c) + 140.0 * (at(3 * s) - c) -
            30.0 * (at(4 * s) - c) + 3.0 * (at(5 * s) - c);
   }
+  // lopsided (offsets -3..5) = A + 1.5 Q and its mirror A - 1.5 Q (in units
+  // of 1/840h), A = 735 b1 - 240 b2 + 72.5 b3 - 15 b4 + 1.5 b5 and Q the
+  // tenth difference 210 s1 - 120 s2 + 45 s3 - 10 s4 + s5 of Kreiss-Oliger
+  // dissipation of radius 5
+  static constexpr int UR = 5;
+  static constexpr double UA = 1.0, UQ = 1.5;
+  static constexpr double USYM[5] = {210.0, -120.0, 45.0, -10.0, 1.0};
+  template <class F>
+  __device__ static __forceinline__ double upwind_anti(F&& at) {
+    return 735.0 * (at(1) - at(-1)) - 240.0 * (at(2) - at(-2)) + 72.5 * (at(3) - at(-3)) -
+           15.0 * (at(4) - at(-4)) + 1.5 * (at(5) - at(-5));
+  }
   // split-precision forms (the host builds split precision for order 4 only)
   template <class F>
   __device__ static __forceinline__ float first_f(F&& at) {
@@ -120,7 +145,8 @@ struct Stencil<8> {
 };
 
 // Kreiss-Oliger term along one axis for radius r <= RMAX (the reach of the
-// caller's staged neighbourhood): the weighted sum of the symmetric
+// caller's staged neighbourhood; ko_sum is the sum before the scale, which
+// the upwind decomposition above reuses): the weighted sum of the symmetric
 // differences s_k = (u_k - u_0) + (u_-k - u_0), accumulated from k = 1 upward
 // with the integer weights w[k-1] of the radius (zero past it, so that the
 // radius is data, not a branch), times scale = 2^(-2r) eps / h.  It is a
@@ -129,7 +155,7 @@ struct Stencil<8> {
 // is then reproducible to the bit across compilers and independent of how
 // the rest is scheduled.  A zero weight adds an exact zero.
 template <int RMAX, class F>
-__device__ __forceinline__ double ko_axis(F&& at, const double (&w)[5], double scale) {
+__device__ __forceinline__ double ko_sum(F&& at, const double (&w)[5]) {
 #pragma clang fp contract(off)
   static_assert(RMAX >= 1 && RMAX <= 5, "radius");
   const double c = at(0);
@@ -137,7 +163,13 @@ __device__ __forceinline__ double ko_axis(F&& at, const double (&w)[5], double s
   double acc = w[0] * s(1);
 #pragma unroll
   for (int k = 2; k <= RMAX; ++k) acc = acc + w[k - 1] * s(k);
-  return acc * scale;
+  return acc;
+}
+
+template <int RMAX, class F>
+__device__ __forceinline__ double ko_axis(F&& at, const double (&w)[5], double scale) {
+#pragma clang fp contract(off)
+  return ko_sum<RMAX>(at, w) * scale;
 }
 
 // Split precision: the symmetric differences are formed in FP64 and rounded

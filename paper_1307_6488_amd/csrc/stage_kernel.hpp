@@ -228,7 +228,8 @@ __device__ __forceinline__ void wait_staged(int m) {
 // cover a block that is deep in z and share their z halos in its L2.  Every
 // work-item of the work-group must call it (it synchronises); it ends with a
 // barrier, so the buffers may be reused right after.
-template <int ORDER, bool UPWIND, int R, int NB, bool BOUND, bool OFFS_LDS, bool PARK, class SH, typename T>
+template <int ORDER, bool UPWIND, int R, int NB, bool BOUND, bool OFFS_LDS, bool PARK, class SH, typename T,
+          bool KOQ>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* const (&bufs)[NB], unsigned* offs,
                                            double* park) {
   // T: the arithmetic type of stencil combinations and algebra -- double, or
@@ -381,6 +382,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // The stencils below take a precision tag: double() gives the FP64 forms,
   // float() the split forms (FP64 differences rounded to FP32, FP32 weights).
   const double bet_d[3] = {val(gBETA), val(gBETA + 1), val(gBETA + 2)};
+  // FP64 upwinding as UA beta A + UQ |beta| Q per axis (fd_ops.hpp): the
+  // velocity factors with the 1/(DU h) scale folded in, once per point
+  double bA[3], bQ[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    bA[ax] = (St::UA * a.sc.up) * bet_d[ax];
+    bQ[ax] = (St::UQ * a.sc.up) * __builtin_fabs(bet_d[ax]);
+  }
   auto D1 = [&](auto tag, const auto& src, int ax) __attribute__((always_inline)) {
     using TC = decltype(tag);
     auto along = [&](int o) __attribute__((always_inline)) { return src(ax, o); };
@@ -476,31 +485,39 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     for (int ax = 0; ax < 3; ++ax) {
       auto along = [&](int o) __attribute__((always_inline)) { return src(ax, o); };
       const TC b = TC(bet_d[ax]);
-      TC d;
-      if (UPWIND) {
-        // both lopsided stencils from the same taps, then select by the sign of beta
-        if constexpr (F32) {
+      TC qd;
+      if constexpr (UPWIND && !F32) {
+        // the antisymmetric part and the symmetric difference Q of the
+        // lopsided stencils, Q summed exactly as Kreiss-Oliger sums (so with
+        // KOQ -- the dissipation radius is Q's, or 0 -- the dissipation is
+        // Q times its scale, the same bits as the separate sum)
+        const double Qs = ko_sum<St::UR>(along, St::USYM);
+        const double As = St::upwind_anti(along);
+        adv = __builtin_fma(bA[ax], As, __builtin_fma(bQ[ax], Qs, adv));
+        if constexpr (KOQ)
+          qd = Qs * a.sc.ko;
+        else
+          qd = ko_axis<R>(along, a.sc.kow, a.sc.ko);
+      } else {
+        TC d;
+        if constexpr (UPWIND) {
+          // both lopsided stencils from the same taps, then select by the sign of beta
           const float dp = St::lopsided_f(along, 1);
           const float dm = -St::lopsided_f([&](int o) { return along(-o); }, 1);
           d = (bet_d[ax] >= 0.0 ? dp : dm) * float(a.sc.up);
         } else {
-          const double dp = St::lopsided(along, 1);
-          const double dm = -St::lopsided([&](int o) { return along(-o); }, 1);
-          d = (bet_d[ax] >= 0.0 ? dp : dm) * a.sc.up;
+          if constexpr (F32)
+            d = St::first_f(along) * float(a.sc.d1);
+          else
+            d = St::first(along) * a.sc.d1;
         }
-      } else {
+        adv += b * d;
+        // radius 0 has zero weights and scale: the term is an exact zero
         if constexpr (F32)
-          d = St::first_f(along) * float(a.sc.d1);
+          qd = ko_axis_f<R>(along, a.sc.kow, float(a.sc.ko));
         else
-          d = St::first(along) * a.sc.d1;
+          qd = ko_axis<R>(along, a.sc.kow, a.sc.ko);
       }
-      adv += b * d;
-      // radius 0 has zero weights and scale: the term is an exact zero
-      TC qd;
-      if constexpr (F32)
-        qd = ko_axis_f<R>(along, a.sc.kow, float(a.sc.ko));
-      else
-        qd = ko_axis<R>(along, a.sc.kow, a.sc.ko);
       diss = (ax == 0) ? qd : diss + qd;
       bound(adv);
       bound(diss);
@@ -989,7 +1006,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
 // OCC waves share a SIMD (OCC * 4 / WPG work-groups per CU): their NB
 // staging buffers must fit the 160 KB LDS together, and the registers per
 // lane drop to 512 / OCC.
-template <int ORDER, bool UPWIND, int R, int NB, int OCC, int TX, int WPG, typename T, int TZ = 1>
+template <int ORDER, bool UPWIND, int R, int NB, int OCC, int TX, int WPG, typename T, int TZ = 1, bool KOQ = false>
 __global__ __launch_bounds__(64 * WPG) __attribute__((amdgpu_waves_per_eu(OCC)))
 void stage_kernel(StageArgs a1, BatchTable bt) {
   using SH = Shape<TX, WPG, TZ>;
@@ -1022,7 +1039,7 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
     a = uniform_args(bt.args + p);
     t -= uniform(bt.tile_start[p]);
   }
-  stage_tile<ORDER, UPWIND, R, NB, (ORDER >= 8 || OCC >= 2), OFFS_LDS, PARK, SH, T>(a, t, bufs, offs, park);
+  stage_tile<ORDER, UPWIND, R, NB, (ORDER >= 8 || OCC >= 2), OFFS_LDS, PARK, SH, T, KOQ>(a, t, bufs, offs, park);
 }
 
 }  // namespace chemora

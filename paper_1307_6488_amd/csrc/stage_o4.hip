@@ -53,16 +53,21 @@ constexpr int depth() {
   return nb;
 }
 
-template <int TX, int WPG, int TZ, bool UPWIND, int R, typename T>
+template <int TX, int WPG, int TZ, bool UPWIND, int R, typename T, bool KOQ = false>
 void launch(const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
   hipLaunchKernelGGL((stage_kernel<4, UPWIND, R, depth<TX, WPG, R, T, TZ>(), occupancy<TX, WPG, R, T, TZ>(), TX,
-                                   WPG, T, TZ>),
+                                   WPG, T, TZ, KOQ>),
                      dim3(grid), dim3(64, WPG, 1), 0, s, a, bt);
 }
 
+// Upwinded FP64 kernels reuse the sixth difference of the lopsided stencils
+// as the Kreiss-Oliger sum when the dissipation radius is 3 (or 0: zero scale)
 template <int TX, int WPG, typename T, int TZ = 1>
 void by_reach(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
-  if (upwind)
+  constexpr bool FP64 = !std::is_same<T, float>::value;
+  if (upwind && FP64 && (ko_r == Stencil<4>::UR || ko_r == 0))
+    launch<TX, WPG, TZ, true, 3, T, FP64>(a, bt, grid, s);
+  else if (upwind)
     launch<TX, WPG, TZ, true, 3, T>(a, bt, grid, s);
   else if (ko_r > 2)
     launch<TX, WPG, TZ, false, 3, T>(a, bt, grid, s);

@@ -15,15 +15,20 @@
 namespace chemora {
 
 namespace {
-template <int TX, int WPG, bool UPWIND, int R>
+template <int TX, int WPG, bool UPWIND, int R, bool KOQ = false>
 void launch(const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((stage_kernel<8, UPWIND, R, CHEMORA_STAGING_DEPTH_O8, CHEMORA_WAVES_O8, TX, WPG, double>),
-                     dim3(grid), dim3(64, WPG, 1), 0, s, a, bt);
+  hipLaunchKernelGGL(
+      (stage_kernel<8, UPWIND, R, CHEMORA_STAGING_DEPTH_O8, CHEMORA_WAVES_O8, TX, WPG, double, 1, KOQ>), dim3(grid),
+      dim3(64, WPG, 1), 0, s, a, bt);
 }
 
+// the upwinded kernels reuse the tenth difference of the lopsided stencils as
+// the Kreiss-Oliger sum when the dissipation radius is 5 (or 0)
 template <int TX, int WPG>
 void by_reach(bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid, hipStream_t s) {
-  if (upwind)
+  if (upwind && (ko_r == Stencil<8>::UR || ko_r == 0))
+    launch<TX, WPG, true, 5, true>(a, bt, grid, s);
+  else if (upwind)
     launch<TX, WPG, true, 5>(a, bt, grid, s);
   else if (ko_r > 4)
     launch<TX, WPG, false, 5>(a, bt, grid, s);
