@@ -1387,7 +1387,7 @@ struct chemora_plan {
   hipGraphExec_t exec = nullptr;
   // synchronised plans: ghost refill / restriction maps and their buffers
   bool synced = false;
-  std::vector<int> fill_start, restr_start;
+  std::vector<int> fill_start, fill_copies, restr_start;
   chemora::SyncItem* d_fill = nullptr;
   chemora::SyncItem* d_restr = nullptr;
   chemora::SyncGeo* d_geo = nullptr;
@@ -1425,12 +1425,13 @@ namespace {
 void plan_restrict_and_fill(const chemora_plan* pl, double* const* bufs, bool restrict_first, hipStream_t s) {
   const int order = pl->params.fd_order;
   if (restrict_first)
-    for (size_t q = 0; q + 1 < pl->restr_start.size(); ++q)
-      chemora::launch_sync(order, pl->d_restr + pl->restr_start[q], pl->restr_start[q + 1] - pl->restr_start[q], bufs,
-                           pl->d_geo, s);
+    for (size_t q = 0; q + 1 < pl->restr_start.size(); ++q) {
+      const int n = pl->restr_start[q + 1] - pl->restr_start[q];   // all copies
+      chemora::launch_sync(order, pl->d_restr + pl->restr_start[q], n, n, bufs, pl->d_geo, s);
+    }
   for (size_t L = 0; L + 1 < pl->fill_start.size(); ++L)
-    chemora::launch_sync(order, pl->d_fill + pl->fill_start[L], pl->fill_start[L + 1] - pl->fill_start[L], bufs,
-                         pl->d_geo, s);
+    chemora::launch_sync(order, pl->d_fill + pl->fill_start[L], pl->fill_start[L + 1] - pl->fill_start[L],
+                         pl->fill_copies[L], bufs, pl->d_geo, s);
 }
 
 // dt_all > 0: a synchronised plan -- every patch steps with dt_all and the
@@ -1561,6 +1562,7 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
   if (synced) {
     pl->synced = true;
     pl->fill_start = maps.fill_start;
+    pl->fill_copies = maps.fill_copies;
     pl->restr_start = maps.restr_start;
     for (int p = 0; p < npatch; ++p) geo.push_back({patches[p].sy, patches[p].sz, patches[p].sf});
     bufs.assign((size_t)(nst + 1) * npatch, nullptr);

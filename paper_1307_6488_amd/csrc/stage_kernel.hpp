@@ -45,12 +45,13 @@
 // for each of its wave's chunks is computed once per tile, so issuing a grid
 // function costs one instruction per chunk.  One barrier per grid function.
 //
-// LDS layout per staged grid function (pitch P = TX + 2R doubles):
+// LDS layout per staged grid function (one-plane tiles):
 //   plane dz = 0            rows y in [-R,  TY-1+R]   (x and y stencils, xy mixed)
 //   planes 1 <= |dz| <= RM  rows y in [-RM, TY-1+RM]  (xz / yz mixed, z stencils)
 //   planes RM < |dz| <= R   rows y in [0, TY-1]       (z stencils only)
 // with R the axis reach (upwind, Kreiss-Oliger) and RM = ORDER/2 the mixed
-// reach; planes are ordered dz = 0, +1, -1, +2, -2, ...
+// reach; planes are ordered dz = 0, +1, -1, +2, -2, ...; rows span columns
+// [-R, TX-1+R] (pitch P = TX + 2R).
 #pragma once
 
 #include <type_traits>
@@ -77,15 +78,25 @@ struct Shape {
 template <int R, int RM, class SH, int TZ = SH::TZ>
 struct LdsLayout;
 
+// Every layout maps a tap (dx, dy, dz) of a work-item to its anchor plus
+// off(dx, dy, dz), a compile-time constant; decode() is the inverse over the
+// buffer, and stage_point() the clamped point a staging lane loads.
+
 // One plane per tile: the neighbourhood is cut to what the stencils reach
-// (see the file header).
+// (see the file header).  Plane kinds by |dz|: 0 (dz = 0), 1 (|dz| <= RM)
+// and 2 (RM < |dz| <= R), with y halos R, RM, 0; every row has pitch
+// P = TX + 2R.
 template <int R, int RM, class SH>
 struct LdsLayout<R, RM, SH, 1> {
   static constexpr int TX = SH::TX, TY = SH::TY;
   static constexpr int P = TX + 2 * R;
-  static constexpr int PLANE_STEP = 0;   // one plane: no per-plane anchor shift
-  static constexpr int ROWS0 = TY + 2 * R, ROWS1 = TY + 2 * RM, ROWS2 = TY;
-  static constexpr int SIZE = P * (ROWS0 + 2 * RM * ROWS1 + 2 * (R - RM) * ROWS2);
+  __host__ __device__ static constexpr int kind(int dz) {
+    const int a = dz < 0 ? -dz : dz;
+    return a == 0 ? 0 : (a <= RM ? 1 : 2);
+  }
+  __host__ __device__ static constexpr int yh(int k) { return k == 0 ? R : (k == 1 ? RM : 0); }
+  __host__ __device__ static constexpr int psize(int k) { return P * (TY + 2 * yh(k)); }
+  static constexpr int SIZE = psize(0) + 2 * RM * psize(1) + 2 * (R - RM) * psize(2);
   static constexpr int CHUNK = 128;                          // doubles per LDS-DMA instruction
   static constexpr int NCHUNK = (SIZE + CHUNK - 1) / CHUNK;
   static constexpr int SIZEP = NCHUNK * CHUNK;               // buffer size incl. padding
@@ -93,20 +104,18 @@ struct LdsLayout<R, RM, SH, 1> {
   static constexpr int CMIN = NCHUNK / SH::WPG;                 // chunks per wave (at least)
   static_assert(P % 2 == 0, "a lane's pair of doubles must not straddle rows");
 
-  // first row (y = -yhalo) of plane dz, in doubles
+  // anchor of the work-item at tile point (xr, yr) (of the one plane)
+  __host__ __device__ static constexpr int anchor(int xr, int yr, int) { return yr * P + xr; }
+  // first element of plane dz (planes ordered dz = 0, +1, -1, +2, -2, ...)
   __host__ __device__ static constexpr int plane(int dz) {
     const int a = dz < 0 ? -dz : dz;
     if (a == 0) return 0;
-    if (a <= RM) return P * (ROWS0 + ((dz > 0 ? 2 * a - 1 : 2 * a) - 1) * ROWS1);
-    return P * (ROWS0 + 2 * RM * ROWS1 + ((dz > 0 ? 2 * (a - RM) - 1 : 2 * (a - RM)) - 1) * ROWS2);
+    if (a <= RM) return psize(0) + ((dz > 0 ? 2 * a - 1 : 2 * a) - 1) * psize(1);
+    return psize(0) + 2 * RM * psize(1) + ((dz > 0 ? 2 * (a - RM) - 1 : 2 * (a - RM)) - 1) * psize(2);
   }
-  __host__ __device__ static constexpr int yhalo(int dz) {
-    const int a = dz < 0 ? -dz : dz;
-    return a == 0 ? R : (a <= RM ? RM : 0);
-  }
-  // offset (doubles) of tap (dx, dy, dz) from the work-item's anchor ty*P + tx
+  // offset (doubles) of tap (dx, dy, dz) from the work-item's anchor
   __host__ __device__ static constexpr int off(int dx, int dy, int dz) {
-    return plane(dz) + (dy + yhalo(dz)) * P + (dx + R);
+    return plane(dz) + (dy + yh(kind(dz))) * P + (dx + R);
   }
   // inverse of off(): the tile-relative point (x, y, dz) stored at LDS double
   // idx; the padding past SIZE maps to the anchor (0, 0, 0)
@@ -115,26 +124,40 @@ struct LdsLayout<R, RM, SH, 1> {
       x = 0; y = 0; dz = 0;
       return;
     }
-    const int row = idx / P;
-    x = idx - row * P - R;
-    if (row < ROWS0) {
+    int k = 0, q = 0, r = idx;   // plane kind, plane index within the kind, offset in the plane
+    if (r < psize(0)) {
       dz = 0;
-      y = row - R;
-      return;
-    }
-    int r = row - ROWS0;
-    int a, q;
-    if (r < 2 * RM * ROWS1) {
-      q = r / ROWS1;
-      y = r - q * ROWS1 - RM;
-      a = q / 2 + 1;
+    } else if ((r -= psize(0)) < 2 * RM * psize(1)) {
+      k = 1;
+      q = r / psize(1);
+      r -= q * psize(1);
+      dz = (q & 1) ? -(q / 2 + 1) : q / 2 + 1;
     } else {
-      r -= 2 * RM * ROWS1;
-      q = r / ROWS2;
-      y = r - q * ROWS2;
-      a = RM + q / 2 + 1;
+      r -= 2 * RM * psize(1);
+      k = 2;
+      q = r / psize(2);
+      r -= q * psize(2);
+      dz = (q & 1) ? -(RM + q / 2 + 1) : RM + q / 2 + 1;
     }
-    dz = (q & 1) ? -a : a;
+    const int row = r / P;
+    y = row - yh(k);
+    x = r - row * P - R;
+  }
+  // the point a staging lane loads for LDS double idx of a tile at (i0, j0,
+  // k0), clamped into the staged reach of a patch of nx x ny x nz interior
+  // points: a row / column / plane of a ragged tile past it re-reads one
+  // inside (never used by a valid work-item).  Pairs start on even column
+  // offsets from -R; one whose first column is the last one inside is
+  // possible for odd nx only, and its second element then lies at most one
+  // column past the ghost zone (row padding, which the host guarantees for
+  // odd nx).
+  __host__ __device__ static constexpr void stage_point(int idx, int i0, int j0, int k0, int nx, int ny, int nz,
+                                                        int& x, int& y, int& dz) {
+    decode(idx, x, y, dz);
+    const int xmax = nx - 1 + R - i0, ymax = ny - 1 + R - j0, zmax = nz - 1 + R - k0;
+    y = y < ymax ? y : ymax;
+    dz = dz < zmax ? dz : zmax;
+    if (x > xmax) x = xmax - 1;
   }
 };
 
@@ -149,7 +172,6 @@ struct LdsLayout {
   static constexpr int P = TX + 2 * R;
   static constexpr int ROWS = TY + 2 * R;
   static constexpr int PLANE = ROWS * P;
-  static constexpr int PLANE_STEP = PLANE;   // anchor shift per tile plane
   static constexpr int NPL = TZ + 2 * R;
   static constexpr int SIZE = NPL * PLANE;
   static constexpr int CHUNK = 128;
@@ -158,6 +180,7 @@ struct LdsLayout {
   static constexpr int CPW = (NCHUNK + SH::WPG - 1) / SH::WPG;
   static constexpr int CMIN = NCHUNK / SH::WPG;
   static_assert(P % 2 == 0, "a lane's pair of doubles must not straddle rows");
+  __host__ __device__ static constexpr int anchor(int xr, int yr, int tz) { return tz * PLANE + yr * P + xr; }
   // offset of tap (dx, dy, dz) from the anchor of a work-item on plane 0
   __host__ __device__ static constexpr int off(int dx, int dy, int dz) {
     return (dz + R) * PLANE + (dy + R) * P + (dx + R);
@@ -174,6 +197,15 @@ struct LdsLayout {
     dz = q - R;
     y = row - R;
     x = r - row * P - R;
+  }
+  // as for one plane
+  __host__ __device__ static constexpr void stage_point(int idx, int i0, int j0, int k0, int nx, int ny, int nz,
+                                                        int& x, int& y, int& dz) {
+    decode(idx, x, y, dz);
+    const int xmax = nx - 1 + R - i0, ymax = ny - 1 + R - j0, zmax = nz - 1 + R - k0;
+    y = y < ymax ? y : ymax;
+    dz = dz < zmax ? dz : zmax;
+    if (x > xmax) x = xmax - 1;
   }
 };
 
@@ -266,14 +298,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // ---- staging offsets of this tile.  Lane l of wave w moves LDS doubles
   // [c*128 + 2l, c*128 + 2l + 1] of chunks c = w, w+WPG, ...  Points outside
   // the patch's stored box (rows / columns of a ragged tile past the ghost
-  // zone) are clamped into it: their LDS values are never read by a valid
-  // work-item.  A pair whose first column is the last one of the box (odd nx
-  // only) reads one element of row padding, which the host guarantees
-  // (sy >= nx + 2g + 1 for odd nx), so no access leaves its row.  voff is
-  // biased by (R sz + R sy + R) so that it stays non-negative.
-  const int xmax = G.nx - 1 + R - i0;       // last tile-relative column inside the box
-  const int ymax = G.ny - 1 + R - j0;       // last tile-relative row inside the box
-  const int zmax = G.nz - 1 + R - k0;       // last tile-relative plane inside the box
+  // zone) are clamped into it by the layout's stage_point(): their LDS
+  // values are never read by a valid work-item.  A pair whose first column
+  // is the last one of the box (odd nx only) reads one element of row
+  // padding, which the host guarantees (sy >= nx + 2g + 1 for odd nx), so no
+  // access leaves its row.  voff is biased by (R sz + R sy + R) so that it
+  // stays non-negative.
   const unsigned bias = (unsigned)R * (sz + sy + 1u);
   unsigned voff[L::CPW];
   // opaque copies: the decode depends only on lane and wave, and hoisted out
@@ -285,10 +315,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
 #pragma unroll
   for (int q = 0; q < L::CPW; ++q) {
     int x, y, dz;
-    L::decode((wave_t + SH::WPG * q) * L::CHUNK + 2 * lane_t, x, y, dz);
-    y = min(y, ymax);
-    dz = min(dz, zmax);
-    if (x > xmax) x = xmax - 1;
+    L::stage_point((wave_t + SH::WPG * q) * L::CHUNK + 2 * lane_t, i0, j0, k0, G.nx, G.ny, G.nz, x, y, dz);
     voff[q] = (unsigned)(dz * (int)sz + y * (int)sy + x + (int)bias) * 8u;
     // OFFS_LDS: park the offsets in LDS (each lane reads back only its own
     // slots, so no barrier is involved) and free their registers
@@ -306,7 +333,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     }
   };
 
-  const int anchor = (SH::TZ > 1 ? tz * L::PLANE_STEP : 0) + yr * L::P + xr;
   // Stencil taps of the current phase's buffer.  Each phase addresses it from
   // an opaque copy of the anchor: LDS reads are merged in pairs (8-bit
   // offsets, +-2 KB), so a buffer needs a base register per 2 KB it spans,
@@ -339,7 +365,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     }
   };
   auto make_ops = [&](const double* cur) __attribute__((always_inline)) {
-    int anc = anchor;
+    int anc = L::anchor(xr, yr, tz);
     asm volatile("" : "+v"(anc));
     return Taps{cur, anc};
   };
@@ -382,14 +408,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // The stencils below take a precision tag: double() gives the FP64 forms,
   // float() the split forms (FP64 differences rounded to FP32, FP32 weights).
   const double bet_d[3] = {val(gBETA), val(gBETA + 1), val(gBETA + 2)};
-  // FP64 upwinding as UA beta A + UQ |beta| Q per axis (fd_ops.hpp): the
-  // velocity factors with the 1/(DU h) scale folded in, once per point
-  double bA[3], bQ[3];
-#pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-    bA[ax] = (St::UA * a.sc.up) * bet_d[ax];
-    bQ[ax] = (St::UQ * a.sc.up) * __builtin_fabs(bet_d[ax]);
-  }
+  // FP64 upwinding as UA beta A + UQ |beta| Q per axis (fd_ops.hpp), with
+  // velocity factors (UA / (DU h)) beta and (UQ / (DU h)) |beta| formed in
+  // each phase (two multiplies per axis; held through the kernel they would
+  // take six registers more than beta)
+  const double cA = St::UA * a.sc.up, cQ = St::UQ * a.sc.up;
   auto D1 = [&](auto tag, const auto& src, int ax) __attribute__((always_inline)) {
     using TC = decltype(tag);
     auto along = [&](int o) __attribute__((always_inline)) { return src(ax, o); };
@@ -493,7 +516,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
         // Q times its scale, the same bits as the separate sum)
         const double Qs = ko_sum<St::UR>(along, St::USYM);
         const double As = St::upwind_anti(along);
-        adv = __builtin_fma(bA[ax], As, __builtin_fma(bQ[ax], Qs, adv));
+        adv = __builtin_fma(cA * bet_d[ax], As, __builtin_fma(cQ * __builtin_fabs(bet_d[ax]), Qs, adv));
         if constexpr (KOQ)
           qd = Qs * a.sc.ko;
         else
@@ -728,38 +751,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       Ric[s] = r;
     }
   }
-  // At_ij and At^ij (point values), loaded and formed here rather than at
-  // the start so that they are not live through the metric phases, where
-  // register pressure peaks (each metric phase loads the one component it
-  // needs; these loads hit in L2)
-  T A[6], Au[6];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) A[s] = T(val(gAT + s));
-  {
-    T Am[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int jj = 0; jj < 3; ++jj)
-        Am[i][jj] = gu[S(i, 0)] * A[S(0, jj)] + gu[S(i, 1)] * A[S(1, jj)] + gu[S(i, 2)] * A[S(2, jj)];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      const int i = SI(s), jj = SJ(s);
-      Au[s] = Am[i][0] * gu[S(0, jj)] + Am[i][1] * gu[S(1, jj)] + Am[i][2] * gu[S(2, jj)];
-    }
-  }
-  // Gt^c_jk At^jk, the only later use of the Christoffel symbols besides chi/alpha
-  T ga[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    T acc = T(0.0);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) acc += T(W(q)) * Gu[c][q] * Au[q];
-    ga[c] = acc;
-  }
   keep(Gu);
   keep(Gd);
-  keep(ga);
   keep(Ric);
 
   // ---- chi (phase 9), in precision TC: FP64, or FP32 in split waves away
@@ -874,6 +867,37 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       emit(gALPHA, ad.rhs(gauge.lapse == 0 ? -T(2.0) * alpha * K : -alpha * alpha * K), e);
     sync(10);
   }
+
+  // At_ij and At^ij (point values), loaded and formed here rather than at
+  // the start so that they are not live through the metric, chi and lapse
+  // phases, where register pressure peaks (each metric phase loads the one
+  // component it needs; these loads hit in L2)
+  T A[6], Au[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) A[s] = T(val(gAT + s));
+  {
+    T Am[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj)
+        Am[i][jj] = gu[S(i, 0)] * A[S(0, jj)] + gu[S(i, 1)] * A[S(1, jj)] + gu[S(i, 2)] * A[S(2, jj)];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int i = SI(s), jj = SJ(s);
+      Au[s] = Am[i][0] * gu[S(0, jj)] + Am[i][1] * gu[S(1, jj)] + Am[i][2] * gu[S(2, jj)];
+    }
+  }
+  // Gt^c_jk At^jk, the only later use of the Christoffel symbols besides chi/alpha
+  T ga[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T acc = T(0.0);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc += T(W(q)) * Gu[c][q] * Au[q];
+    ga[c] = acc;
+  }
+  keep(ga);
 
   // ---- evolved Gt (phases 11-13)
   T xt_ad[3];
@@ -1012,11 +1036,13 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
   using SH = Shape<TX, WPG, TZ>;
   using L = LdsLayout<R, ORDER / 2, SH>;
   static_assert(NB >= 2 && NB <= 5, "staging depth");
-  // FP64 with two waves per SIMD keeps the per-lane staging offsets in LDS
-  // (its 256 registers are otherwise exhausted); FP32 algebra needs ~156
-  constexpr bool OFFS_LDS = OCC == 2 && sizeof(T) == 8;
   constexpr int WG_PER_CU = (OCC * 4) / WPG > 1 ? (OCC * 4) / WPG : 1;
-  constexpr int LDS_BASE = NB * L::SIZEP * 8 + (OFFS_LDS ? L::CPW * SH::NT * 4 : 0);
+  constexpr int LDS_STAGE = NB * L::SIZEP * 8, LDS_OFFS = L::CPW * SH::NT * 4;
+  // FP64 with two waves per SIMD keeps the per-lane staging offsets in LDS
+  // where they fit (its 256 registers are otherwise exhausted); FP32 algebra
+  // needs ~156
+  constexpr bool OFFS_LDS = OCC == 2 && sizeof(T) == 8 && WG_PER_CU * (LDS_STAGE + LDS_OFFS) <= 160 * 1024;
+  constexpr int LDS_BASE = LDS_STAGE + (OFFS_LDS ? LDS_OFFS : 0);
   static_assert(WG_PER_CU * LDS_BASE <= 160 * 1024, "LDS");
   // order 4 at two waves per SIMD parks six accumulators in LDS where it fits
   constexpr bool PARK = ORDER == 4 && OFFS_LDS && WG_PER_CU * (LDS_BASE + 6 * SH::NT * 8) <= 160 * 1024;

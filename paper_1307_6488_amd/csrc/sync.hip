@@ -33,34 +33,49 @@ struct Mid<8> {
   }
 };
 
-// One work-item per (item, grid function): blockIdx.y is the grid function,
-// consecutive work-items take consecutive items (the maps list them in
-// memory order of their destination).
+// Copies (mid == 0): one work-item per item, all 24 grid functions -- the
+// item is read once and its 24 loads are in flight together.  Consecutive
+// work-items take consecutive items (destination memory order).
+__global__ __launch_bounds__(256) void sync_copy_kernel(const SyncItem* __restrict__ items, int n,
+                                                        double* const* __restrict__ bufs,
+                                                        const SyncGeo* __restrict__ geo) {
+  constexpr int NF = CHEMORA_NGF;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const SyncItem it = items[t];
+  const int64_t sfs = geo[it.src].sf, sfd = geo[it.dst].sf;
+  const double* src = bufs[it.src] + it.src_off;
+  double* dst = bufs[it.dst] + it.dst_off;
+  double v[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) v[f] = src[f * sfs];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) dst[f * sfd] = v[f];
+}
+
+// Interpolations: one work-item per (item, grid function), blockIdx.y the
+// grid function -- up to ORDER^3 taps each, so spread over 24 times as many
+// work-items as items rather than summed in one.
 template <int ORDER>
-__global__ __launch_bounds__(256) void sync_kernel(const SyncItem* __restrict__ items, int n,
-                                                   double* const* __restrict__ bufs, const SyncGeo* __restrict__ geo) {
+__global__ __launch_bounds__(256) void sync_interp_kernel(const SyncItem* __restrict__ items, int n,
+                                                          double* const* __restrict__ bufs,
+                                                          const SyncGeo* __restrict__ geo) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= n) return;
   const int f = blockIdx.y;
   const SyncItem it = items[t];
   const SyncGeo gs = geo[it.src], gd = geo[it.dst];
   const double* src = bufs[it.src] + f * gs.sf + it.src_off;
-  double v;
-  if (it.mid == 0) {
-    v = src[0];
-  } else {
-    const int n0 = (it.mid & 1) ? ORDER : 1, n1 = (it.mid & 2) ? ORDER : 1, n2 = (it.mid & 4) ? ORDER : 1;
-    double acc = 0.0;
-    for (int c2 = 0; c2 < n2; ++c2)
-      for (int c1 = 0; c1 < n1; ++c1)
-        for (int c0 = 0; c0 < n0; ++c0) {
-          const double w = (n0 > 1 ? Mid<ORDER>::w(c0) : 1.0) * (n1 > 1 ? Mid<ORDER>::w(c1) : 1.0) *
-                           (n2 > 1 ? Mid<ORDER>::w(c2) : 1.0);
-          acc += w * src[c2 * gs.sz + c1 * gs.sy + c0];
-        }
-    v = acc;
-  }
-  bufs[it.dst][f * gd.sf + it.dst_off] = v;
+  const int n0 = (it.mid & 1) ? ORDER : 1, n1 = (it.mid & 2) ? ORDER : 1, n2 = (it.mid & 4) ? ORDER : 1;
+  double acc = 0.0;
+  for (int c2 = 0; c2 < n2; ++c2)
+    for (int c1 = 0; c1 < n1; ++c1)
+      for (int c0 = 0; c0 < n0; ++c0) {
+        const double w = (n0 > 1 ? Mid<ORDER>::w(c0) : 1.0) * (n1 > 1 ? Mid<ORDER>::w(c1) : 1.0) *
+                         (n2 > 1 ? Mid<ORDER>::w(c2) : 1.0);
+        acc += w * src[c2 * gs.sz + c1 * gs.sy + c0];
+      }
+  bufs[it.dst][f * gd.sf + it.dst_off] = acc;
 }
 
 struct Box {
@@ -221,6 +236,9 @@ int build_sync_maps(const chemora_params* P, const chemora_patch* X, int np, Syn
     // a group: a wave then runs one loop shape, without divergence
     std::stable_sort(M.fill.begin() + M.fill_start.back(), M.fill.end(),
                      [](const SyncItem& x, const SyncItem& y) { return x.mid < y.mid; });
+    M.fill_copies.push_back((int)(std::find_if(M.fill.begin() + M.fill_start.back(), M.fill.end(),
+                                               [](const SyncItem& x) { return x.mid != 0; }) -
+                                  (M.fill.begin() + M.fill_start.back())));
     M.fill_start.push_back((int)M.fill.size());
   }
   // restriction, finest pair first
@@ -266,13 +284,17 @@ int build_sync_maps(const chemora_params* P, const chemora_patch* X, int np, Syn
   return CHEMORA_OK;
 }
 
-void launch_sync(int order, const SyncItem* items, int n, double* const* bufs, const SyncGeo* geo, hipStream_t s) {
-  if (n <= 0) return;
-  dim3 grid((n + 255) / 256, 24, 1);
+void launch_sync(int order, const SyncItem* items, int n, int ncopy, double* const* bufs, const SyncGeo* geo,
+                 hipStream_t s) {
+  if (ncopy > 0)
+    hipLaunchKernelGGL(sync_copy_kernel, dim3((ncopy + 255) / 256), dim3(256), 0, s, items, ncopy, bufs, geo);
+  const int ni = n - ncopy;
+  if (ni <= 0) return;
+  dim3 grid((ni + 255) / 256, CHEMORA_NGF, 1);
   if (order == 8)
-    hipLaunchKernelGGL(sync_kernel<8>, grid, dim3(256), 0, s, items, n, bufs, geo);
+    hipLaunchKernelGGL(sync_interp_kernel<8>, grid, dim3(256), 0, s, items + ncopy, ni, bufs, geo);
   else
-    hipLaunchKernelGGL(sync_kernel<4>, grid, dim3(256), 0, s, items, n, bufs, geo);
+    hipLaunchKernelGGL(sync_interp_kernel<4>, grid, dim3(256), 0, s, items + ncopy, ni, bufs, geo);
 }
 
 }  // namespace chemora

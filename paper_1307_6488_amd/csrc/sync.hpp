@@ -53,6 +53,7 @@ struct SyncMaps {
   int nlevels = 0;
   std::vector<SyncItem> fill;        // ghost refills, level by level
   std::vector<int> fill_start;       // nlevels + 1 offsets into fill
+  std::vector<int> fill_copies;      // per level: its first fill_copies[L] items are copies (mid == 0)
   std::vector<SyncItem> restr;       // restriction, finest level pair first
   std::vector<int> restr_start;      // pair L -> L-1 for L = max .. 1: nlevels offsets into restr (the last = end)
   std::vector<int> level;            // per patch
@@ -64,8 +65,10 @@ struct SyncMaps {
 // Host only, no HIP call.
 int build_sync_maps(const chemora_params* P, const chemora_patch* patches, int np, SyncMaps* out, std::string* err);
 
-// Launches the refill of one level's items (or one restriction pair's):
-// bufs[p] is patch p's state of the stage being refilled.
-void launch_sync(int order, const SyncItem* items, int n, double* const* bufs, const SyncGeo* geo, hipStream_t s);
+// Launches the refill of one level's items (or one restriction pair's), the
+// first ncopy of which are copies: bufs[p] is patch p's state of the stage
+// being refilled.
+void launch_sync(int order, const SyncItem* items, int n, int ncopy, double* const* bufs, const SyncGeo* geo,
+                 hipStream_t s);
 
 }  // namespace chemora

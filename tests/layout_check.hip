@@ -14,40 +14,55 @@ int check(int nx, int ny, int nz, int g) {
   using L = LdsLayout<R, RM, SH>;
   int bad = 0;
   // taps read by a work-item at (xr, yr, tz): axis taps |d| <= R along each
-  // axis, mixed taps (a, b) with |a|, |b| <= RM in each pair of axes
+  // axis, mixed taps (a, b) with |a|, |b| <= RM in each pair of axes; each
+  // at the work-item's anchor plus the compile-time offset
+  auto taps = [&](auto&& tap) {
+    for (int d = -R; d <= R; ++d) { tap(d, 0, 0); tap(0, d, 0); tap(0, 0, d); }
+    for (int a = -RM; a <= RM; ++a)
+      for (int b = -RM; b <= RM; ++b) { tap(a, b, 0); tap(a, 0, b); tap(0, a, b); }
+  };
   for (int tz = 0; tz < SH::TZ; ++tz)
     for (int yr = 0; yr < SH::TY; ++yr)
-      for (int xr = 0; xr < SH::TX; ++xr) {
-        const int anchor = (SH::TZ > 1 ? tz * L::PLANE_STEP : 0) + yr * L::P + xr;
-        auto tap = [&](int dx, int dy, int dz) {
-          const int idx = anchor + L::off(dx, dy, dz);
+      for (int xr = 0; xr < SH::TX; ++xr)
+        taps([&](int dx, int dy, int dz) {
+          const int idx = L::anchor(xr, yr, tz) + L::off(dx, dy, dz);
           if (idx < 0 || idx >= L::SIZE) { ++bad; return; }
           int x, y, z;
           L::decode(idx, x, y, z);
           if (x != xr + dx || y != yr + dy || z != tz + dz) ++bad;
-        };
-        for (int d = -R; d <= R; ++d) { tap(d, 0, 0); tap(0, d, 0); tap(0, 0, d); }
-        for (int a = -RM; a <= RM; ++a)
-          for (int b = -RM; b <= RM; ++b) { tap(a, b, 0); tap(a, 0, b); tap(0, a, b); }
-      }
-  // staging offsets: clamped points inside the stored box, pairs inside a row
+        });
+  // staging offsets: clamped points inside the stored box, pairs inside a
+  // row; on small patches also every tap of every valid work-item of every
+  // tile reads an element its staging lane loaded unclamped
   const long sy = nx + 2 * g + (nx & 1), sz = sy * (ny + 2 * g);
+  (void)sz;
   const int tx = (nx + SH::TX - 1) / SH::TX, ty = (ny + SH::TY - 1) / SH::TY, tzn = (nz + SH::TZ - 1) / SH::TZ;
+  const bool small = (long)nx * ny * nz <= 40000;
   for (int kb = 0; kb < tzn; ++kb)
     for (int tyi = 0; tyi < ty; ++tyi)
       for (int txi = 0; txi < tx; ++txi) {
         const int i0 = txi * SH::TX, j0 = tyi * SH::TY, k0 = kb * SH::TZ;
-        const int xmax = nx - 1 + R - i0, ymax = ny - 1 + R - j0, zmax = nz - 1 + R - k0;
         for (int c = 0; c < L::NCHUNK; ++c)
           for (int lane = 0; lane < 64; ++lane) {
             int x, y, dz;
-            L::decode(c * L::CHUNK + 2 * lane, x, y, dz);
-            y = y < ymax ? y : ymax;
-            dz = dz < zmax ? dz : zmax;
-            if (x > xmax) x = xmax - 1;
+            L::stage_point(c * L::CHUNK + 2 * lane, i0, j0, k0, nx, ny, nz, x, y, dz);
             const long gi = i0 + x + g, gj = j0 + y + g, gk = k0 + dz + g;
             if (gi < 0 || gi + 1 >= sy || gj < 0 || gj >= ny + 2 * g || gk < 0 || gk >= nz + 2 * g) ++bad;
           }
+        if (!small) continue;
+        for (int tz = 0; tz < SH::TZ; ++tz)
+          for (int yr = 0; yr < SH::TY; ++yr)
+            for (int xr = 0; xr < SH::TX; ++xr) {
+              if (i0 + xr >= nx || j0 + yr >= ny || k0 + tz >= nz) continue;
+              taps([&](int dx, int dy, int dz) {
+                const int idx = L::anchor(xr, yr, tz) + L::off(dx, dy, dz);
+                const int pair = idx & ~1;   // the lane's pair holds idx
+                int x, y, z, ux, uy, uz;
+                L::stage_point(pair, i0, j0, k0, nx, ny, nz, x, y, z);
+                L::decode(pair, ux, uy, uz);
+                if (x != ux || y != uy || z != uz) ++bad;
+              });
+            }
       }
   return bad;
 }
@@ -57,13 +72,18 @@ int main() {
   const int shapes[][4] = {{70, 37, 19, 3}, {33, 9, 7, 3}, {128, 128, 128, 3}, {1, 1, 1, 3}, {65, 1, 2, 3},
                            {2, 33, 1, 3}, {21, 14, 11, 3}, {22, 13, 9, 4}, {26, 11, 8, 3}};
   for (auto& s : shapes) {
+    const int g8 = 5 > s[3] ? 5 : s[3];
     bad += check<3, 2, Shape<32, 8, 2>>(s[0], s[1], s[2], s[3]);
     bad += check<3, 2, Shape<32, 8, 4>>(s[0], s[1], s[2], s[3]);
     bad += check<2, 2, Shape<32, 8, 2>>(s[0], s[1], s[2], s[3]);
     bad += check<2, 2, Shape<32, 8, 4>>(s[0], s[1], s[2], s[3]);
     bad += check<3, 2, Shape<32, 8, 1>>(s[0], s[1], s[2], s[3]);
     bad += check<3, 2, Shape<64, 4, 1>>(s[0], s[1], s[2], s[3]);
-    bad += check<5, 4, Shape<32, 4, 1>>(s[0], s[1], s[2], 5 > s[3] ? 5 : s[3]);
+    bad += check<2, 2, Shape<32, 4, 1>>(s[0], s[1], s[2], s[3]);
+    bad += check<3, 2, Shape<64, 8, 1>>(s[0], s[1], s[2], s[3]);
+    bad += check<5, 4, Shape<32, 4, 1>>(s[0], s[1], s[2], g8);
+    bad += check<5, 4, Shape<64, 4, 1>>(s[0], s[1], s[2], g8);
+    bad += check<4, 4, Shape<32, 4, 1>>(s[0], s[1], s[2], g8);
   }
   printf("layout check: %d violations\n", bad);
   return bad != 0;
