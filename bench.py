@@ -327,20 +327,26 @@ def batched_form(C, I, torch, no_tune, steps=10, warmup=2):
     params = I.workload(2).params
     states = [I.brill_lindquist(g) for g in grids]
     npts = sum(g.npoints for g in grids)
-    B = C.Batch(params, grids, states, 0.25, tune_cache_path=None if no_tune else _tune_cache())
-    B.step(warmup)
-    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    B.step(steps)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    variants = sorted(set(B.variants()))
-    B.close()
-    del B
-    torch.cuda.empty_cache()
+
+    def plan_ms(tune_cache_path):
+        B = C.Batch(params, grids, states, 0.25, tune_cache_path=tune_cache_path)
+        B.step(warmup)
+        torch.cuda.synchronize()
+        e0.record()
+        B.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        variants = sorted(set(B.variants()))
+        B.close()
+        del B
+        torch.cuda.empty_cache()
+        return e0.elapsed_time(e1) / steps, variants
+    # untuned first (no size class of these patches has a table entry yet:
+    # every patch runs the default 32x8 tile), then the tuned plan
+    ms_untuned = None if no_tune else plan_ms(None)[0]
+    ms, variants = plan_ms(None if no_tune else _tune_cache())
     # the same patches and data stepped one chemora_rk4_step call each, with
     # the tile variants the plan's tuner recorded for their classes
     Ps = [C.Patch(params, g, s) for g, s in zip(grids, states)]
@@ -377,6 +383,8 @@ def batched_form(C, I, torch, no_tune, steps=10, warmup=2):
             "per_patch": {"ms_per_step": ms_pp, "value": npts / (ms_pp * 1e-3),
                           "calls": "one chemora_rk4_step per patch and step, same tile variants"},
             "speedup_vs_per_patch": ms_pp / ms,
+            "untuned": None if ms_untuned is None else {
+                "ms_per_step": ms_untuned, "tile_variants": ["32x8"], "tuned_speedup": ms_untuned / ms},
             "rk3": {"ms_per_step": ms3, "value": npts / (ms3 * 1e-3)}}
 
 
