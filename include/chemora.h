@@ -345,7 +345,12 @@ typedef struct chemora_plan chemora_plan;   /* opaque, library-owned */
  * cache file is read if it exists, every class of the plan without an entry
  * is timed on its largest patch (chemora_tune; this synchronises `stream`
  * and overwrites that patch's scratch, before the ghosts are prepared), and the
- * file is rewritten with all entries.  Device tables and the graph are
+ * file is rewritten with all entries.  An FP64 plan whose classes then use
+ * more than one variant also times an RK4 stage-2 pass over all its patches
+ * with that mix (one launch per variant group, one after another) and with
+ * each built variant for every patch, and keeps the fastest assignment: the
+ * FP64 variants are bit-identical, so only the time changes
+ * (chemora_plan_patch_variant reports each patch's).  Device tables and the graph are
  * allocated here (ENOMEM or EDEVICE on failure, nothing leaked). */
 int chemora_plan_create(const chemora_params *params, const chemora_patch *patches, double *const *scratch,
                         int32_t npatch, double courant, const char *tune_cache_path, void *stream,

@@ -1417,6 +1417,85 @@ void plan_free(chemora_plan* pl) {
 
 namespace {
 
+// Time of one RK4 stage-2 pass over all patches of a plan with tile variants
+// var[p]: the patches grouped by variant, one batched launch per group, the
+// groups one after another as in the plan's graph.  One warm-up pass, then
+// the fastest of three samples of two passes (as the per-class tuner).
+// Overwrites the S_B and accumulator parts of scratch.
+int plan_pass_ms(const chemora_params* P, const chemora_patch* X, double* const* scratch, int npatch,
+                 const std::vector<int>& var, hipStream_t s, float* best_ms) {
+  std::vector<int> order(npatch);
+  for (int p = 0; p < npatch; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return var[x] < var[y]; });
+  std::vector<chemora::StageArgs> args(npatch);
+  std::vector<int> starts;
+  std::vector<PlanGroup> groups;
+  for (int r = 0; r < npatch;) {
+    PlanGroup g{var[order[r]], r, 0, 0, (int)starts.size()};
+    starts.push_back(0);
+    int64_t tiles = 0;
+    for (; r < npatch && var[order[r]] == g.variant; ++r) {
+      const chemora_patch* Y = &X[order[r]];
+      const size_t state = (size_t)CHEMORA_NGF * Y->sf;
+      chemora::StageArgs a = base_args(P, Y);
+      set_tiles(a, g.variant);
+      tiles += (int64_t)a.tiles_x * a.tiles_y * tile_planes(a.geo.nz, g.variant);
+      if (tiles > INT32_MAX) return fail(CHEMORA_EINVAL, "too many tiles in the plan");
+      starts.push_back((int)tiles);
+      double* sc = scratch[order[r]];
+      stage_args(a, 2, Y->h * 0.25, Y->u, sc, sc + state, sc + 2 * state);
+      args[r] = a;
+      ++g.count;
+    }
+    g.ntiles = (int)tiles;
+    groups.push_back(g);
+  }
+  chemora::StageArgs* d_args = nullptr;
+  int* d_starts = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc((void**)&d_args, args.size() * sizeof(chemora::StageArgs));
+  if (e == hipSuccess) e = hipMalloc((void**)&d_starts, starts.size() * sizeof(int));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_args, args.data(), args.size() * sizeof(chemora::StageArgs), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_starts, starts.data(), starts.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  auto pass = [&]() {
+    for (const PlanGroup& g : groups) {
+      chemora::BatchTable bt;
+      bt.args = d_args + g.first;
+      bt.tile_start = d_starts + g.toff;
+      bt.npatch = g.count;
+      bt.ntiles = g.ntiles;
+      dispatch_batch(P, g.variant, bt, s);
+    }
+  };
+  constexpr int ROUNDS = 3, PER_SAMPLE = 2;
+  *best_ms = -1.0f;
+  if (e == hipSuccess) {
+    pass();
+    e = hipGetLastError();
+  }
+  for (int r = 0; r < ROUNDS && e == hipSuccess; ++r) {
+    e = hipEventRecord(e0, s);
+    for (int k = 0; k < PER_SAMPLE && e == hipSuccess; ++k) pass();
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && (*best_ms < 0.0f || ms / PER_SAMPLE < *best_ms)) *best_ms = ms / PER_SAMPLE;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (d_args) (void)hipFree(d_args);
+  if (d_starts) (void)hipFree(d_starts);
+  if (e != hipSuccess) return fail(CHEMORA_EDEVICE, "plan tuning: %s", hipGetErrorString(e));
+  return CHEMORA_OK;
+}
+
 // A plan capturing one step of RK4 (4 stages) or of the third-order SSP
 // scheme (3 stages); scratch holds 3 states per patch either way (the
 // tuner times RK4 stage-2 launches in it).
@@ -1501,6 +1580,27 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
     for (int p : by_size)
       if ((rc = tune_class(params, &patches[p], scratch[p], s, &var[p]))) return rc;
     if ((rc = save_cache(tune_cache_path))) return rc;
+    // The classes were timed one patch at a time, but a plan launches each
+    // variant group after the other, so a mix of variants also pays for
+    // every group's tail.  FP64 plans (whose variants are bit-identical)
+    // therefore also time one pass with every built variant for all
+    // patches and keep whichever assignment is fastest.
+    bool mixed = false;
+    for (int p = 1; p < npatch; ++p) mixed |= var[p] != var[0];
+    if (mixed && params->precision == CHEMORA_PREC_FP64) {
+      float best = 0.0f;
+      if ((rc = plan_pass_ms(params, patches, scratch, npatch, var, s, &best))) return rc;
+      for (int v = 0; v < chemora::NVARIANT; ++v) {
+        if (!chemora::variant_supported(params->fd_order, v)) continue;
+        const std::vector<int> uni(npatch, v);
+        float ms = 0.0f;
+        if ((rc = plan_pass_ms(params, patches, scratch, npatch, uni, s, &ms))) return rc;
+        if (ms < best) {
+          best = ms;
+          var = uni;
+        }
+      }
+    }
   } else {
     for (int p = 0; p < npatch; ++p) var[p] = choose_variant(params, &patches[p]);
   }
