@@ -329,10 +329,30 @@ int chemora_tile_variant_depth(int32_t variant);
  * strides; all share params) and their RK4 scratch buffers.  One RK4 step of
  * every patch is captured once into a HIP graph: per RK stage one launch
  * per tile variant covers the tiles of all the plan's patches of that
- * variant (one work-group per tile).  Patch p advances with its own time
+ * variant.  By default that launch is persistent: as many work-groups as
+ * the GPU holds at once, each pulling tiles from a device-side queue of its
+ * own XCD (the XCD's contiguous eighth of the tile list, so that
+ * neighbouring tiles share that XCD's L2) and then from the other XCDs'
+ * queues until every tile is done; the queue counters live in the plan and
+ * each launch leaves them zeroed for the next, so the graph holds no
+ * memset.  chemora_set_plan_dispatch selects one work-group per tile
+ * instead.  Both compute the same bits.  Patch p advances with its own time
  * step dt_p = courant * h_p.  Patches are independent (each
- * keeps its own ghosts); no data moves between patches. */
+ * keeps its own ghosts); no data moves between patches.  Replaying one plan
+ * on two streams at once races on its queues. */
 typedef struct chemora_plan chemora_plan;   /* opaque, library-owned */
+
+/* How the stage launches of plans are dispatched. */
+enum { CHEMORA_DISPATCH_PERSISTENT = 0, CHEMORA_DISPATCH_PER_TILE = 1 };
+
+/* Sets the dispatch of plans created after this call, process-wide
+ * (thread-safe): CHEMORA_DISPATCH_PERSISTENT (the default) or
+ * CHEMORA_DISPATCH_PER_TILE (one work-group per tile, in the same XCD
+ * order).  Existing plans keep theirs.  EINVAL for another value. */
+int chemora_set_plan_dispatch(int32_t mode);
+
+/* Dispatch of a plan (>= 0), or EINVAL for a NULL plan. */
+int chemora_plan_dispatch(const chemora_plan *plan);
 
 /* Creates a plan.  patches[p].u and scratch[p] (chemora_rk4_scratch_elems
  * doubles) must stay allocated, and scratch must not be modified by the
@@ -419,11 +439,12 @@ int chemora_check_finite(const chemora_params *params, const chemora_patch *patc
 /* Message of the last failed call on this thread ("" if none). */
 const char *chemora_last_error(void);
 
-/* ABI version of this header (major*100 + minor): 102 (1.1 added
+/* ABI version of this header (major*100 + minor): 103 (1.1 added
  * chemora_rk3_step, chemora_rk3_scratch_elems, chemora_plan_create_rk3,
  * chemora_enforce_constraints and chemora_momentum_constraint; 1.2 added
  * chemora_rk4_step_noalloc, chemora_psi4, chemora_plan_create_synced and
- * CHEMORA_BC_RADIATIVE; nothing earlier changed). */
+ * CHEMORA_BC_RADIATIVE; 1.3 added chemora_set_plan_dispatch and
+ * chemora_plan_dispatch; nothing earlier changed). */
 int chemora_abi_version(void);
 
 #ifdef __cplusplus

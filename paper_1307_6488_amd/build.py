@@ -1,7 +1,7 @@
 """Build libchemora.so (gfx950) in-tree with hipcc.
 
 Usage: ``python -m paper_1307_6488_amd.build``.  Cross-compiles without a
-GPU: each translation unit is compiled in parallel to an object under
+GPU: each translation unit (or part of one) is compiled in parallel to an object under
 ``_build/`` and the objects are linked into ``paper_1307_6488_amd/libchemora.so``.
 Packed FP32 instructions are disabled for the whole library.
 """
@@ -18,11 +18,25 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libchemora.so")
-SOURCES = ["chemora.hip", "stage_o4.hip", "stage_o8.hip", "sync.hip"]
+# (source, defines, object): the stage kernels are built in parts -- per
+# precision and per batched form -- that compile in parallel
+UNITS = [
+    ("chemora.hip", [], "chemora"),
+    ("sync.hip", [], "sync"),
+    *[("stage_o4.hip", [f"-DCHEMORA_PART_SPLIT={sp}", f"-DCHEMORA_PART_PERSIST={pe}"], f"stage_o4_s{sp}p{pe}")
+      for sp in (0, 1) for pe in (0, 1)],
+    *[("stage_o8.hip", [f"-DCHEMORA_PART_PERSIST={pe}"], f"stage_o8_p{pe}") for pe in (0, 1)],
+]
+SOURCES = sorted({u[0] for u in UNITS})
 ARCH = os.environ.get("CHEMORA_ARCH", "gfx950")
 
+# -ffp-contract=on: a multiply and an add are fused only where one source
+# expression holds both (the C rule), never across statements by the code
+# generator, whose choices depend on the surrounding code.  Every instance of
+# the stage kernel (tile variants, single-patch, batched and persistent
+# forms) then computes the same bits for a point.
 HIPCC_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
@@ -35,9 +49,11 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def _compile(src: str, extra, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit, extra, verbose: bool) -> str:
+    src, defines, name = unit
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [hipcc(), *HIPCC_FLAGS, *defines, *extra, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src),
+           "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -51,8 +67,8 @@ def _compile(src: str, extra, verbose: bool) -> str:
 
 def build(verbose: bool = False, extra=()) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, list(extra), verbose), SOURCES))
+    with cf.ThreadPoolExecutor(max_workers=len(UNITS)) as ex:
+        objs = list(ex.map(lambda u: _compile(u, list(extra), verbose), UNITS))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

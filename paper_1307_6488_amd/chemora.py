@@ -28,6 +28,7 @@ EXPORTS = (
     "chemora_tile_variant_shape", "chemora_hamiltonian", "chemora_rk3_scratch_elems", "chemora_rk3_step",
     "chemora_enforce_constraints", "chemora_momentum_constraint", "chemora_plan_create_rk3",
     "chemora_rk4_step_noalloc", "chemora_psi4", "chemora_plan_create_synced", "chemora_tile_variant_depth",
+    "chemora_set_plan_dispatch", "chemora_plan_dispatch",
 )
 # CHEMORA_NOALLOC_SCRATCH_ELEMS of include/chemora.h
 NOALLOC_SCRATCH_ELEMS = 8 << 20
@@ -105,6 +106,10 @@ def lib() -> ctypes.CDLL:
         L.chemora_plan_destroy.restype = ctypes.c_int
         L.chemora_hamiltonian.argtypes = [P, X, ctypes.c_void_p, ctypes.c_void_p]
         L.chemora_hamiltonian.restype = ctypes.c_int
+        L.chemora_set_plan_dispatch.argtypes = [ctypes.c_int32]
+        L.chemora_set_plan_dispatch.restype = ctypes.c_int
+        L.chemora_plan_dispatch.argtypes = [ctypes.c_void_p]
+        L.chemora_plan_dispatch.restype = ctypes.c_int
         L.chemora_plan_patch_variant.argtypes = [ctypes.c_void_p, ctypes.c_int32]
         L.chemora_plan_patch_variant.restype = ctypes.c_int
         L.chemora_tune.argtypes = [P, X, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p,
@@ -274,6 +279,17 @@ def chemora_hamiltonian(params: chemora_params, patch: chemora_patch, h_ptr: int
                                             _stream(stream)))
 
 
+DISPATCH_PERSISTENT, DISPATCH_PER_TILE = 0, 1
+
+
+def chemora_set_plan_dispatch(mode: int) -> int:
+    return _check(lib().chemora_set_plan_dispatch(mode))
+
+
+def chemora_plan_dispatch(plan: int) -> int:
+    return _check_id(lib().chemora_plan_dispatch(ctypes.c_void_p(plan)))
+
+
 def chemora_plan_patch_variant(plan: int, p: int) -> int:
     return _check_id(lib().chemora_plan_patch_variant(ctypes.c_void_p(plan), p))
 
@@ -408,9 +424,11 @@ class Batch:
     """Several device-resident patches advanced together through a plan."""
 
     def __init__(self, params, grids, states, courant: float = 0.0, device="cuda", tune_cache_path=None,
-                 integrator: str = "rk4", synced_dt: float = 0.0):
+                 integrator: str = "rk4", synced_dt: float = 0.0, dispatch: int = DISPATCH_PERSISTENT):
         """Independent patches with dt = courant * h each, or (synced_dt > 0)
-        one synchronised grid hierarchy stepped with synced_dt."""
+        one synchronised grid hierarchy stepped with synced_dt.  dispatch:
+        DISPATCH_PERSISTENT or DISPATCH_PER_TILE (the process-wide setting is
+        restored to persistent afterwards)."""
         import torch
         if integrator not in ("rk4", "rk3"):
             raise ValueError(f"integrator {integrator!r} is neither 'rk4' nor 'rk3'")
@@ -418,13 +436,21 @@ class Batch:
         self.patches = [Patch(params, g, s, device=device) for g, s in zip(grids, states)]
         self.params = make_params(params)
         scr = [p.scratch().data_ptr() for p in self.patches]
-        if synced_dt > 0.0:
-            self.plan = chemora_plan_create_synced(self.params, [p.patch for p in self.patches], scr, synced_dt,
-                                                   3 if integrator == "rk3" else 4, tune_cache_path,
-                                                   torch.cuda.current_stream())
-        else:
-            self.plan = chemora_plan_create(self.params, [p.patch for p in self.patches], scr, courant,
-                                            tune_cache_path, torch.cuda.current_stream(), rk3=integrator == "rk3")
+        chemora_set_plan_dispatch(dispatch)
+        try:
+            if synced_dt > 0.0:
+                self.plan = chemora_plan_create_synced(self.params, [p.patch for p in self.patches], scr, synced_dt,
+                                                       3 if integrator == "rk3" else 4, tune_cache_path,
+                                                       torch.cuda.current_stream())
+            else:
+                self.plan = chemora_plan_create(self.params, [p.patch for p in self.patches], scr, courant,
+                                                tune_cache_path, torch.cuda.current_stream(),
+                                                rk3=integrator == "rk3")
+        finally:
+            chemora_set_plan_dispatch(DISPATCH_PERSISTENT)
+
+    def dispatch(self) -> int:
+        return chemora_plan_dispatch(self.plan)
 
     def variants(self):
         return [chemora_plan_patch_variant(self.plan, p) for p in range(len(self.patches))]

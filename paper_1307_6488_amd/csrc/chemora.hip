@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 #include <fstream>
 #include <map>
 #include <mutex>
@@ -682,22 +683,54 @@ void dispatch_stage(const chemora_params* P, chemora::StageArgs& a, int v, hipSt
   set_tiles(a, v);
   const int tiles = a.tiles_x * a.tiles_y * tile_planes(a.geo.nz, v);
   if (P->fd_order == 4)
-    chemora::launch_stage_o4(v, P->precision == CHEMORA_PREC_SPLIT, P->upwind != 0, P->ko_radius, a, none, tiles,
-                             s);
+    chemora::launch_stage_o4(v, P->precision == CHEMORA_PREC_SPLIT, false, P->upwind != 0, P->ko_radius, a, none,
+                             tiles, s);
   else
-    chemora::launch_stage_o8(v, P->upwind != 0, P->ko_radius, a, none, tiles, s);
+    chemora::launch_stage_o8(v, false, P->upwind != 0, P->ko_radius, a, none, tiles, s);
 }
 
-// batched form: one work-group per tile of the plan's tile list
-void dispatch_batch(const chemora_params* P, int v, const chemora::BatchTable& bt, hipStream_t s) {
+// batched form over the plan's tile list: grid work-groups, one per tile
+// (bt.queue null, grid = bt.ntiles) or persistent (grid from
+// persistent_grid())
+void dispatch_batch(const chemora_params* P, int v, const chemora::BatchTable& bt, int grid, hipStream_t s) {
   chemora::StageArgs none;
   std::memset(&none, 0, sizeof none);
   if (P->fd_order == 4)
-    chemora::launch_stage_o4(v, P->precision == CHEMORA_PREC_SPLIT, P->upwind != 0, P->ko_radius, none, bt,
-                             bt.ntiles, s);
+    chemora::launch_stage_o4(v, P->precision == CHEMORA_PREC_SPLIT, bt.queue != nullptr, P->upwind != 0,
+                             P->ko_radius, none, bt, grid, s);
   else
-    chemora::launch_stage_o8(v, P->upwind != 0, P->ko_radius, none, bt, bt.ntiles, s);
+    chemora::launch_stage_o8(v, bt.queue != nullptr, P->upwind != 0, P->ko_radius, none, bt, grid, s);
 }
+
+// Work-groups of a persistent stage launch over ntiles tiles of variant v:
+// as many as are resident at once on the current device (its CUs times the
+// kernel's work-groups per CU, from the occupancy query), a multiple of the
+// XCD count when there are that many, never more than the tiles.  0 if the
+// device cannot be queried.
+int persistent_grid(const chemora_params* P, int v, int ntiles) {
+  chemora::StageArgs none;
+  std::memset(&none, 0, sizeof none);
+  chemora::BatchTable bt;
+  std::memset(&bt, 0, sizeof bt);
+  int wgs = 0, dev = 0, cus = 0;
+  if (P->fd_order == 4)
+    chemora::launch_stage_o4(v, P->precision == CHEMORA_PREC_SPLIT, true, P->upwind != 0, P->ko_radius, none, bt,
+                             0, nullptr, &wgs);
+  else
+    chemora::launch_stage_o8(v, true, P->upwind != 0, P->ko_radius, none, bt, 0, nullptr, &wgs);
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  if (wgs < 1 || cus < 1) return 0;
+  int64_t g = std::min<int64_t>((int64_t)wgs * cus, ntiles);
+  if (g >= chemora::NXCD) g -= g % chemora::NXCD;
+  return (int)g;
+}
+
+// how plans created from now on launch their stage kernels
+std::atomic<int> g_plan_dispatch{CHEMORA_DISPATCH_PERSISTENT};
 
 // ---------------------------------------------------------------------------
 // tile variants: the per-class choice and its cache
@@ -872,7 +905,7 @@ void launch_radiative(const chemora_params* P, const chemora_patch* X, const che
 
 extern "C" {
 
-int chemora_abi_version(void) { return 102; }
+int chemora_abi_version(void) { return 103; }
 
 const char* chemora_last_error(void) { return g_error.c_str(); }
 
@@ -1372,6 +1405,7 @@ struct PlanGroup {
   int count;       // patches
   int ntiles;
   int toff;        // offset of its tile-start prefix sums (count + 1 entries)
+  int grid;        // work-groups per launch: ntiles, or the persistent grid
 };
 
 struct chemora_plan {
@@ -1382,6 +1416,8 @@ struct chemora_plan {
   std::vector<int> variant_of;                    // per patch (caller's order)
   chemora::StageArgs* d_args = nullptr;           // 4 (RK4) or 3 (RK3) stage tables of npatch entries, group order
   int* d_tile_start = nullptr;
+  int dispatch = CHEMORA_DISPATCH_PERSISTENT;
+  int* d_queue = nullptr;                         // persistent: QUEUE_INTS counters per stage and group
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1406,6 +1442,7 @@ void plan_free(chemora_plan* pl) {
   }
   if (pl->d_args) (void)hipFree(pl->d_args);
   if (pl->d_tile_start) (void)hipFree(pl->d_tile_start);
+  if (pl->d_queue) (void)hipFree(pl->d_queue);
   if (pl->d_fill) (void)hipFree(pl->d_fill);
   if (pl->d_restr) (void)hipFree(pl->d_restr);
   if (pl->d_geo) (void)hipFree(pl->d_geo);
@@ -1423,7 +1460,7 @@ namespace {
 // the fastest of three samples of two passes (as the per-class tuner).
 // Overwrites the S_B and accumulator parts of scratch.
 int plan_pass_ms(const chemora_params* P, const chemora_patch* X, double* const* scratch, int npatch,
-                 const std::vector<int>& var, hipStream_t s, float* best_ms) {
+                 const std::vector<int>& var, int dispatch, hipStream_t s, float* best_ms) {
   std::vector<int> order(npatch);
   for (int p = 0; p < npatch; ++p) order[p] = p;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return var[x] < var[y]; });
@@ -1431,7 +1468,7 @@ int plan_pass_ms(const chemora_params* P, const chemora_patch* X, double* const*
   std::vector<int> starts;
   std::vector<PlanGroup> groups;
   for (int r = 0; r < npatch;) {
-    PlanGroup g{var[order[r]], r, 0, 0, (int)starts.size()};
+    PlanGroup g{var[order[r]], r, 0, 0, (int)starts.size(), 0};
     starts.push_back(0);
     int64_t tiles = 0;
     for (; r < npatch && var[order[r]] == g.variant; ++r) {
@@ -1448,13 +1485,19 @@ int plan_pass_ms(const chemora_params* P, const chemora_patch* X, double* const*
       ++g.count;
     }
     g.ntiles = (int)tiles;
+    g.grid = dispatch == CHEMORA_DISPATCH_PERSISTENT ? persistent_grid(P, g.variant, g.ntiles) : g.ntiles;
+    if (g.grid < 1) return fail(CHEMORA_EDEVICE, "plan tuning: occupancy or device query failed");
     groups.push_back(g);
   }
   chemora::StageArgs* d_args = nullptr;
   int* d_starts = nullptr;
+  int* d_queue = nullptr;   // one set of counters: the launches run one after another
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipMalloc((void**)&d_args, args.size() * sizeof(chemora::StageArgs));
   if (e == hipSuccess) e = hipMalloc((void**)&d_starts, starts.size() * sizeof(int));
+  if (e == hipSuccess && dispatch == CHEMORA_DISPATCH_PERSISTENT)
+    e = hipMalloc((void**)&d_queue, chemora::QUEUE_INTS * sizeof(int));
+  if (e == hipSuccess && d_queue) e = hipMemsetAsync(d_queue, 0, chemora::QUEUE_INTS * sizeof(int), s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_args, args.data(), args.size() * sizeof(chemora::StageArgs), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
@@ -1466,9 +1509,10 @@ int plan_pass_ms(const chemora_params* P, const chemora_patch* X, double* const*
       chemora::BatchTable bt;
       bt.args = d_args + g.first;
       bt.tile_start = d_starts + g.toff;
+      bt.queue = d_queue;
       bt.npatch = g.count;
       bt.ntiles = g.ntiles;
-      dispatch_batch(P, g.variant, bt, s);
+      dispatch_batch(P, g.variant, bt, g.grid, s);
     }
   };
   constexpr int ROUNDS = 3, PER_SAMPLE = 2;
@@ -1492,6 +1536,7 @@ int plan_pass_ms(const chemora_params* P, const chemora_patch* X, double* const*
   if (e1) (void)hipEventDestroy(e1);
   if (d_args) (void)hipFree(d_args);
   if (d_starts) (void)hipFree(d_starts);
+  if (d_queue) (void)hipFree(d_queue);
   if (e != hipSuccess) return fail(CHEMORA_EDEVICE, "plan tuning: %s", hipGetErrorString(e));
   return CHEMORA_OK;
 }
@@ -1521,6 +1566,7 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
                 double dt_all = 0.0) {
   const int nst = rk3 ? 3 : 4;
   const bool synced = dt_all > 0.0;
+  const int dispatch = g_plan_dispatch.load();
   if (!out) return fail(CHEMORA_EINVAL, "out is NULL");
   *out = nullptr;
   if (!patches || !scratch) return fail(CHEMORA_EINVAL, "patches or scratch is NULL");
@@ -1589,12 +1635,12 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
     for (int p = 1; p < npatch; ++p) mixed |= var[p] != var[0];
     if (mixed && params->precision == CHEMORA_PREC_FP64) {
       float best = 0.0f;
-      if ((rc = plan_pass_ms(params, patches, scratch, npatch, var, s, &best))) return rc;
+      if ((rc = plan_pass_ms(params, patches, scratch, npatch, var, dispatch, s, &best))) return rc;
       for (int v = 0; v < chemora::NVARIANT; ++v) {
         if (!chemora::variant_supported(params->fd_order, v)) continue;
         const std::vector<int> uni(npatch, v);
         float ms = 0.0f;
-        if ((rc = plan_pass_ms(params, patches, scratch, npatch, uni, s, &ms))) return rc;
+        if ((rc = plan_pass_ms(params, patches, scratch, npatch, uni, dispatch, s, &ms))) return rc;
         if (ms < best) {
           best = ms;
           var = uni;
@@ -1611,6 +1657,7 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
   pl->npatch = npatch;
   pl->points = points;
   pl->variant_of = var;
+  pl->dispatch = dispatch;
 
   // group order: patches sorted by variant (stable); per-stage argument
   // tables in that order and per-group tile prefix sums (host side first)
@@ -1620,7 +1667,7 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
   std::vector<chemora::StageArgs> args(nst * (size_t)npatch);
   std::vector<int> starts;
   for (int r = 0; r < npatch;) {
-    PlanGroup g{var[order[r]], r, 0, 0, (int)starts.size()};
+    PlanGroup g{var[order[r]], r, 0, 0, (int)starts.size(), 0};
     starts.push_back(0);
     int64_t tiles = 0;
     for (; r < npatch && var[order[r]] == g.variant; ++r) {
@@ -1646,10 +1693,19 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
       ++g.count;
     }
     g.ntiles = (int)tiles;
+    g.grid = dispatch == CHEMORA_DISPATCH_PERSISTENT ? persistent_grid(params, g.variant, g.ntiles) : g.ntiles;
+    if (g.grid < 1) {
+      plan_free(pl);
+      return fail(CHEMORA_EDEVICE, "plan setup: occupancy or device query failed");
+    }
     pl->groups.push_back(g);
   }
+  // persistent launches: one set of queue counters per stage and group,
+  // zeroed here; every launch leaves its set zeroed again
+  const size_t nqueue = dispatch == CHEMORA_DISPATCH_PERSISTENT ? nst * pl->groups.size() * chemora::QUEUE_INTS : 0;
   hipError_t e = hipMalloc((void**)&pl->d_args, args.size() * sizeof(chemora::StageArgs));
   if (e == hipSuccess) e = hipMalloc((void**)&pl->d_tile_start, starts.size() * sizeof(int));
+  if (e == hipSuccess && nqueue) e = hipMalloc((void**)&pl->d_queue, nqueue * sizeof(int));
   if (e != hipSuccess) {
     plan_free(pl);
     (void)hipGetLastError();
@@ -1684,6 +1740,7 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
   e = hipMemcpyAsync(pl->d_args, args.data(), args.size() * sizeof(chemora::StageArgs), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(pl->d_tile_start, starts.data(), starts.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && nqueue) e = hipMemsetAsync(pl->d_queue, 0, nqueue * sizeof(int), s);   // before capture
   if (synced) {
     if (e == hipSuccess && !maps.fill.empty())
       e = hipMemcpyAsync(pl->d_fill, maps.fill.data(), maps.fill.size() * sizeof(chemora::SyncItem),
@@ -1724,13 +1781,15 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
   }
   const bool periodic = params->bc == CHEMORA_BC_PERIODIC;
   for (int st = 0; st < nst; ++st) {
-    for (const PlanGroup& g : pl->groups) {
+    for (size_t gi = 0; gi < pl->groups.size(); ++gi) {
+      const PlanGroup& g = pl->groups[gi];
       chemora::BatchTable bt;
       bt.args = pl->d_args + st * (size_t)npatch + g.first;
       bt.tile_start = pl->d_tile_start + g.toff;
+      bt.queue = nqueue ? pl->d_queue + (st * pl->groups.size() + gi) * chemora::QUEUE_INTS : nullptr;
       bt.npatch = g.count;
       bt.ntiles = g.ntiles;
-      dispatch_batch(params, g.variant, bt, pl->capture);
+      dispatch_batch(params, g.variant, bt, g.grid, pl->capture);
     }
     if (periodic)
       for (int r = 0; r < npatch; ++r) {
@@ -1785,6 +1844,20 @@ int chemora_plan_create_synced(const chemora_params* params, const chemora_patch
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CHEMORA_EINVAL, "dt must be finite and > 0");
   if (integrator != 3 && integrator != 4) return fail(CHEMORA_EINVAL, "integrator %d not 3 or 4", integrator);
   return plan_create(params, patches, scratch, npatch, 0.0, tune_cache_path, stream, out, integrator == 3, dt);
+}
+
+int chemora_set_plan_dispatch(int32_t mode) {
+  g_error.clear();
+  if (mode != CHEMORA_DISPATCH_PERSISTENT && mode != CHEMORA_DISPATCH_PER_TILE)
+    return fail(CHEMORA_EINVAL, "unknown plan dispatch mode %d", mode);
+  g_plan_dispatch.store(mode);
+  return CHEMORA_OK;
+}
+
+int chemora_plan_dispatch(const chemora_plan* plan) {
+  g_error.clear();
+  if (!plan) return fail(CHEMORA_EINVAL, "plan is NULL");
+  return plan->dispatch;
 }
 
 int chemora_plan_patch_variant(const chemora_plan* plan, int32_t p) {

@@ -77,16 +77,25 @@ struct StageArgs {
   int mode;                        // a Mode
 };
 
+constexpr int NXCD = 8;
+
 // Batched form: all tiles of all patches of a plan.  ntiles == 0 selects the
 // single-patch form (the StageArgs kernel argument, one tile per work-group).
+// queue == nullptr: one work-group per tile.  Otherwise the launch is
+// persistent (a few work-groups per CU) and its work-groups pull tiles from
+// NXCD queues -- queue x hands out the x-th contiguous eighth of the tile
+// list, a work-group pulls from its own XCD's queue first and then from the
+// others -- and queue[NXCD] counts the work-groups that have finished: the
+// last one returns every counter to zero for the next launch.  The counters
+// must be zero when the launch starts.
+constexpr int QUEUE_INTS = 16;   // ints per launch: NXCD heads, the finished count, padding
 struct BatchTable {
   const StageArgs* args;     // one per patch (device memory)
   const int* tile_start;     // prefix sums of tiles per patch, npatch + 1 entries
+  int* queue;                // persistent form: QUEUE_INTS zeroed counters
   int npatch;
   int ntiles;
 };
-
-constexpr int NXCD = 8;
 
 // ---- device helpers ------------------------------------------------------
 // Materialises a value in registers at this point.  Without it the compiler
@@ -153,6 +162,24 @@ __device__ __forceinline__ StageArgs uniform_args(const StageArgs* p) {
   return a;
 }
 
+// The XCD a work-group runs on (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ int xcd_id() { return __builtin_amdgcn_s_getreg(0xf814) & (NXCD - 1); }
+
+// Persistent form: the next tile for a work-group on XCD x, or -1 when every
+// queue is empty.  Queue q hands out tiles [q n / NXCD, (q + 1) n / NXCD) in
+// order; each atomic increment hands out one index exactly once, so a tile
+// is taken by exactly one work-group whichever queues the work-groups try.
+__device__ __forceinline__ int pull_tile(const BatchTable& bt, int x) {
+  for (int s = 0; s < NXCD; ++s) {
+    const int q = (x + s) & (NXCD - 1);
+    const int lo = (int)((int64_t)q * bt.ntiles / NXCD), hi = (int)((int64_t)(q + 1) * bt.ntiles / NXCD);
+    if (hi <= lo || __atomic_load_n(bt.queue + q, __ATOMIC_RELAXED) >= hi - lo) continue;
+    const int i = atomicAdd(bt.queue + q, 1);
+    if (i < hi - lo) return lo + i;
+  }
+  return -1;
+}
+
 // patch of global tile t (binary search over the prefix sums)
 __device__ __forceinline__ int batch_patch(const BatchTable& bt, int t) {
   int lo = 0, hi = bt.npatch - 1;
@@ -180,12 +207,47 @@ inline bool variant_supported(int order, int v) {
 
 // ---- host-side launchers, one per order (stage_o4.hip / stage_o8.hip) ----
 // Single-patch form: bt.ntiles == 0, grid = tiles of a.  Batched form: a is
-// unused, grid = bt.ntiles (one work-group per tile of the plan).  The tile
-// counts in a / the plan tables must be those of `variant`.
+// unused, grid = bt.ntiles (one work-group per tile of the plan) or, with
+// persist (bt.queue set), any grid >= 1.  The tile counts in a / the plan
+// tables must be those of `variant`.  wgs != nullptr: nothing is launched;
+// *wgs receives how many work-groups of that kernel fit one CU (0 if the
+// query fails).  Each (precision, persist) part is its own object file.
 // split: FP32 stencil combinations and algebra (order 4 only)
-void launch_stage_o4(int variant, bool split, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt,
-                     int grid, hipStream_t s);
-void launch_stage_o8(int variant, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid,
-                     hipStream_t s);
+template <bool SPLIT, bool PERSIST>
+void launch_stage_o4_part(int variant, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid,
+                          hipStream_t s, int* wgs);
+template <bool PERSIST>
+void launch_stage_o8_part(int variant, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, int grid,
+                          hipStream_t s, int* wgs);
+#define CHEMORA_DECLARE_O4_PART(SP, PE)                                                                          \
+  template <>                                                                                                     \
+  void launch_stage_o4_part<SP, PE>(int variant, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt, \
+                                    int grid, hipStream_t s, int* wgs);
+CHEMORA_DECLARE_O4_PART(false, false)
+CHEMORA_DECLARE_O4_PART(false, true)
+CHEMORA_DECLARE_O4_PART(true, false)
+CHEMORA_DECLARE_O4_PART(true, true)
+#undef CHEMORA_DECLARE_O4_PART
+template <>
+void launch_stage_o8_part<false>(int variant, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt,
+                                 int grid, hipStream_t s, int* wgs);
+template <>
+void launch_stage_o8_part<true>(int variant, bool upwind, int ko_r, const StageArgs& a, const BatchTable& bt,
+                                int grid, hipStream_t s, int* wgs);
+
+inline void launch_stage_o4(int variant, bool split, bool persist, bool upwind, int ko_r, const StageArgs& a,
+                            const BatchTable& bt, int grid, hipStream_t s, int* wgs = nullptr) {
+  if (split)
+    persist ? launch_stage_o4_part<true, true>(variant, upwind, ko_r, a, bt, grid, s, wgs)
+            : launch_stage_o4_part<true, false>(variant, upwind, ko_r, a, bt, grid, s, wgs);
+  else
+    persist ? launch_stage_o4_part<false, true>(variant, upwind, ko_r, a, bt, grid, s, wgs)
+            : launch_stage_o4_part<false, false>(variant, upwind, ko_r, a, bt, grid, s, wgs);
+}
+inline void launch_stage_o8(int variant, bool persist, bool upwind, int ko_r, const StageArgs& a,
+                            const BatchTable& bt, int grid, hipStream_t s, int* wgs = nullptr) {
+  persist ? launch_stage_o8_part<true>(variant, upwind, ko_r, a, bt, grid, s, wgs)
+          : launch_stage_o8_part<false>(variant, upwind, ko_r, a, bt, grid, s, wgs);
+}
 
 }  // namespace chemora

@@ -212,11 +212,17 @@ struct LdsLayout {
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 // a staged grid function's advection and dissipation terms; its right-hand
-// side is (algebra + advection) + dissipation
-template <typename TC>
+// side is (algebra + advection) + dissipation, or algebra + (advection and
+// dissipation summed together) where MERGED
+template <typename TC, bool MERGED = false>
 struct AdvDiss {
   TC adv, diss;
-  __device__ __forceinline__ TC rhs(TC alg) const { return (alg + adv) + diss; }
+  __device__ __forceinline__ TC rhs(TC alg) const {
+    if constexpr (MERGED)
+      return alg + adv;
+    else
+      return (alg + adv) + diss;
+  }
 };
 
 // s_waitcnt vmcnt(N) lgkmcnt(0) (gfx9 encoding: vmcnt bits 3:0 and 15:14,
@@ -498,11 +504,83 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     bound(v);
     return v;
   };
+  // Order 4: the three mixed derivatives of a phase (slots xy, xz, yz) with
+  // their tap reads pipelined -- the taps of the next one are read from LDS
+  // before the current one is combined, so that their latency overlaps that
+  // arithmetic.  Each value is computed exactly as D2m computes it.
+  struct Mix16 {
+    double m[4][4];
+  };
+  auto mixed_taps = [&](const auto& src, int slot) __attribute__((always_inline)) {
+    constexpr int M = 2;
+    const Taps tap = src.t.fresh();
+    const int ai = SI(slot), bj = SJ(slot);
+    Mix16 r;
+#pragma unroll
+    for (int oa = -M; oa <= M; ++oa)
+#pragma unroll
+      for (int ob = -M; ob <= M; ++ob)
+        if (oa != 0 && ob != 0) {
+          int d[3] = {0, 0, 0};
+          d[ai] = oa;
+          d[bj] = ob;
+          r.m[oa < 0 ? oa + M : oa + M - 1][ob < 0 ? ob + M : ob + M - 1] = tap(d[0], d[1], d[2]);
+        }
+    return r;
+  };
+  auto mixed_from = [&](auto tag, Mix16& r) __attribute__((always_inline)) {
+    using TC = decltype(tag);
+    keep(r.m);
+    auto outer = [&](int oa) __attribute__((always_inline)) {
+      const int i = oa < 0 ? oa + 2 : oa + 1;
+      return St::first([&](int ob) { return r.m[i][ob < 0 ? ob + 2 : ob + 1]; });
+    };
+    TC v;
+    if constexpr (std::is_same<TC, float>::value)
+      v = St::first_f(outer) * float(a.sc.d11);
+    else
+      v = St::first(outer) * a.sc.d11;
+    bound(v);
+    return v;
+  };
+  // mx[1], mx[2], mx[4] (the off-diagonal slots) of the staged GF
+  auto mixed3 = [&](auto tag, const auto& src, auto (&mx)[6]) __attribute__((always_inline)) {
+    static_assert(ORDER == 4, "pipelined mixed derivatives are built for order 4");
+    Mix16 A = mixed_taps(src, 1);
+    Mix16 B = mixed_taps(src, 2);
+    __builtin_amdgcn_sched_barrier(0);
+    mx[1] = mixed_from(tag, A);
+    Mix16 C = mixed_taps(src, 4);
+    __builtin_amdgcn_sched_barrier(0);
+    mx[2] = mixed_from(tag, B);
+    mx[4] = mixed_from(tag, C);
+  };
+#ifndef CHEMORA_PIPE_MIXED
+#define CHEMORA_PIPE_MIXED 1
+#endif
+  constexpr bool PIPE = MIXED_GROUP && CHEMORA_PIPE_MIXED;
+
   // advection and dissipation of the staged GF; its right-hand side is
   // (algebra + advection) + dissipation
   auto advdiss = [&](auto tag, const auto& src) __attribute__((always_inline)) {
     using TC = decltype(tag);
     constexpr bool F32 = std::is_same<TC, float>::value;
+    if constexpr (UPWIND && !F32 && KOQ) {
+      // the dissipation is Q times its scale (its radius is Q's, or 0), so
+      // per axis beta * lopsided + dissipation = cA beta A + (cQ |beta| + ko) Q:
+      // one sum of both terms, Q summed exactly as Kreiss-Oliger sums
+      double acc = 0.0;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        auto along = [&](int o) __attribute__((always_inline)) { return src(ax, o); };
+        const double Qs = ko_sum<St::UR>(along, St::USYM);
+        const double As = St::upwind_anti(along);
+        const double kq = __builtin_fma(cQ, __builtin_fabs(bet_d[ax]), a.sc.ko);
+        acc = __builtin_fma(cA * bet_d[ax], As, ax == 0 ? kq * Qs : __builtin_fma(kq, Qs, acc));
+        bound(acc);
+      }
+      return AdvDiss<TC, true>{acc, 0.0};
+    } else {
     TC adv = TC(0.0), diss = TC(0.0);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
@@ -546,6 +624,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       bound(diss);
     }
     return AdvDiss<TC>{adv, diss};
+    }
   };
   auto finish = [&](auto tag, const auto& src, decltype(tag) alg) __attribute__((always_inline)) {
     return advdiss(tag, src).rhs(alg);
@@ -648,11 +727,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     T d2p[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) d2p[ax] = D2d(T(), src, ax);
-    const AdvDiss<T> ad = advdiss(T(), src);
+    const auto ad = advdiss(T(), src);
+    T mx[6];
+    if constexpr (PIPE) mixed3(T(), src, mx);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       const int qi = SI(q), qj = SJ(q);
-      const T dd = qi == qj ? d2p[qi] : D2m(T(), src, q);
+      const T dd = qi == qj ? d2p[qi] : (PIPE ? mx[q] : D2m(T(), src, q));
       xts[c] += T(W(q)) * gu[q] * dd;
       if (qj == c) ddiv[qi] += dd;
       if (qi == c && qi != qj) ddiv[qj] += dd;
@@ -698,10 +779,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       T d2p[3];
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) d2p[ax] = D2d(T(), src, ax);
-      const AdvDiss<T> ad = advdiss(T(), src);
+      const auto ad = advdiss(T(), src);
       T r = T(0.0);
+      T mx[6];
+      if constexpr (PIPE) mixed3(T(), src, mx);
 #pragma unroll
-      for (int q = 0; q < 6; ++q) r += T(W(q)) * gu[q] * (SI(q) == SJ(q) ? d2p[SI(q)] : D2m(T(), src, q));
+      for (int q = 0; q < 6; ++q)
+        r += T(W(q)) * gu[q] * (SI(q) == SJ(q) ? d2p[SI(q)] : (PIPE ? mx[q] : D2m(T(), src, q)));
       Ric[s] = -T(0.5) * r;
       const int i = SI(s), jj = SJ(s);
       T lie = T(0.0);
@@ -780,11 +864,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       TC d2p[3];
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) d2p[ax] = D2d(tag, src, ax);
-      const AdvDiss<TC> ad = advdiss(tag, src);
-      TC cdd[6];
+      const auto ad = advdiss(tag, src);
+      TC cdd[6], mx[6];
+      if constexpr (PIPE) mixed3(tag, src, mx);
 #pragma unroll
       for (int s = 0; s < 6; ++s)
-        cdd[s] = (SI(s) == SJ(s) ? d2p[SI(s)] : D2m(tag, src, s)) -
+        cdd[s] = (SI(s) == SJ(s) ? d2p[SI(s)] : (PIPE ? mx[s] : D2m(tag, src, s))) -
                  (TC(Gu[0][s]) * dc[0] + TC(Gu[1][s]) * dc[1] + TC(Gu[2][s]) * dc[2]);
       TC trc = TC(0.0), dchi2 = TC(0.0);
 #pragma unroll
@@ -845,7 +930,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     T d2p[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) d2p[ax] = D2d(T(), src, ax);
-    const AdvDiss<T> ad = advdiss(T(), src);
+    const auto ad = advdiss(T(), src);
+    T mx[6];
+    if constexpr (PIPE) mixed3(T(), src, mx);
     // the 1/chi correction is evaluated in FP64 in both precisions
     double gudchi_da = 0.0;
 #pragma unroll
@@ -856,7 +943,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     for (int s = 0; s < 6; ++s) {
       const int i = SI(s), jj = SJ(s);
       const double corr = 0.5 * ichi * (double(g[s]) * gudchi_da - dchi[jj] * double(da[i]) - dchi[i] * double(da[jj]));
-      DDa[s] = (SI(s) == SJ(s) ? d2p[SI(s)] : D2m(T(), src, s)) - (Gu[0][s] * da[0] + Gu[1][s] * da[1] + Gu[2][s] * da[2]) -
+      DDa[s] = (SI(s) == SJ(s) ? d2p[SI(s)] : (PIPE ? mx[s] : D2m(T(), src, s))) - (Gu[0][s] * da[0] + Gu[1][s] * da[1] + Gu[2][s] * da[2]) -
                T(corr);
     }
     keep(da);
@@ -1021,16 +1108,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   }
 }
 
-// The stage kernel, one tile per work-group, hardware block ids remapped so
-// that each XCD gets a contiguous range of tiles (neighbours share its L2).
-// Single-patch form (bt.ntiles == 0): the tiles of patch a1.  Batched form:
-// the concatenated tiles of all patches of a plan, each work-group finding
-// its patch by binary search; the hardware dispatcher balances the uneven
-// patches dynamically.
+// The stage kernel.  Single-patch form (bt.ntiles == 0): the tiles of patch
+// a1, one per work-group, hardware block ids remapped so that each XCD gets
+// a contiguous range of tiles (neighbours share its L2).  Batched form: the
+// concatenated tiles of all patches of a plan, each work-group finding its
+// patch by binary search -- one tile per work-group in the same XCD order
+// (bt.queue null), or persistent: a grid sized to the resident work-groups,
+// each pulling tiles from its XCD's queue (the same contiguous eighth of
+// the tile list) until all queues are empty.
 // OCC waves share a SIMD (OCC * 4 / WPG work-groups per CU): their NB
 // staging buffers must fit the 160 KB LDS together, and the registers per
 // lane drop to 512 / OCC.
-template <int ORDER, bool UPWIND, int R, int NB, int OCC, int TX, int WPG, typename T, int TZ = 1, bool KOQ = false>
+// PERSIST: the persistent batched form (bt.queue set); the other forms are
+// separate instances without its loop, whose loop-carried state would cost
+// them scalar registers.
+template <int ORDER, bool UPWIND, int R, int NB, int OCC, int TX, int WPG, typename T, int TZ = 1, bool KOQ = false,
+          bool PERSIST = false>
 __global__ __launch_bounds__(64 * WPG) __attribute__((amdgpu_waves_per_eu(OCC)))
 void stage_kernel(StageArgs a1, BatchTable bt) {
   using SH = Shape<TX, WPG, TZ>;
@@ -1058,14 +1151,42 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
   double* bufs[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) bufs[i] = all[i];
-  int t = xcd_tile(blockIdx.x, gridDim.x);
-  StageArgs a = a1;
-  if (bt.ntiles > 0) {
-    const int p = batch_patch(bt, t);
-    a = uniform_args(bt.args + p);
-    t -= uniform(bt.tile_start[p]);
+  constexpr bool BOUND = ORDER >= 8 || OCC >= 2;
+  if constexpr (!PERSIST) {
+    int t = xcd_tile(blockIdx.x, gridDim.x);
+    StageArgs a = a1;
+    if (bt.ntiles > 0) {
+      const int p = batch_patch(bt, t);
+      a = uniform_args(bt.args + p);
+      t -= uniform(bt.tile_start[p]);
+    }
+    stage_tile<ORDER, UPWIND, R, NB, BOUND, OFFS_LDS, PARK, SH, T, KOQ>(a, t, bufs, offs, park);
+  } else {
+    // One work-item fetches each tile and hands it over through LDS.  Every
+    // work-item reads the slot before stage_tile's first barrier, and the
+    // fetch after it comes after stage_tile's last barrier, so one slot
+    // suffices.
+    const bool leader = threadIdx.x == 0 && threadIdx.y == 0;
+    const int x = xcd_id();
+    __shared__ int next;
+    for (;;) {
+      if (leader) next = pull_tile(bt, x);
+      __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the LDS write is done
+      lds_barrier();
+      const int t = uniform(next);
+      if (t < 0) break;
+      const int p = batch_patch(bt, t);
+      const StageArgs a = uniform_args(bt.args + p);
+      stage_tile<ORDER, UPWIND, R, NB, BOUND, OFFS_LDS, PARK, SH, T, KOQ>(a, t - uniform(bt.tile_start[p]), bufs,
+                                                                          offs, park);
+    }
+    // the last work-group to finish leaves the counters zeroed for the next
+    // launch: every other work-group has made its last pull by then
+    if (leader && atomicAdd(bt.queue + NXCD, 1) == (int)gridDim.x - 1) {
+#pragma unroll
+      for (int q = 0; q <= NXCD; ++q) atomicExch(bt.queue + q, 0);
+    }
   }
-  stage_tile<ORDER, UPWIND, R, NB, (ORDER >= 8 || OCC >= 2), OFFS_LDS, PARK, SH, T, KOQ>(a, t, bufs, offs, park);
 }
 
 }  // namespace chemora

@@ -29,7 +29,16 @@ def test_library_exports_every_declared_symbol():
     assert set(declared) == set(C.EXPORTS)
     for name in declared:
         assert hasattr(L, name), name
-    assert C.chemora_abi_version() == 102
+    assert C.chemora_abi_version() == 103
+
+
+def test_plan_dispatch_mode_checks():
+    L = C.lib()
+    assert L.chemora_set_plan_dispatch(2) == C.EINVAL
+    assert L.chemora_set_plan_dispatch(-1) == C.EINVAL
+    assert L.chemora_plan_dispatch(None) == C.EINVAL
+    assert L.chemora_set_plan_dispatch(C.DISPATCH_PER_TILE) == C.OK
+    assert L.chemora_set_plan_dispatch(C.DISPATCH_PERSISTENT) == C.OK
 
 
 def test_required_ghost_matches_inputs():

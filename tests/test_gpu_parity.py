@@ -412,6 +412,45 @@ def test_batched_plan_equals_per_patch_steps(torch_cuda):
     B2.close()
 
 
+@pytest.mark.parametrize("integrator", ["rk4", "rk3"])
+def test_persistent_plan_equals_per_tile_dispatch(torch_cuda, integrator):
+    """Plans launch each stage persistently by default: resident work-groups
+    pull tiles from per-XCD queues that every launch leaves zeroed for the
+    next.  The same plan dispatched one work-group per tile computes the
+    same bits, and so do per-patch steps, over several graph replays, with
+    two tile-variant groups (two launches and two queue sets per stage) of
+    which one has fewer tiles than there are XCDs (its work-groups pull from
+    other XCDs' queues)."""
+    from paper_1307_6488_amd import chemora as C
+    torch = torch_cuda
+    params = I.workload(2).params
+    grids = _small_patches(count=5, seed=31) + [bl_grid((9, 3, 3), 3)]
+    states = [I.brill_lindquist(g) for g in grids]
+    P = C.make_params(params)
+    tiny = C.make_patch(grids[-1], 0x7F0000001000)   # class key only
+    before = C.chemora_tile_variant(P, tiny)
+    C.chemora_set_tile_variant(P, tiny, 0)            # 64x4: 3 tiles for the tiny patch
+    try:
+        out = {}
+        for mode in (C.DISPATCH_PERSISTENT, C.DISPATCH_PER_TILE):
+            B = C.Batch(params, grids, states, 0.25, integrator=integrator, dispatch=mode)
+            assert B.dispatch() == mode
+            variants = B.variants()
+            B.step(2)
+            B.step(3)
+            torch.cuda.synchronize()
+            out[mode] = [p.u.cpu().numpy() for p in B.patches]
+            B.close()
+        say(f"persistent vs per-tile {integrator}: variants {variants}")
+        assert variants[-1] == 0 and len(set(variants)) == 2, variants
+        step = gpu_rk3 if integrator == "rk3" else gpu_rk4
+        for g, u0, a, b in zip(grids, states, out[C.DISPATCH_PERSISTENT], out[C.DISPATCH_PER_TILE]):
+            assert np.array_equal(a, b, equal_nan=True), g.n
+            assert np.array_equal(a, step(torch, params, g, u0, 0.25 * g.h, 5), equal_nan=True), g.n
+    finally:
+        C.chemora_set_tile_variant(P, tiny, before)
+
+
 @pytest.mark.parametrize("bc", ["static", "periodic"])
 def test_rk3_plan_equals_per_patch_steps_and_oracle(torch_cuda, bc):
     """An RK3 plan over uneven patches advances every patch exactly as
