@@ -54,7 +54,9 @@
 // [-R, TX-1+R] (pitch P = TX + 2R).
 #pragma once
 
+#include <cstddef>
 #include <type_traits>
+#include <utility>
 
 #include "fd_ops.hpp"
 #include "stage_common.hpp"
@@ -267,7 +269,7 @@ __device__ __forceinline__ void wait_staged(int m) {
 // work-item of the work-group must call it (it synchronises); it ends with a
 // barrier, so the buffers may be reused right after.
 template <int ORDER, bool UPWIND, int R, int NB, bool BOUND, bool OFFS_LDS, bool PARK, class SH, typename T,
-          bool KOQ>
+          bool KOQ, bool AXIS_GROUPS>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* const (&bufs)[NB], unsigned* offs,
                                            double* park) {
   // T: the arithmetic type of stencil combinations and algebra -- double, or
@@ -419,6 +421,23 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // each phase (two multiplies per axis; held through the kernel they would
   // take six registers more than beta)
   const double cA = St::UA * a.sc.up, cQ = St::UQ * a.sc.up;
+  // The stencils along the three axes read the phase's register-held axis
+  // taps.  FENCE_AXES 0: the first and pure second derivatives of the three
+  // axes (and, below, the advection and dissipation of the three axes) form
+  // one scheduling region each, so that their independent dependency chains
+  // interleave -- a dependent FP64 operation waits several issue slots for
+  // its operand -- and one fence follows the group.  1: a fence after every
+  // stencil.
+#ifndef CHEMORA_FENCE_AXES
+#define CHEMORA_FENCE_AXES 0
+#endif
+  constexpr bool FENCE_AXES = CHEMORA_FENCE_AXES != 0;
+  auto abound = [&](auto& v) __attribute__((always_inline)) {
+    if (FENCE_AXES) bound(v);
+  };
+  auto gbound = [&](auto& v) __attribute__((always_inline)) {
+    if (!FENCE_AXES) bound(v);
+  };
   auto D1 = [&](auto tag, const auto& src, int ax) __attribute__((always_inline)) {
     using TC = decltype(tag);
     auto along = [&](int o) __attribute__((always_inline)) { return src(ax, o); };
@@ -427,7 +446,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       v = St::first_f(along) * float(a.sc.d1);
     else
       v = St::first(along) * a.sc.d1;
-    bound(v);
+    abound(v);
     return v;
   };
   // pure second derivative along ax
@@ -439,8 +458,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       v = St::second_f(along) * float(a.sc.d2);
     else
       v = St::second(along) * a.sc.d2;
-    bound(v);
+    abound(v);
     return v;
+  };
+  // the first (and pure second) derivatives along the three axes
+  auto D1all = [&](auto tag, const auto& src, auto (&d)[3]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) d[ax] = D1(tag, src, ax);
+    gbound(d);
+  };
+  auto D12all = [&](auto tag, const auto& src, auto (&d)[3], auto (&d2)[3]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) d[ax] = D1(tag, src, ax);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) d2[ax] = D2d(tag, src, ax);
+    gbound(d);
+    gbound(d2);
   };
   // mixed second derivative of slot (ai != bj): outer D1 along ai of inner
   // D1's along bj (the inner ones FP64 in both precisions)
@@ -489,8 +522,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
             return ti(d[0], d[1], d[2]);
           });
         };
-        double ip = in_at(k), im = in_at(-k);
-        bound(ip);
+        double ip = in_at(k);
+        // with axis-by-axis taps (two waves per SIMD at order 8) one inner
+        // stencil per group
+        if constexpr (AXIS_GROUPS) bound(ip);
+        double im = in_at(-k);
+        if constexpr (!AXIS_GROUPS) bound(ip);
         bound(im);
         inner[idx(k)] = ip;
         inner[idx(-k)] = im;
@@ -560,45 +597,32 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
 #endif
   constexpr bool PIPE = MIXED_GROUP && CHEMORA_PIPE_MIXED;
 
-  // advection and dissipation of the staged GF; its right-hand side is
-  // (algebra + advection) + dissipation
-  auto advdiss = [&](auto tag, const auto& src) __attribute__((always_inline)) {
+  // Advection and dissipation of the staged GF, one axis at a time: its
+  // right-hand side is (algebra + advection) + dissipation.  ad_step adds
+  // axis ax (ax = 0, 1, 2 in turn) to the running sums st[0] (advection)
+  // and st[1] (dissipation).
+  auto ad_step = [&](auto tag, auto&& along, int ax, auto (&st)[2]) __attribute__((always_inline)) {
     using TC = decltype(tag);
     constexpr bool F32 = std::is_same<TC, float>::value;
     if constexpr (UPWIND && !F32 && KOQ) {
       // the dissipation is Q times its scale (its radius is Q's, or 0), so
       // per axis beta * lopsided + dissipation = cA beta A + (cQ |beta| + ko) Q:
-      // one sum of both terms, Q summed exactly as Kreiss-Oliger sums
-      double acc = 0.0;
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        auto along = [&](int o) __attribute__((always_inline)) { return src(ax, o); };
-        const double Qs = ko_sum<St::UR>(along, St::USYM);
-        const double As = St::upwind_anti(along);
-        const double kq = __builtin_fma(cQ, __builtin_fabs(bet_d[ax]), a.sc.ko);
-        acc = __builtin_fma(cA * bet_d[ax], As, ax == 0 ? kq * Qs : __builtin_fma(kq, Qs, acc));
-        bound(acc);
-      }
-      return AdvDiss<TC, true>{acc, 0.0};
+      // one sum of both terms (st[0]), Q summed exactly as Kreiss-Oliger sums
+      const double Qs = ko_sum<St::UR>(along, St::USYM);
+      const double As = St::upwind_anti(along);
+      const double kq = __builtin_fma(cQ, __builtin_fabs(bet_d[ax]), a.sc.ko);
+      st[0] = __builtin_fma(cA * bet_d[ax], As, ax == 0 ? kq * Qs : __builtin_fma(kq, Qs, st[0]));
+      abound(st[0]);
     } else {
-    TC adv = TC(0.0), diss = TC(0.0);
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      auto along = [&](int o) __attribute__((always_inline)) { return src(ax, o); };
       const TC b = TC(bet_d[ax]);
       TC qd;
       if constexpr (UPWIND && !F32) {
         // the antisymmetric part and the symmetric difference Q of the
-        // lopsided stencils, Q summed exactly as Kreiss-Oliger sums (so with
-        // KOQ -- the dissipation radius is Q's, or 0 -- the dissipation is
-        // Q times its scale, the same bits as the separate sum)
+        // lopsided stencils, Q summed exactly as Kreiss-Oliger sums
         const double Qs = ko_sum<St::UR>(along, St::USYM);
         const double As = St::upwind_anti(along);
-        adv = __builtin_fma(cA * bet_d[ax], As, __builtin_fma(cQ * __builtin_fabs(bet_d[ax]), Qs, adv));
-        if constexpr (KOQ)
-          qd = Qs * a.sc.ko;
-        else
-          qd = ko_axis<R>(along, a.sc.kow, a.sc.ko);
+        st[0] = __builtin_fma(cA * bet_d[ax], As, __builtin_fma(cQ * __builtin_fabs(bet_d[ax]), Qs, st[0]));
+        qd = ko_axis<R>(along, a.sc.kow, a.sc.ko);
       } else {
         TC d;
         if constexpr (UPWIND) {
@@ -612,22 +636,90 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
           else
             d = St::first(along) * a.sc.d1;
         }
-        adv += b * d;
+        st[0] += b * d;
         // radius 0 has zero weights and scale: the term is an exact zero
         if constexpr (F32)
           qd = ko_axis_f<R>(along, a.sc.kow, float(a.sc.ko));
         else
           qd = ko_axis<R>(along, a.sc.kow, a.sc.ko);
       }
-      diss = (ax == 0) ? qd : diss + qd;
-      bound(adv);
-      bound(diss);
-    }
-    return AdvDiss<TC>{adv, diss};
+      st[1] = (ax == 0) ? qd : st[1] + qd;
+      bound(st[0]);
+      bound(st[1]);
     }
   };
-  auto finish = [&](auto tag, const auto& src, decltype(tag) alg) __attribute__((always_inline)) {
-    return advdiss(tag, src).rhs(alg);
+  auto ad_result = [&](auto tag, auto (&st)[2]) __attribute__((always_inline)) {
+    using TC = decltype(tag);
+    if constexpr (UPWIND && !std::is_same<TC, float>::value && KOQ) {
+      gbound(st[0]);
+      return AdvDiss<TC, true>{st[0], TC(0.0)};
+    } else {
+      return AdvDiss<TC>{st[0], st[1]};
+    }
+  };
+  auto advdiss = [&](auto tag, const auto& src) __attribute__((always_inline)) {
+    using TC = decltype(tag);
+    TC st[2] = {TC(0.0), TC(0.0)};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) ad_step(tag, [&](int o) __attribute__((always_inline)) { return src(ax, o); }, ax, st);
+    return ad_result(tag, st);
+  };
+  // A phase's stencils along the axes through the point: the first
+  // derivatives into d1 and the pure second derivatives into d2 (either may
+  // be nullptr: not wanted), and the advection and dissipation terms.
+  // AXIS_GROUPS 0: the 1 + 6R axis taps are read in one group (phase_src);
+  // 1: axis by axis, each axis' 1 + 2R taps read in one group and all of that
+  // axis' stencils formed from them before the next axis is read (fewer
+  // live registers, the same arithmetic in the same order).  The result's
+  // t is the phase's LDS view for the mixed derivatives.
+  auto stencils = [&](auto tag, const Taps& t0, auto d1, auto d2) __attribute__((always_inline)) {
+    using TC = decltype(tag);
+    constexpr bool W1 = !std::is_same<decltype(d1), std::nullptr_t>::value;
+    constexpr bool W2 = !std::is_same<decltype(d2), std::nullptr_t>::value;
+    struct Out {
+      struct {
+        Taps t;
+      } src;
+      decltype(advdiss(tag, std::declval<Axes>())) ad;
+    } out;
+    out.src.t = t0;
+    if constexpr (!AXIS_GROUPS) {
+      const auto src = phase_src(t0);
+      if constexpr (W1 && W2)
+        D12all(tag, src, *d1, *d2);
+      else if constexpr (W1)
+        D1all(tag, src, *d1);
+      out.ad = advdiss(tag, src);
+    } else {
+      TC st[2] = {TC(0.0), TC(0.0)};
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const Taps tap = t0.fresh();
+        double c = tap(0, 0, 0), v[2 * R];
+#pragma unroll
+        for (int o = 1; o <= R; ++o) {
+          int d[3] = {0, 0, 0};
+          d[ax] = -o;
+          v[R - o] = tap(d[0], d[1], d[2]);
+          d[ax] = o;
+          v[R + o - 1] = tap(d[0], d[1], d[2]);
+        }
+        keep(c);
+        keep(v);
+        auto along = [&](int o) __attribute__((always_inline)) { return o == 0 ? c : v[o < 0 ? o + R : o + R - 1]; };
+        struct One {
+          decltype(along)& f;
+          __device__ __forceinline__ double operator()(int, int o) const { return f(o); }
+        } one{along};
+        if constexpr (W1) (*d1)[ax] = D1(tag, one, ax);
+        if constexpr (W2) (*d2)[ax] = D2d(tag, one, ax);
+        ad_step(tag, along, ax, st);
+        if constexpr (W1) bound((*d1)[ax]);
+        if constexpr (W2) bound((*d2)[ax]);
+      }
+      out.ad = ad_result(tag, st);
+    }
+    return out;
   };
   // RK epilogue.  Its operands (u_n / accumulator values at the point) are
   // loaded by epi_load() before the phase issues its staging loads: loads
@@ -674,13 +766,27 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // complete in every wave (own loads waited for, then the barrier)
   // The scheduling barrier keeps the phase's pointwise loads (issued just
   // before) ahead of its staging loads in the instruction stream.
+  // One buffer (NB = 1): phase p issues its own grid function, waits for it
+  // and meets the barrier before computing, and meets another at its end so
+  // that no wave overwrites the buffer while another still reads it; the
+  // other work-groups on the CU compute in the meantime.
   auto begin = [&](int p) __attribute__((always_inline)) {
     __builtin_amdgcn_sched_barrier(0);
-    if (p + NB - 1 < nphase) issue(seq_gf(p + NB - 1), bufs[(p + NB - 1) % NB]);
+    if constexpr (NB == 1) {
+      issue(seq_gf(p), bufs[0]);
+      wait_vm<0>();
+      lds_barrier();
+    } else {
+      if (p + NB - 1 < nphase) issue(seq_gf(p + NB - 1), bufs[(p + NB - 1) % NB]);
+    }
   };
   auto sync = [&](int p) __attribute__((always_inline)) {
-    wait_staged<NB, L::CMIN>(min(p + NB - 1, nphase - 1) - (p + 1));
-    lds_barrier();
+    if constexpr (NB == 1) {
+      if (p >= 0) lds_barrier();
+    } else {
+      wait_staged<NB, L::CMIN>(min(p + NB - 1, nphase - 1) - (p + 1));
+      lds_barrier();
+    }
   };
 
   const double alpha_d = val(gALPHA), chi_d = val(gCHI), K_d = val(gK);
@@ -719,15 +825,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const Epi e = epi_load(gBETA + c);
     const T Bc = T(val(gB + c));
     begin(c);
-    const auto src = phase_src(make_ops(bufs[c % NB]));
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) db[c][ax] = D1(T(), src, ax);
     // the axis stencils first, so that register-held axis taps die before
     // the mixed derivatives read theirs
     T d2p[3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) d2p[ax] = D2d(T(), src, ax);
-    const auto ad = advdiss(T(), src);
+    const auto ps = stencils(T(), make_ops(bufs[c % NB]), &db[c], &d2p);
+    const auto& src = ps.src;
+    const auto& ad = ps.ad;
     T mx[6];
     if constexpr (PIPE) mixed3(T(), src, mx);
 #pragma unroll
@@ -773,13 +876,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       const Epi e = epi_load(gGT + s);
       const T As = T(val(gAT + s));
       begin(p);
-      const auto src = phase_src(make_ops(bufs[p % NB]));
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) dg[s][ax] = D1(T(), src, ax);
       T d2p[3];
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) d2p[ax] = D2d(T(), src, ax);
-      const auto ad = advdiss(T(), src);
+      const auto ps = stencils(T(), make_ops(bufs[p % NB]), &dg[s], &d2p);
+      const auto& src = ps.src;
+      const auto& ad = ps.ad;
       T r = T(0.0);
       T mx[6];
       if constexpr (PIPE) mixed3(T(), src, mx);
@@ -857,14 +957,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     auto chi_phase = [&](auto tag) __attribute__((always_inline)) {
       using TC = decltype(tag);
       ChiPart out;
-      const auto src = phase_src(tap);
       TC dc[3];
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) dc[ax] = D1(tag, src, ax);
       TC d2p[3];
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) d2p[ax] = D2d(tag, src, ax);
-      const auto ad = advdiss(tag, src);
+      const auto ps = stencils(tag, tap, &dc, &d2p);
+      const auto& src = ps.src;
+      const auto& ad = ps.ad;
       TC cdd[6], mx[6];
       if constexpr (PIPE) mixed3(tag, src, mx);
 #pragma unroll
@@ -924,13 +1021,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   {
     const Epi e = epi_load(gALPHA);
     begin(10);
-    const auto src = phase_src(make_ops(bufs[10 % NB]));
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) da[ax] = D1(T(), src, ax);
     T d2p[3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) d2p[ax] = D2d(T(), src, ax);
-    const auto ad = advdiss(T(), src);
+    const auto ps = stencils(T(), make_ops(bufs[10 % NB]), &da, &d2p);
+    const auto& src = ps.src;
+    const auto& ad = ps.ad;
     T mx[6];
     if constexpr (PIPE) mixed3(T(), src, mx);
     // the 1/chi correction is evaluated in FP64 in both precisions
@@ -992,10 +1086,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   for (int c = 0; c < 3; ++c) {
     const int p = 11 + c;
     begin(p);
-    const auto src = phase_src(make_ops(bufs[p % NB]));
+    T dx[3];
+    const auto ps = stencils(T(), make_ops(bufs[p % NB]), &dx, nullptr);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const T d = D1(T(), src, ax);
+      const T d = dx[ax];
 #pragma unroll
       for (int s = 0; s < 6; ++s) {
         const int i = SI(s), jj = SJ(s);
@@ -1003,7 +1098,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
         if (i == ax) Ric[s] += T(0.5) * g[S(c, jj)] * d;
       }
     }
-    xt_ad[c] = finish(T(), src, T(0.0));
+    xt_ad[c] = ps.ad.rhs(T(0.0));
     keep(xt_ad[c]);
     keep(Ric);
     sync(p);
@@ -1038,11 +1133,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const Epi e = epi_load(gK);
     const Epi ex[3] = {epi_load(gXT), epi_load(gXT + 1), epi_load(gXT + 2)};
     begin(14);
-    const auto src = phase_src(make_ops(bufs[14 % NB]));
     T dK[3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) dK[ax] = D1(T(), src, ax);
-    emit(gK, finish(T(), src, -chi * trDDa + alpha * (AA + K * K * (T(1.0) / T(3.0)))), e);
+    const auto ps = stencils(T(), make_ops(bufs[14 % NB]), &dK, nullptr);
+    emit(gK, ps.ad.rhs(-chi * trDDa + alpha * (AA + K * K * (T(1.0) / T(3.0)))), e);
     if constexpr (PARK) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1074,7 +1167,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const int p = 15 + s;
     const Epi e = epi_load(gAT + s);
     begin(p);
-    const auto src = phase_src(make_ops(bufs[p % NB]));
+    const auto ps = stencils(T(), make_ops(bufs[p % NB]), nullptr, nullptr);
     const int i = SI(s), jj = SJ(s);
     T la = T(0.0), aa = T(0.0);
 #pragma unroll
@@ -1085,8 +1178,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       aa += A[S(i, kk)] * amkj;
     }
     const T X = alpha * Ric[s] - DDa[s];
-    emit(gAT + s, finish(T(), src, chi * (X - (T(1.0) / T(3.0)) * g[s] * trX) + alpha * (K * A[s] - T(2.0) * aa) + la -
-                              (T(2.0) / T(3.0)) * A[s] * divb), e);
+    emit(gAT + s, ps.ad.rhs(chi * (X - (T(1.0) / T(3.0)) * g[s] * trX) + alpha * (K * A[s] - T(2.0) * aa) + la -
+                            (T(2.0) / T(3.0)) * A[s] * divb), e);
     sync(p);
   }
 
@@ -1098,8 +1191,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       const Epi e = epi_load(gB + c);
       const T Bc = T(val(gB + c));
       begin(p);
-      const auto src = phase_src(make_ops(bufs[p % NB]));
-      emit(gB + c, finish(T(), src, xsrc[c] - gauge.eta * Bc), e);
+      const auto ps = stencils(T(), make_ops(bufs[p % NB]), nullptr, nullptr);
+      emit(gB + c, ps.ad.rhs(xsrc[c] - gauge.eta * Bc), e);
       sync(p);
     }
   } else {
@@ -1128,7 +1221,7 @@ __global__ __launch_bounds__(64 * WPG) __attribute__((amdgpu_waves_per_eu(OCC)))
 void stage_kernel(StageArgs a1, BatchTable bt) {
   using SH = Shape<TX, WPG, TZ>;
   using L = LdsLayout<R, ORDER / 2, SH>;
-  static_assert(NB >= 2 && NB <= 5, "staging depth");
+  static_assert(NB >= 1 && NB <= 5, "staging depth");
   constexpr int WG_PER_CU = (OCC * 4) / WPG > 1 ? (OCC * 4) / WPG : 1;
   constexpr int LDS_STAGE = NB * L::SIZEP * 8, LDS_OFFS = L::CPW * SH::NT * 4;
   // FP64 with two waves per SIMD keeps the per-lane staging offsets in LDS
@@ -1137,11 +1230,12 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
   constexpr bool OFFS_LDS = OCC == 2 && sizeof(T) == 8 && WG_PER_CU * (LDS_STAGE + LDS_OFFS) <= 160 * 1024;
   constexpr int LDS_BASE = LDS_STAGE + (OFFS_LDS ? LDS_OFFS : 0);
   static_assert(WG_PER_CU * LDS_BASE <= 160 * 1024, "LDS");
-  // order 4 at two waves per SIMD parks six accumulators in LDS where it fits
-  constexpr bool PARK = ORDER == 4 && OFFS_LDS && WG_PER_CU * (LDS_BASE + 6 * SH::NT * 8) <= 160 * 1024;
+  // two waves per SIMD park six accumulators in LDS where they fit (beside
+  // the persistent form's tile slot)
+  constexpr bool PARK = OFFS_LDS && WG_PER_CU * (LDS_BASE + 6 * SH::NT * 8 + (PERSIST ? 16 : 0)) <= 160 * 1024;
   // separate arrays, so the compiler can tell the buffers' staging loads apart
   __shared__ double b0[L::SIZEP];
-  __shared__ double b1[L::SIZEP];
+  __shared__ double b1[NB > 1 ? L::SIZEP : 1];
   __shared__ double b2[NB > 2 ? L::SIZEP : 1];
   __shared__ double b3[NB > 3 ? L::SIZEP : 1];
   __shared__ double b4[NB > 4 ? L::SIZEP : 1];
@@ -1152,6 +1246,9 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
 #pragma unroll
   for (int i = 0; i < NB; ++i) bufs[i] = all[i];
   constexpr bool BOUND = ORDER >= 8 || OCC >= 2;
+  // order 8 at two waves per SIMD reads its axis taps axis by axis (256
+  // registers per lane)
+  constexpr bool AXIS_GROUPS = ORDER >= 8 && OCC >= 2;
   if constexpr (!PERSIST) {
     int t = xcd_tile(blockIdx.x, gridDim.x);
     StageArgs a = a1;
@@ -1160,7 +1257,7 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
       a = uniform_args(bt.args + p);
       t -= uniform(bt.tile_start[p]);
     }
-    stage_tile<ORDER, UPWIND, R, NB, BOUND, OFFS_LDS, PARK, SH, T, KOQ>(a, t, bufs, offs, park);
+    stage_tile<ORDER, UPWIND, R, NB, BOUND, OFFS_LDS, PARK, SH, T, KOQ, AXIS_GROUPS>(a, t, bufs, offs, park);
   } else {
     // One work-item fetches each tile and hands it over through LDS.  Every
     // work-item reads the slot before stage_tile's first barrier, and the
@@ -1177,7 +1274,7 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
       if (t < 0) break;
       const int p = batch_patch(bt, t);
       const StageArgs a = uniform_args(bt.args + p);
-      stage_tile<ORDER, UPWIND, R, NB, BOUND, OFFS_LDS, PARK, SH, T, KOQ>(a, t - uniform(bt.tile_start[p]), bufs,
+      stage_tile<ORDER, UPWIND, R, NB, BOUND, OFFS_LDS, PARK, SH, T, KOQ, AXIS_GROUPS>(a, t - uniform(bt.tile_start[p]), bufs,
                                                                           offs, park);
     }
     // the last work-group to finish leaves the counters zeroed for the next

@@ -7,14 +7,17 @@
 #define CHEMORA_PART_PERSIST 0
 #endif
 
-// Staging depth and work-groups per CU.  The staged neighbourhood of one
-// grid function is 62-70 KB, so two buffers and one work-group (one wave per
-// SIMD) per CU is all the LDS holds.
+// Staging depth and waves per SIMD.  The staged neighbourhood of one grid
+// function is 54-70 KB, so the LDS holds either two buffers of one
+// work-group (one wave per SIMD: a wave's LDS, staging and barrier waits go
+// uncovered) or one buffer of each of two work-groups (two waves per SIMD,
+// each work-group waiting for its staging while the other computes; the
+// axis taps are then read axis by axis to fit 256 registers).
 #ifndef CHEMORA_STAGING_DEPTH_O8
-#define CHEMORA_STAGING_DEPTH_O8 2
+#define CHEMORA_STAGING_DEPTH_O8 1
 #endif
 #ifndef CHEMORA_WAVES_O8
-#define CHEMORA_WAVES_O8 1
+#define CHEMORA_WAVES_O8 2
 #endif
 
 namespace chemora {
