@@ -330,7 +330,7 @@ def batched_form(C, I, torch, no_tune, steps=10, warmup=2):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
 
-    def plan_ms(tune_cache_path, dispatch=C.DISPATCH_PERSISTENT):
+    def plan_ms(tune_cache_path, dispatch=C.DISPATCH_AUTO):
         B = C.Batch(params, grids, states, 0.25, tune_cache_path=tune_cache_path, dispatch=dispatch)
         B.step(warmup)
         torch.cuda.synchronize()
@@ -339,16 +339,17 @@ def batched_form(C, I, torch, no_tune, steps=10, warmup=2):
         e1.record()
         torch.cuda.synchronize()
         variants = sorted(set(B.variants()))
+        chosen = B.dispatch()
         B.close()
         del B
         torch.cuda.empty_cache()
-        return e0.elapsed_time(e1) / steps, variants
+        return e0.elapsed_time(e1) / steps, variants, chosen
     # untuned first (no size class of these patches has a table entry yet:
     # every patch runs the default 32x8 tile), then the tuned plan
     ms_untuned = None if no_tune else plan_ms(None)[0]
-    ms, variants = plan_ms(None if no_tune else _tune_cache())
-    # the same tuned plan with one work-group per tile instead of the
-    # persistent launches
+    ms, variants, chosen = plan_ms(None if no_tune else _tune_cache())
+    # the same tuned plan with each dispatch forced
+    ms_pers = plan_ms(None if no_tune else _tune_cache(), C.DISPATCH_PERSISTENT)[0]
     ms_tiles = plan_ms(None if no_tune else _tune_cache(), C.DISPATCH_PER_TILE)[0]
     # the same patches and data stepped one chemora_rk4_step call each, with
     # the tile variants the plan's tuner recorded for their classes
@@ -382,8 +383,11 @@ def batched_form(C, I, torch, no_tune, steps=10, warmup=2):
     return {"workload": "64 patches, 24-96 points per edge, order 4 upwind (batched plan)", "patches": len(grids),
             "points": npts, "steps": steps, "ms_per_step": ms, "value": npts / (ms * 1e-3),
             "unit": "updates/s", "tile_variants": [tile_name(C, v) for v in variants],
-            "dispatch": "persistent: resident work-groups pulling tiles from per-XCD queues, one launch per stage",
-            "per_tile_dispatch": {"ms_per_step": ms_tiles, "persistent_speedup": ms_tiles / ms},
+            "dispatch": ("persistent" if chosen == C.DISPATCH_PERSISTENT else "per-tile")
+            + " (the plan's timed choice)",
+            "persistent_dispatch": {"ms_per_step": ms_pers,
+                                    "launch": "resident work-groups pulling tiles from per-XCD queues"},
+            "per_tile_dispatch": {"ms_per_step": ms_tiles, "launch": "one work-group per tile"},
             "hbm_frac": npts / (ms * 1e-3) * 3072 / (HBM_PEAK_GBS * 1e9),
             "per_patch": {"ms_per_step": ms_pp, "value": npts / (ms_pp * 1e-3),
                           "calls": "one chemora_rk4_step per patch and step, same tile variants"},

@@ -329,29 +329,35 @@ int chemora_tile_variant_depth(int32_t variant);
  * strides; all share params) and their RK4 scratch buffers.  One RK4 step of
  * every patch is captured once into a HIP graph: per RK stage one launch
  * per tile variant covers the tiles of all the plan's patches of that
- * variant.  By default that launch is persistent: as many work-groups as
- * the GPU holds at once, each pulling tiles from a device-side queue of its
- * own XCD (the XCD's contiguous eighth of the tile list, so that
- * neighbouring tiles share that XCD's L2) and then from the other XCDs'
- * queues until every tile is done; the queue counters live in the plan and
- * each launch leaves them zeroed for the next, so the graph holds no
- * memset.  chemora_set_plan_dispatch selects one work-group per tile
- * instead.  Both compute the same bits.  Patch p advances with its own time
+ * variant, dispatched in one of two ways that compute the same bits:
+ * persistent -- as many work-groups as the GPU holds at once, each pulling
+ * tiles from a device-side queue of its own XCD (the XCD's contiguous
+ * eighth of the tile list, so that neighbouring tiles share that XCD's L2)
+ * and then from the other XCDs' queues until every tile is done; the queue
+ * counters live in the plan and each launch leaves them zeroed for the
+ * next, so the graph holds no memset -- or one work-group per tile in the
+ * same XCD order.  By default (CHEMORA_DISPATCH_AUTO) plan creation times
+ * a stage-2 pass both ways and keeps the faster; chemora_set_plan_dispatch
+ * forces one.  Patch p advances with its own time
  * step dt_p = courant * h_p.  Patches are independent (each
  * keeps its own ghosts); no data moves between patches.  Replaying one plan
  * on two streams at once races on its queues. */
 typedef struct chemora_plan chemora_plan;   /* opaque, library-owned */
 
 /* How the stage launches of plans are dispatched. */
-enum { CHEMORA_DISPATCH_PERSISTENT = 0, CHEMORA_DISPATCH_PER_TILE = 1 };
+enum { CHEMORA_DISPATCH_PERSISTENT = 0, CHEMORA_DISPATCH_PER_TILE = 1, CHEMORA_DISPATCH_AUTO = 2 };
 
 /* Sets the dispatch of plans created after this call, process-wide
- * (thread-safe): CHEMORA_DISPATCH_PERSISTENT (the default) or
- * CHEMORA_DISPATCH_PER_TILE (one work-group per tile, in the same XCD
- * order).  Existing plans keep theirs.  EINVAL for another value. */
+ * (thread-safe): CHEMORA_DISPATCH_PERSISTENT, CHEMORA_DISPATCH_PER_TILE (one
+ * work-group per tile, in the same XCD order) or CHEMORA_DISPATCH_AUTO (the
+ * default: each plan times an RK4 stage-2 pass of its patches both ways at
+ * creation -- overwriting the S_B and accumulator parts of their scratch
+ * before the ghosts are prepared -- and keeps the faster).  Existing plans
+ * keep theirs.  EINVAL for another value. */
 int chemora_set_plan_dispatch(int32_t mode);
 
-/* Dispatch of a plan (>= 0), or EINVAL for a NULL plan. */
+/* Dispatch a plan runs (CHEMORA_DISPATCH_PERSISTENT or _PER_TILE; never
+ * AUTO), or EINVAL for a NULL plan. */
 int chemora_plan_dispatch(const chemora_plan *plan);
 
 /* Creates a plan.  patches[p].u and scratch[p] (chemora_rk4_scratch_elems

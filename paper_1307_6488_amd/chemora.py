@@ -279,7 +279,7 @@ def chemora_hamiltonian(params: chemora_params, patch: chemora_patch, h_ptr: int
                                             _stream(stream)))
 
 
-DISPATCH_PERSISTENT, DISPATCH_PER_TILE = 0, 1
+DISPATCH_PERSISTENT, DISPATCH_PER_TILE, DISPATCH_AUTO = 0, 1, 2
 
 
 def chemora_set_plan_dispatch(mode: int) -> int:
@@ -424,11 +424,11 @@ class Batch:
     """Several device-resident patches advanced together through a plan."""
 
     def __init__(self, params, grids, states, courant: float = 0.0, device="cuda", tune_cache_path=None,
-                 integrator: str = "rk4", synced_dt: float = 0.0, dispatch: int = DISPATCH_PERSISTENT):
+                 integrator: str = "rk4", synced_dt: float = 0.0, dispatch: int = DISPATCH_AUTO):
         """Independent patches with dt = courant * h each, or (synced_dt > 0)
         one synchronised grid hierarchy stepped with synced_dt.  dispatch:
-        DISPATCH_PERSISTENT or DISPATCH_PER_TILE (the process-wide setting is
-        restored to persistent afterwards)."""
+        DISPATCH_AUTO, DISPATCH_PERSISTENT or DISPATCH_PER_TILE (the
+        process-wide setting is restored to AUTO afterwards)."""
         import torch
         if integrator not in ("rk4", "rk3"):
             raise ValueError(f"integrator {integrator!r} is neither 'rk4' nor 'rk3'")
@@ -447,7 +447,7 @@ class Batch:
                                                 tune_cache_path, torch.cuda.current_stream(),
                                                 rk3=integrator == "rk3")
         finally:
-            chemora_set_plan_dispatch(DISPATCH_PERSISTENT)
+            chemora_set_plan_dispatch(DISPATCH_AUTO)
 
     def dispatch(self) -> int:
         return chemora_plan_dispatch(self.plan)

@@ -730,7 +730,7 @@ int persistent_grid(const chemora_params* P, int v, int ntiles) {
 }
 
 // how plans created from now on launch their stage kernels
-std::atomic<int> g_plan_dispatch{CHEMORA_DISPATCH_PERSISTENT};
+std::atomic<int> g_plan_dispatch{CHEMORA_DISPATCH_AUTO};
 
 // ---------------------------------------------------------------------------
 // tile variants: the per-class choice and its cache
@@ -1566,7 +1566,10 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
                 double dt_all = 0.0) {
   const int nst = rk3 ? 3 : 4;
   const bool synced = dt_all > 0.0;
-  const int dispatch = g_plan_dispatch.load();
+  int dispatch = g_plan_dispatch.load();
+  // the variant timing passes below run one work-group per tile when the
+  // dispatch is still to be chosen
+  const int pass_dispatch = dispatch == CHEMORA_DISPATCH_AUTO ? CHEMORA_DISPATCH_PER_TILE : dispatch;
   if (!out) return fail(CHEMORA_EINVAL, "out is NULL");
   *out = nullptr;
   if (!patches || !scratch) return fail(CHEMORA_EINVAL, "patches or scratch is NULL");
@@ -1635,12 +1638,12 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
     for (int p = 1; p < npatch; ++p) mixed |= var[p] != var[0];
     if (mixed && params->precision == CHEMORA_PREC_FP64) {
       float best = 0.0f;
-      if ((rc = plan_pass_ms(params, patches, scratch, npatch, var, dispatch, s, &best))) return rc;
+      if ((rc = plan_pass_ms(params, patches, scratch, npatch, var, pass_dispatch, s, &best))) return rc;
       for (int v = 0; v < chemora::NVARIANT; ++v) {
         if (!chemora::variant_supported(params->fd_order, v)) continue;
         const std::vector<int> uni(npatch, v);
         float ms = 0.0f;
-        if ((rc = plan_pass_ms(params, patches, scratch, npatch, uni, dispatch, s, &ms))) return rc;
+        if ((rc = plan_pass_ms(params, patches, scratch, npatch, uni, pass_dispatch, s, &ms))) return rc;
         if (ms < best) {
           best = ms;
           var = uni;
@@ -1649,6 +1652,17 @@ int plan_create(const chemora_params* params, const chemora_patch* patches, doub
     }
   } else {
     for (int p = 0; p < npatch; ++p) var[p] = choose_variant(params, &patches[p]);
+  }
+
+  // AUTO: time the stage-2 pass of the final assignment both ways and keep
+  // the faster (they compute the same bits)
+  if (dispatch == CHEMORA_DISPATCH_AUTO) {
+    float persistent_ms = 0.0f, per_tile_ms = 0.0f;
+    if ((rc = plan_pass_ms(params, patches, scratch, npatch, var, CHEMORA_DISPATCH_PERSISTENT, s, &persistent_ms)))
+      return rc;
+    if ((rc = plan_pass_ms(params, patches, scratch, npatch, var, CHEMORA_DISPATCH_PER_TILE, s, &per_tile_ms)))
+      return rc;
+    dispatch = persistent_ms < per_tile_ms ? CHEMORA_DISPATCH_PERSISTENT : CHEMORA_DISPATCH_PER_TILE;
   }
 
   chemora_plan* pl = new (std::nothrow) chemora_plan;
@@ -1848,7 +1862,7 @@ int chemora_plan_create_synced(const chemora_params* params, const chemora_patch
 
 int chemora_set_plan_dispatch(int32_t mode) {
   g_error.clear();
-  if (mode != CHEMORA_DISPATCH_PERSISTENT && mode != CHEMORA_DISPATCH_PER_TILE)
+  if (mode != CHEMORA_DISPATCH_PERSISTENT && mode != CHEMORA_DISPATCH_PER_TILE && mode != CHEMORA_DISPATCH_AUTO)
     return fail(CHEMORA_EINVAL, "unknown plan dispatch mode %d", mode);
   g_plan_dispatch.store(mode);
   return CHEMORA_OK;

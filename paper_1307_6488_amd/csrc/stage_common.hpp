@@ -150,11 +150,18 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
 // waterfall loop.  Broadcasting lane 0 puts them in scalar registers.
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// The plan tables are written by the host only, so they are read through
+// the constant address space: the compiler may then use scalar loads even
+// after the kernel's own stores (the persistent form's tile loop).
+typedef const __attribute__((address_space(4))) int* const_int_ptr;
+__device__ __forceinline__ int table_load(const int* p, int i) { return ((const_int_ptr)p)[i]; }
+
 __device__ __forceinline__ StageArgs uniform_args(const StageArgs* p) {
   constexpr int N = (int)(sizeof(StageArgs) / 4);
   static_assert(sizeof(StageArgs) % 4 == 0, "StageArgs is a whole number of words");
   int w[N];
-  __builtin_memcpy(w, p, sizeof(StageArgs));
+#pragma unroll
+  for (int i = 0; i < N; ++i) w[i] = table_load((const int*)p, i);
 #pragma unroll
   for (int i = 0; i < N; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
   StageArgs a;
@@ -185,7 +192,7 @@ __device__ __forceinline__ int batch_patch(const BatchTable& bt, int t) {
   int lo = 0, hi = bt.npatch - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (uniform(bt.tile_start[mid]) <= t) lo = mid; else hi = mid - 1;
+    if (uniform(table_load(bt.tile_start, mid)) <= t) lo = mid; else hi = mid - 1;
   }
   return lo;
 }

@@ -595,7 +595,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
 #ifndef CHEMORA_PIPE_MIXED
 #define CHEMORA_PIPE_MIXED 1
 #endif
-  constexpr bool PIPE = MIXED_GROUP && CHEMORA_PIPE_MIXED;
+  constexpr bool PIPE = MIXED_GROUP && CHEMORA_PIPE_MIXED && !AXIS_GROUPS;
 
   // Advection and dissipation of the staged GF, one axis at a time: its
   // right-hand side is (algebra + advection) + dissipation.  ad_step adds
@@ -1246,16 +1246,24 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
 #pragma unroll
   for (int i = 0; i < NB; ++i) bufs[i] = all[i];
   constexpr bool BOUND = ORDER >= 8 || OCC >= 2;
-  // order 8 at two waves per SIMD reads its axis taps axis by axis (256
-  // registers per lane)
-  constexpr bool AXIS_GROUPS = ORDER >= 8 && OCC >= 2;
+  // order 8 at two waves per SIMD and split precision at three read their
+  // axis taps axis by axis (256 and 168 registers per lane)
+#ifndef CHEMORA_SPLIT_AXIS_GROUPS
+#define CHEMORA_SPLIT_AXIS_GROUPS 1
+#endif
+#ifndef CHEMORA_O4_AXIS_GROUPS
+#define CHEMORA_O4_AXIS_GROUPS 0
+#endif
+  constexpr bool AXIS_GROUPS = (ORDER >= 8 && OCC >= 2) ||
+                               (CHEMORA_SPLIT_AXIS_GROUPS && std::is_same<T, float>::value && OCC >= 3) ||
+                               (CHEMORA_O4_AXIS_GROUPS && ORDER == 4);
   if constexpr (!PERSIST) {
     int t = xcd_tile(blockIdx.x, gridDim.x);
     StageArgs a = a1;
     if (bt.ntiles > 0) {
       const int p = batch_patch(bt, t);
       a = uniform_args(bt.args + p);
-      t -= uniform(bt.tile_start[p]);
+      t -= uniform(table_load(bt.tile_start, p));
     }
     stage_tile<ORDER, UPWIND, R, NB, BOUND, OFFS_LDS, PARK, SH, T, KOQ, AXIS_GROUPS>(a, t, bufs, offs, park);
   } else {
@@ -1274,7 +1282,7 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
       if (t < 0) break;
       const int p = batch_patch(bt, t);
       const StageArgs a = uniform_args(bt.args + p);
-      stage_tile<ORDER, UPWIND, R, NB, BOUND, OFFS_LDS, PARK, SH, T, KOQ, AXIS_GROUPS>(a, t - uniform(bt.tile_start[p]), bufs,
+      stage_tile<ORDER, UPWIND, R, NB, BOUND, OFFS_LDS, PARK, SH, T, KOQ, AXIS_GROUPS>(a, t - uniform(table_load(bt.tile_start, p)), bufs,
                                                                           offs, park);
     }
     // the last work-group to finish leaves the counters zeroed for the next

@@ -34,11 +34,12 @@ def test_library_exports_every_declared_symbol():
 
 def test_plan_dispatch_mode_checks():
     L = C.lib()
-    assert L.chemora_set_plan_dispatch(2) == C.EINVAL
+    assert L.chemora_set_plan_dispatch(3) == C.EINVAL
     assert L.chemora_set_plan_dispatch(-1) == C.EINVAL
     assert L.chemora_plan_dispatch(None) == C.EINVAL
     assert L.chemora_set_plan_dispatch(C.DISPATCH_PER_TILE) == C.OK
     assert L.chemora_set_plan_dispatch(C.DISPATCH_PERSISTENT) == C.OK
+    assert L.chemora_set_plan_dispatch(C.DISPATCH_AUTO) == C.OK
 
 
 def test_required_ghost_matches_inputs():
