@@ -211,6 +211,57 @@ struct LdsLayout {
   }
 };
 
+// Cross layout (one-plane tiles): what the axis stencils of a grid function
+// without mixed derivatives read.  Plane dz = 0 as in the full layout (rows
+// [-R, TY-1+R], pitch P), padded to whole chunks (the padding is staged with
+// the full layout's points, never read), then the 2R planes dz = +1, -1, +2,
+// -2, ... holding only the tile's own TX x TY points (pitch TX).  x and y
+// taps sit at the full layout's offsets from the full anchor; z taps at
+// zoff(dz) from the column anchor Z0 + yr TX + xr.
+template <int R, int RM, class SH>
+struct CrossLayout {
+  using F = LdsLayout<R, RM, SH, 1>;
+  static constexpr int TX = SH::TX, TY = SH::TY;
+  static constexpr int CHUNK = F::CHUNK;
+  static constexpr int NCHUNK0 = (F::psize(0) + CHUNK - 1) / CHUNK;   // chunks of plane 0
+  static constexpr int Z0 = NCHUNK0 * CHUNK;
+  static constexpr int CPP = TX * TY / CHUNK;                          // chunks per column plane
+  static constexpr int SIZE = Z0 + 2 * R * TX * TY;
+  static constexpr int NCHUNK = SIZE / CHUNK;
+  static_assert(TX * TY % CHUNK == 0 && SH::WPG % CPP == 0, "a wave's column chunks share one place in their plane");
+  static_assert(SIZE <= F::SIZEP, "the cross layout fits the full layout's buffer");
+  __host__ __device__ static constexpr int zplane(int dz) { return dz > 0 ? 2 * (dz - 1) : 2 * (-dz) - 1; }
+  __host__ __device__ static constexpr int col_anchor(int xr, int yr) { return Z0 + yr * TX + xr; }
+  __host__ __device__ static constexpr int zoff(int dz) { return zplane(dz) * TX * TY; }
+  // the tile-relative point stored at LDS double idx
+  __host__ __device__ static constexpr void decode(int idx, int& x, int& y, int& dz) {
+    if (idx < Z0) {
+      F::decode(idx, x, y, dz);
+      return;
+    }
+    const int r = idx - Z0, j = r / (TX * TY), e = r - j * TX * TY;
+    dz = (j & 1) ? -(j / 2 + 1) : j / 2 + 1;
+    y = e / TX;
+    x = e - y * TX;
+  }
+  // the point a staging lane loads for LDS double idx, clamped as in the
+  // full layout
+  __host__ __device__ static constexpr void stage_point(int idx, int i0, int j0, int k0, int nx, int ny, int nz,
+                                                        int& x, int& y, int& dz) {
+    if (idx < Z0) {
+      F::stage_point(idx, i0, j0, k0, nx, ny, nz, x, y, dz);
+      return;
+    }
+    decode(idx, x, y, dz);
+    const int xmax = nx - 1 + R - i0, ymax = ny - 1 + R - j0, zmax = nz - 1 + R - k0;
+    y = y < ymax ? y : ymax;
+    dz = dz < zmax ? dz : zmax;
+    // column pairs start at even x, so a pair starting at xmax would leave
+    // the row; no valid work-item reads a column element past nx - 1 - i0
+    if (x >= xmax) x = xmax - 1;
+  }
+};
+
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 // a staged grid function's advection and dissipation terms; its right-hand
@@ -338,6 +389,47 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       if (L::CPW * SH::WPG != L::NCHUNK && c >= L::NCHUNK) break;   // wave-uniform
       const unsigned vo = OFFS_LDS ? offs[q * SH::NT + wave * 64 + lane] : voff[q];
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr_t)(dst + c * L::CHUNK), 16, vo, so, 0, 0);
+    }
+  };
+  // CROSS (order 8, one buffer): the 13 grid functions without mixed
+  // derivatives (phases 11-23: Gt, K, At, B) stage only the cross of
+  // CrossLayout, less than half the full neighbourhood.  Its plane-0 chunks
+  // are the full layout's; a column chunk holds CHUNK points of one plane
+  // z = k + dz, and all of a wave's column chunks sit at the same place in
+  // their planes, so one per-lane offset serves them, the plane entering
+  // through the scalar offset.
+  constexpr bool CROSS = AXIS_GROUPS && NB == 1 && ORDER == 8 && SH::TZ == 1;
+  using LC = std::conditional_t<CROSS, CrossLayout<R, RM, SH>, L>;
+  auto issue_cross = [&](int f, double* dst) __attribute__((always_inline)) {
+    if constexpr (CROSS) {
+      const unsigned so = tile_base + f * sf * 8u;
+#pragma unroll
+      for (int q = 0; q < L::CPW; ++q) {
+        const int c = wave + SH::WPG * q;
+        if (c >= LC::NCHUNK0) break;   // wave-uniform
+        const unsigned vo = OFFS_LDS ? offs[q * SH::NT + wave * 64 + lane] : voff[q];
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr_t)(dst + c * L::CHUNK), 16, vo, so, 0, 0);
+      }
+      const int pos = ((wave - LC::NCHUNK0) % LC::CPP + LC::CPP) % LC::CPP;
+      const int e = pos * LC::CHUNK + 2 * lane;
+      int y = e / SH::TX, x = e - y * SH::TX;
+      const int xmax = G.nx - 1 + R - i0, ymax = G.ny - 1 + R - j0, zmax = G.nz - 1 + R - k0;
+      y = y < ymax ? y : ymax;
+      if (x >= xmax) x = xmax - 1;
+      // the plane offset (dz + R) sz >= 0 goes to the scalar part, the rest
+      // of the full layout's bias to the lane's part
+      const unsigned vo = (unsigned)(y * (int)sy + x + R * ((int)sy + 1)) * 8u;
+#pragma unroll
+      for (int q = 0; q < (LC::NCHUNK + SH::WPG - 1) / SH::WPG; ++q) {
+        const int c = wave + SH::WPG * q;
+        if (c < LC::NCHUNK0) continue;
+        if (c >= LC::NCHUNK) break;   // wave-uniform
+        const int j = (c - LC::NCHUNK0) / LC::CPP;
+        int dz = (j & 1) ? -(j / 2 + 1) : j / 2 + 1;
+        dz = dz < zmax ? dz : zmax;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr_t)(dst + c * L::CHUNK), 16, vo,
+                                                 so + (unsigned)(dz + R) * sz * 8u, 0, 0);
+      }
     }
   };
 
@@ -672,7 +764,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // axis' stencils formed from them before the next axis is read (fewer
   // live registers, the same arithmetic in the same order).  The result's
   // t is the phase's LDS view for the mixed derivatives.
-  auto stencils = [&](auto tag, const Taps& t0, auto d1, auto d2) __attribute__((always_inline)) {
+  // cross: the buffer holds the CrossLayout (CROSS phases): z taps at the
+  // column anchor
+  auto stencils = [&](auto tag, const Taps& t0, auto d1, auto d2, auto cross) __attribute__((always_inline)) {
+    constexpr bool XC = decltype(cross)::value;
+    // dependent on the call, so that only cross calls name CrossLayout's members
+    using LX = std::conditional_t<XC, LC, CrossLayout<R, RM, Shape<32, 4, 1>>>;
     using TC = decltype(tag);
     constexpr bool W1 = !std::is_same<decltype(d1), std::nullptr_t>::value;
     constexpr bool W2 = !std::is_same<decltype(d2), std::nullptr_t>::value;
@@ -684,6 +781,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     } out;
     out.src.t = t0;
     if constexpr (!AXIS_GROUPS) {
+      static_assert(!XC, "the cross layout is read axis by axis");
       const auto src = phase_src(t0);
       if constexpr (W1 && W2)
         D12all(tag, src, *d1, *d2);
@@ -696,13 +794,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       for (int ax = 0; ax < 3; ++ax) {
         const Taps tap = t0.fresh();
         double c = tap(0, 0, 0), v[2 * R];
+        if constexpr (XC) {
+          if (ax == 2) {
+            int az = LX::col_anchor(xr, yr);
+            asm volatile("" : "+v"(az));
 #pragma unroll
-        for (int o = 1; o <= R; ++o) {
-          int d[3] = {0, 0, 0};
-          d[ax] = -o;
-          v[R - o] = tap(d[0], d[1], d[2]);
-          d[ax] = o;
-          v[R + o - 1] = tap(d[0], d[1], d[2]);
+            for (int o = 1; o <= R; ++o) {
+              v[R - o] = t0.cur[az + LX::zoff(-o)];
+              v[R + o - 1] = t0.cur[az + LX::zoff(o)];
+            }
+          }
+        }
+        if (!XC || ax != 2) {
+#pragma unroll
+          for (int o = 1; o <= R; ++o) {
+            int d[3] = {0, 0, 0};
+            d[ax] = -o;
+            v[R - o] = tap(d[0], d[1], d[2]);
+            d[ax] = o;
+            v[R + o - 1] = tap(d[0], d[1], d[2]);
+          }
         }
         keep(c);
         keep(v);
@@ -773,7 +884,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   auto begin = [&](int p) __attribute__((always_inline)) {
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (NB == 1) {
-      issue(seq_gf(p), bufs[0]);
+      if (CROSS && p >= 11)
+        issue_cross(seq_gf(p), bufs[0]);
+      else
+        issue(seq_gf(p), bufs[0]);
       wait_vm<0>();
       lds_barrier();
     } else {
@@ -828,7 +942,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     // the axis stencils first, so that register-held axis taps die before
     // the mixed derivatives read theirs
     T d2p[3];
-    const auto ps = stencils(T(), make_ops(bufs[c % NB]), &db[c], &d2p);
+    const auto ps = stencils(T(), make_ops(bufs[c % NB]), &db[c], &d2p, std::false_type());
     const auto& src = ps.src;
     const auto& ad = ps.ad;
     T mx[6];
@@ -877,7 +991,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       const T As = T(val(gAT + s));
       begin(p);
       T d2p[3];
-      const auto ps = stencils(T(), make_ops(bufs[p % NB]), &dg[s], &d2p);
+      const auto ps = stencils(T(), make_ops(bufs[p % NB]), &dg[s], &d2p, std::false_type());
       const auto& src = ps.src;
       const auto& ad = ps.ad;
       T r = T(0.0);
@@ -959,7 +1073,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       ChiPart out;
       TC dc[3];
       TC d2p[3];
-      const auto ps = stencils(tag, tap, &dc, &d2p);
+      const auto ps = stencils(tag, tap, &dc, &d2p, std::false_type());
       const auto& src = ps.src;
       const auto& ad = ps.ad;
       TC cdd[6], mx[6];
@@ -1022,7 +1136,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const Epi e = epi_load(gALPHA);
     begin(10);
     T d2p[3];
-    const auto ps = stencils(T(), make_ops(bufs[10 % NB]), &da, &d2p);
+    const auto ps = stencils(T(), make_ops(bufs[10 % NB]), &da, &d2p, std::false_type());
     const auto& src = ps.src;
     const auto& ad = ps.ad;
     T mx[6];
@@ -1087,7 +1201,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const int p = 11 + c;
     begin(p);
     T dx[3];
-    const auto ps = stencils(T(), make_ops(bufs[p % NB]), &dx, nullptr);
+    const auto ps = stencils(T(), make_ops(bufs[p % NB]), &dx, nullptr, std::bool_constant<CROSS>());
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const T d = dx[ax];
@@ -1134,7 +1248,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const Epi ex[3] = {epi_load(gXT), epi_load(gXT + 1), epi_load(gXT + 2)};
     begin(14);
     T dK[3];
-    const auto ps = stencils(T(), make_ops(bufs[14 % NB]), &dK, nullptr);
+    const auto ps = stencils(T(), make_ops(bufs[14 % NB]), &dK, nullptr, std::bool_constant<CROSS>());
     emit(gK, ps.ad.rhs(-chi * trDDa + alpha * (AA + K * K * (T(1.0) / T(3.0)))), e);
     if constexpr (PARK) {
 #pragma unroll
@@ -1167,7 +1281,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const int p = 15 + s;
     const Epi e = epi_load(gAT + s);
     begin(p);
-    const auto ps = stencils(T(), make_ops(bufs[p % NB]), nullptr, nullptr);
+    const auto ps = stencils(T(), make_ops(bufs[p % NB]), nullptr, nullptr, std::bool_constant<CROSS>());
     const int i = SI(s), jj = SJ(s);
     T la = T(0.0), aa = T(0.0);
 #pragma unroll
@@ -1191,7 +1305,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       const Epi e = epi_load(gB + c);
       const T Bc = T(val(gB + c));
       begin(p);
-      const auto ps = stencils(T(), make_ops(bufs[p % NB]), nullptr, nullptr);
+      const auto ps = stencils(T(), make_ops(bufs[p % NB]), nullptr, nullptr, std::bool_constant<CROSS>());
       emit(gB + c, ps.ad.rhs(xsrc[c] - gauge.eta * Bc), e);
       sync(p);
     }

@@ -2,7 +2,8 @@
 // compiled for the host): off() and decode() are inverse on every tap a
 // work-item reads, every tap lies inside the staged buffer, and the clamped
 // staging offsets of every tile of ragged patches stay inside the patch's
-// stored box with each staged pair of doubles inside one row.  Built and run
+// stored box with each staged pair of doubles inside one row; the same for the
+// cross layout of order 8 with one buffer.  Built and run
 // by tests/test_layout_host.py; exit status 0 when no violation is found.
 #include <cstdio>
 #include <cstdlib>
@@ -67,6 +68,77 @@ int check(int nx, int ny, int nz, int g) {
   return bad;
 }
 
+// The cross layout (order 8 with one staging buffer, grid functions without
+// mixed derivatives): every axis tap decodes back to its point inside the
+// buffer (x and y taps at the full anchor, z taps at the column anchor);
+// every staged element's clamped point lies inside the stored box with its
+// pair in one row; the stage kernel's own column formula (one per-lane place
+// per wave, the plane in the scalar offset) loads the same clamped points;
+// and on small patches every tap of every valid work-item reads an element
+// loaded unclamped.
+template <int R, int RM, class SH>
+int check_cross(int nx, int ny, int nz, int g) {
+  using F = LdsLayout<R, RM, SH, 1>;
+  using LC = CrossLayout<R, RM, SH>;
+  int bad = 0;
+  auto taps = [&](int xr, int yr, auto&& tap) {
+    for (int d = -R; d <= R; ++d) {
+      tap(F::anchor(xr, yr, 0) + F::off(d, 0, 0), d, 0, 0);
+      tap(F::anchor(xr, yr, 0) + F::off(0, d, 0), 0, d, 0);
+      if (d != 0) tap(LC::col_anchor(xr, yr) + LC::zoff(d), 0, 0, d);
+    }
+  };
+  for (int yr = 0; yr < SH::TY; ++yr)
+    for (int xr = 0; xr < SH::TX; ++xr)
+      taps(xr, yr, [&](int idx, int dx, int dy, int dz) {
+        if (idx < 0 || idx >= LC::SIZE) { ++bad; return; }
+        int x, y, z;
+        LC::decode(idx, x, y, z);
+        if (x != xr + dx || y != yr + dy || z != dz) ++bad;
+      });
+  const long sy = nx + 2 * g + (nx & 1);
+  const int tx = (nx + SH::TX - 1) / SH::TX, ty = (ny + SH::TY - 1) / SH::TY;
+  const bool small = (long)nx * ny * nz <= 40000;
+  for (int kb = 0; kb < nz; ++kb)
+    for (int tyi = 0; tyi < ty; ++tyi)
+      for (int txi = 0; txi < tx; ++txi) {
+        const int i0 = txi * SH::TX, j0 = tyi * SH::TY, k0 = kb;
+        for (int c = 0; c < LC::NCHUNK; ++c)
+          for (int lane = 0; lane < 64; ++lane) {
+            int x, y, dz;
+            LC::stage_point(c * LC::CHUNK + 2 * lane, i0, j0, k0, nx, ny, nz, x, y, dz);
+            const long gi = i0 + x + g, gj = j0 + y + g, gk = k0 + dz + g;
+            if (gi < 0 || gi + 1 >= sy || gj < 0 || gj >= ny + 2 * g || gk < 0 || gk >= nz + 2 * g) ++bad;
+            if (c < LC::NCHUNK0) continue;
+            // the kernel's formula for a column chunk of wave c % WPG
+            const int wave = c % SH::WPG;
+            const int pos = ((wave - LC::NCHUNK0) % LC::CPP + LC::CPP) % LC::CPP;
+            const int e = pos * LC::CHUNK + 2 * lane;
+            int ky = e / SH::TX, kx = e - ky * SH::TX;
+            const int xmax = nx - 1 + R - i0, ymax = ny - 1 + R - j0, zmax = nz - 1 + R - k0;
+            ky = ky < ymax ? ky : ymax;
+            if (kx >= xmax) kx = xmax - 1;
+            const int j = (c - LC::NCHUNK0) / LC::CPP;
+            int kz = (j & 1) ? -(j / 2 + 1) : j / 2 + 1;
+            kz = kz < zmax ? kz : zmax;
+            if (kx != x || ky != y || kz != dz || kz + R < 0) ++bad;
+          }
+        if (!small) continue;
+        for (int yr = 0; yr < SH::TY; ++yr)
+          for (int xr = 0; xr < SH::TX; ++xr) {
+            if (i0 + xr >= nx || j0 + yr >= ny) continue;
+            taps(xr, yr, [&](int idx, int, int, int) {
+              const int pair = idx & ~1;
+              int x, y, z, ux, uy, uz;
+              LC::stage_point(pair, i0, j0, k0, nx, ny, nz, x, y, z);
+              LC::decode(pair, ux, uy, uz);
+              if (x != ux || y != uy || z != uz) ++bad;
+            });
+          }
+      }
+  return bad;
+}
+
 int main() {
   int bad = 0;
   const int shapes[][4] = {{70, 37, 19, 3}, {33, 9, 7, 3}, {128, 128, 128, 3}, {1, 1, 1, 3}, {65, 1, 2, 3},
@@ -84,6 +156,9 @@ int main() {
     bad += check<5, 4, Shape<32, 4, 1>>(s[0], s[1], s[2], g8);
     bad += check<5, 4, Shape<64, 4, 1>>(s[0], s[1], s[2], g8);
     bad += check<4, 4, Shape<32, 4, 1>>(s[0], s[1], s[2], g8);
+    bad += check_cross<5, 4, Shape<32, 4, 1>>(s[0], s[1], s[2], g8);
+    bad += check_cross<5, 4, Shape<64, 4, 1>>(s[0], s[1], s[2], g8);
+    bad += check_cross<4, 4, Shape<32, 4, 1>>(s[0], s[1], s[2], g8);
   }
   printf("layout check: %d violations\n", bad);
   return bad != 0;
