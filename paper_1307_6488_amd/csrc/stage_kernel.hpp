@@ -881,21 +881,38 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // and meets the barrier before computing, and meets another at its end so
   // that no wave overwrites the buffer while another still reads it; the
   // other work-groups on the CU compute in the meantime.
+  // With CROSS the cross phases 11.. are double-buffered inside the one
+  // buffer (two cross neighbourhoods fit it): phase p >= 11 reads half p & 1,
+  // and the grid function of phase p + 1 is issued into the other half at the
+  // start of phase p, once every wave has left phase p - 1.
+  static_assert(!CROSS || 2 * LC::SIZE <= L::SIZEP, "two cross neighbourhoods fit one buffer");
+  auto cross_half = [&](int p) __attribute__((always_inline)) { return bufs[0] + (p & 1) * LC::SIZE; };
+  auto buf_of = [&](int p) __attribute__((always_inline)) {
+    return (CROSS && p >= 11) ? cross_half(p) : bufs[p % NB];
+  };
   auto begin = [&](int p) __attribute__((always_inline)) {
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (NB == 1) {
-      if (CROSS && p >= 11)
-        issue_cross(seq_gf(p), bufs[0]);
-      else
+      if (CROSS && p >= 11) {
+        if (p == 11) {   // the first cross phase: nothing staged ahead yet
+          issue_cross(seq_gf(p), cross_half(p));
+          wait_vm<0>();
+          lds_barrier();
+        }
+        if (p + 1 < nphase) issue_cross(seq_gf(p + 1), cross_half(p + 1));
+      } else {
         issue(seq_gf(p), bufs[0]);
-      wait_vm<0>();
-      lds_barrier();
+        wait_vm<0>();
+        lds_barrier();
+      }
     } else {
       if (p + NB - 1 < nphase) issue(seq_gf(p + NB - 1), bufs[(p + NB - 1) % NB]);
     }
   };
   auto sync = [&](int p) __attribute__((always_inline)) {
     if constexpr (NB == 1) {
+      // a cross phase waits for the next phase's staging (and its own stores)
+      if (CROSS && p >= 11) wait_vm<0>();
       if (p >= 0) lds_barrier();
     } else {
       wait_staged<NB, L::CMIN>(min(p + NB - 1, nphase - 1) - (p + 1));
@@ -1201,7 +1218,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const int p = 11 + c;
     begin(p);
     T dx[3];
-    const auto ps = stencils(T(), make_ops(bufs[p % NB]), &dx, nullptr, std::bool_constant<CROSS>());
+    const auto ps = stencils(T(), make_ops(buf_of(p)), &dx, nullptr, std::bool_constant<CROSS>());
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const T d = dx[ax];
@@ -1248,7 +1265,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const Epi ex[3] = {epi_load(gXT), epi_load(gXT + 1), epi_load(gXT + 2)};
     begin(14);
     T dK[3];
-    const auto ps = stencils(T(), make_ops(bufs[14 % NB]), &dK, nullptr, std::bool_constant<CROSS>());
+    const auto ps = stencils(T(), make_ops(buf_of(14)), &dK, nullptr, std::bool_constant<CROSS>());
     emit(gK, ps.ad.rhs(-chi * trDDa + alpha * (AA + K * K * (T(1.0) / T(3.0)))), e);
     if constexpr (PARK) {
 #pragma unroll
@@ -1281,7 +1298,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const int p = 15 + s;
     const Epi e = epi_load(gAT + s);
     begin(p);
-    const auto ps = stencils(T(), make_ops(bufs[p % NB]), nullptr, nullptr, std::bool_constant<CROSS>());
+    const auto ps = stencils(T(), make_ops(buf_of(p)), nullptr, nullptr, std::bool_constant<CROSS>());
     const int i = SI(s), jj = SJ(s);
     T la = T(0.0), aa = T(0.0);
 #pragma unroll
@@ -1305,7 +1322,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       const Epi e = epi_load(gB + c);
       const T Bc = T(val(gB + c));
       begin(p);
-      const auto ps = stencils(T(), make_ops(bufs[p % NB]), nullptr, nullptr, std::bool_constant<CROSS>());
+      const auto ps = stencils(T(), make_ops(buf_of(p)), nullptr, nullptr, std::bool_constant<CROSS>());
       emit(gB + c, ps.ad.rhs(xsrc[c] - gauge.eta * Bc), e);
       sync(p);
     }
