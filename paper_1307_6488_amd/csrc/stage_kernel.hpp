@@ -264,6 +264,15 @@ struct CrossLayout {
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
+// the double v of lane src mod 64 of the wave (every lane active)
+__device__ __forceinline__ double lane_read(double v, int src) {
+  const int a = (src & 63) << 2;
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(a, (int)(unsigned)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(a, (int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // a staged grid function's advection and dissipation terms; its right-hand
 // side is (algebra + advection) + dissipation, or algebra + (advection and
 // dissipation summed together) where MERGED
@@ -478,6 +487,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // reads the inner stencils at +-oa together, 16 taps per group (measured
   // against 8, 32 and all 64 per group).
   constexpr bool MIXED_GROUP = ORDER == 4;
+  // Order 8: the mixed derivatives whose outer direction is x (xy, xz) take
+  // their inner stencils from the neighbouring lanes (16 taps and 16 lane
+  // reads each instead of 64 taps)
+#ifndef CHEMORA_MIXED_SHUFFLE
+#define CHEMORA_MIXED_SHUFFLE 1
+#endif
+  constexpr bool XSHUF = CHEMORA_MIXED_SHUFFLE && ORDER == 8 && SH::TZ == 1;
   struct Axes {
     Taps t;                  // the mixed derivatives read from LDS
     double c;
@@ -583,7 +599,41 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     };
     auto idx = [](int o) { return o < 0 ? o + M : o + M - 1; };
     TC v;
-    if constexpr (MIXED_GROUP) {
+    if (XSHUF && ai == 0) {
+      // outer direction x: the inner stencil at column x + oa is the one the
+      // work-item oa columns away evaluates at its own column -- the same
+      // taps and arithmetic, so the same bits -- read across lanes.  The
+      // lane rotation (lane + oa) mod 64 carries rows past the tile's x
+      // edges to the first / last M lanes of a row, which hold the halo
+      // columns' inner stencils (hal) for the row that reads them there:
+      // with two rows per wave the other row, with one row its own.
+      auto inner = [&](const Taps& tt) __attribute__((always_inline)) {
+        return St::first([&](int ob) __attribute__((always_inline)) {
+          int d[3] = {0, 0, 0};
+          d[bj] = ob;
+          return tt(d[0], d[1], d[2]);
+        });
+      };
+      // the first M lanes of a row hold columns TX.., the last M columns -M..
+      const bool first = xr < M, last = xr >= SH::TX - M;
+      Taps th = tap.fresh();
+      th.anc += (first ? SH::TX : (last ? -SH::TX : 0)) +
+                (SH::RPW == 2 && (first || last) ? (lane < 32 ? L::P : -L::P) : 0);
+      double own = inner(tap);
+      double hal = inner(th);
+      bound(own);
+      bound(hal);
+      // each lane offers hal where the lanes oa away read a halo column
+      // through it, else own
+      auto outer = [&](int oa) __attribute__((always_inline)) {
+        const bool offer_hal = oa > 0 ? xr < oa : xr >= SH::TX + oa;
+        return lane_read(offer_hal ? hal : own, lane + oa);
+      };
+      if constexpr (F32)
+        v = St::first_f(outer) * float(a.sc.d11);
+      else
+        v = St::first(outer) * a.sc.d11;
+    } else if constexpr (MIXED_GROUP) {
       // the 4M^2 taps in one group
       double m[2 * M][2 * M];
 #pragma unroll
