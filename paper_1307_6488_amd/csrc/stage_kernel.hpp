@@ -493,7 +493,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
 #ifndef CHEMORA_MIXED_SHUFFLE
 #define CHEMORA_MIXED_SHUFFLE 1
 #endif
-  constexpr bool XSHUF = CHEMORA_MIXED_SHUFFLE && ORDER == 8 && SH::TZ == 1;
+  constexpr bool XSHUF = CHEMORA_MIXED_SHUFFLE && ORDER == 8 && SH::TZ == 1 && AXIS_GROUPS;
   struct Axes {
     Taps t;                  // the mixed derivatives read from LDS
     double c;
@@ -619,7 +619,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       Taps th = tap.fresh();
       th.anc += (first ? SH::TX : (last ? -SH::TX : 0)) +
                 (SH::RPW == 2 && (first || last) ? (lane < 32 ? L::P : -L::P) : 0);
-      double own = inner(tap);
+      // the lane's own inner stencil is the unscaled first derivative
+      // along bj that the phase's axis stencils kept (src.fu)
+      double own = src.fu[bj];
       double hal = inner(th);
       bound(own);
       bound(hal);
@@ -826,6 +828,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     struct Out {
       struct {
         Taps t;
+        double fu[3];   // XSHUF: the unscaled first derivatives (with d1)
       } src;
       decltype(advdiss(tag, std::declval<Axes>())) ad;
     } out;
@@ -872,7 +875,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
           decltype(along)& f;
           __device__ __forceinline__ double operator()(int, int o) const { return f(o); }
         } one{along};
-        if constexpr (W1) (*d1)[ax] = D1(tag, one, ax);
+        if constexpr (W1 && XSHUF) {
+          // D1 as D1() forms it, its unscaled stencil kept for the mixed
+          // derivatives with outer direction x
+          out.src.fu[ax] = St::first(along);
+          (*d1)[ax] = out.src.fu[ax] * a.sc.d1;
+          abound((*d1)[ax]);
+        } else if constexpr (W1) {
+          (*d1)[ax] = D1(tag, one, ax);
+        }
         if constexpr (W2) (*d2)[ax] = D2d(tag, one, ax);
         ad_step(tag, along, ax, st);
         if constexpr (W1) bound((*d1)[ax]);
