@@ -390,12 +390,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     if (OFFS_LDS) offs[q * SH::NT + wave * 64 + lane] = voff[q];
   }
   const unsigned tile_base = ((k0 + gg) * sz + (j0 + gg) * sy + i0 + gg + XB) * 8u - bias * 8u;
+  // whether chunk wave + WPG q exists: with q a compile-time constant the
+  // wave-uniform test remains only for the last q, so that the loads before
+  // it are unconditional and their offsets are read from LDS together
+  // rather than with one wait per load
+  auto chunk_exists = [&](int q) __attribute__((always_inline)) {
+    return SH::WPG * (q + 1) <= L::NCHUNK ? true : wave + SH::WPG * q < L::NCHUNK;
+  };
   auto issue = [&](int f, double* dst) __attribute__((always_inline)) {
     const unsigned so = tile_base + f * sf * 8u;
 #pragma unroll
     for (int q = 0; q < L::CPW; ++q) {
       const int c = wave + SH::WPG * q;
-      if (L::CPW * SH::WPG != L::NCHUNK && c >= L::NCHUNK) break;   // wave-uniform
+      if (!chunk_exists(q)) break;   // wave-uniform
       const unsigned vo = OFFS_LDS ? offs[q * SH::NT + wave * 64 + lane] : voff[q];
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr_t)(dst + c * L::CHUNK), 16, vo, so, 0, 0);
     }
