@@ -93,6 +93,9 @@ CASES_RHS = [
                                                None, 1 / 32, 1)),
     ("bl-pert-ragged-o8-upwind", lambda: I.Workload("blp", I.workload(3).params, bl_grid((45, 20, 13), 5),
                                                     None, 1 / 32, 1)),
+    # a 3-column last tile in x at either tile width
+    ("bl-pert-ragged-o8-narrow-tail", lambda: I.Workload("blp", I.workload(3).params, bl_grid((67, 11, 9), 5),
+                                                         None, 1 / 32, 1)),
 ]
 
 
@@ -516,11 +519,17 @@ def test_batched_plan_matches_oracle(torch_cuda):
     B.close()
 
 
-@pytest.mark.parametrize("index,n", [(2, (70, 37, 19)), (2, (33, 9, 7)), (3, (45, 20, 13))])
+@pytest.mark.parametrize("index,n", [(2, (70, 37, 19)), (2, (33, 9, 7)), (3, (45, 20, 13)), (3, (67, 11, 9)),
+                                     (3, (36, 17, 6))])
 def test_tile_variants_are_bitwise_identical(torch_cuda, index, n):
     """Every tile variant computes every point with the same arithmetic in
     the same order: the right-hand side and two RK4 steps agree bitwise with
-    variant 0 (ragged extents in x and y, odd nx, both orders)."""
+    variant 0 (ragged extents in x and y, odd nx, both orders).  At order 8
+    the x-outer mixed derivatives move inner stencils across lanes, with the
+    halo columns held by the row-edge lanes of the same row (64-wide tiles)
+    or of the other row of the wave (32-wide tiles); the extents put valid
+    points next to both tile edges and leave narrow last tiles of 3 and 4
+    columns."""
     from paper_1307_6488_amd import chemora as C
     w = I.workload(index)
     grid = bl_grid(n, w.params.ghost)
