@@ -33,18 +33,22 @@ RK4_FLOPS = 24 * 14
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same
 # counters read for a plain 2 GiB device copy (FETCH_SIZE reads half the
 # bytes copied: x2.0; WRITE_SIZE reads them exactly: x1.0).  They hold only
-# for the kernel sources and tile variant they were taken with; otherwise
-# the bench reports traffic as null.
+# for the kernel sources and tile variant they were taken with (one record
+# per tile variant the tuner picks on that workload: their times are within
+# a few per cent, so its choice varies between runs); otherwise the bench
+# reports traffic as null.
 MEASURED_TRAFFIC = {
     "brill-lindquist-128^3-o4-upwind": {
-        "sources_sha256": "e90b303c657cf8021c4dd73a26252f2fa6599f375da4fc633073616147792ed4",
-        "tile": "32x16",
-        "fetch_kib": 1.2183e6, "write_kib": 8.1204e5, "fetch_scale": 2.0, "write_scale": 1.0,
+        "32x8x2": {"sources_sha256": "dcfeafced77f7a44a46f6170cf81583e1091e55e0b9b33411cd9df4dfaa40786",
+            "fetch_kib": 1.0884e6, "write_kib": 8.1150e5, "fetch_scale": 2.0, "write_scale": 1.0},
+        "32x16": {"sources_sha256": "dcfeafced77f7a44a46f6170cf81583e1091e55e0b9b33411cd9df4dfaa40786",
+            "fetch_kib": 1.2074e6, "write_kib": 8.1222e5, "fetch_scale": 2.0, "write_scale": 1.0},
+        "32x4x4": {"sources_sha256": "dcfeafced77f7a44a46f6170cf81583e1091e55e0b9b33411cd9df4dfaa40786",
+            "fetch_kib": 1.2189e6, "write_kib": 8.1141e5, "fetch_scale": 2.0, "write_scale": 1.0},
     },
     "brill-lindquist-pert-192^3-o8-upwind": {
-        "sources_sha256": "e90b303c657cf8021c4dd73a26252f2fa6599f375da4fc633073616147792ed4",
-        "tile": "32x8",
-        "fetch_kib": 6.5887e6, "write_kib": 2.8818e6, "fetch_scale": 2.0, "write_scale": 1.0,
+        "32x8": {"sources_sha256": "dcfeafced77f7a44a46f6170cf81583e1091e55e0b9b33411cd9df4dfaa40786",
+            "fetch_kib": 5.7620e6, "write_kib": 2.8608e6, "fetch_scale": 2.0, "write_scale": 1.0},
     },
 }
 KERNEL_SOURCES = ["stage_kernel.hpp", "stage_common.hpp", "fd_ops.hpp", "stage_o4.hip", "stage_o8.hip"]
@@ -55,6 +59,19 @@ def tile_name(C, variant):
     tx, ty = C.chemora_tile_variant_shape(variant)
     tz = C.chemora_tile_variant_depth(variant)
     return f"{tx}x{ty}" + (f"x{tz}" if tz > 1 else "")
+
+
+def set_tile(C, P, name):
+    """Select the tile variant called `name` for the class of patch P."""
+    v = 0
+    while True:
+        try:
+            if tile_name(C, v) == name:
+                C.chemora_set_tile_variant(P.params, P.patch, v)
+                return v
+        except C.ChemoraError:   # past the last variant id
+            raise SystemExit(f"no tile variant {name}")
+        v += 1
 
 
 def kernel_sources_sha256():
@@ -68,8 +85,8 @@ def kernel_sources_sha256():
 
 
 def measured_traffic(workload, tile):
-    m = MEASURED_TRAFFIC.get(workload)
-    if m is None or m["tile"] != tile or m["sources_sha256"] != kernel_sources_sha256():
+    m = MEASURED_TRAFFIC.get(workload, {}).get(tile)
+    if m is None or m["sources_sha256"] != kernel_sources_sha256():
         return None
     return (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024.0
 
@@ -83,6 +100,8 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the interior edge (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="run the untuned default tile variant")
+    ap.add_argument("--tile", default="", help="run the main workload with this tile variant (e.g. 32x16, "
+                    "32x8x2) instead of the tuner's choice: counter runs per variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-patch batched form")
     ap.add_argument("--no-split", action="store_true", help="skip the 256^3 split-precision comparison")
     ap.add_argument("--no-rk3", action="store_true", help="skip the third-order Runge-Kutta form")
@@ -129,8 +148,11 @@ def main():
     sp = scratch.data_ptr()
     # the autotuner picks the tile variant of this patch's class (outside the
     # timed region; it times stage-2 launches of this patch)
-    variant = C.chemora_tile_variant(P.params, P.patch) if args.no_tune else \
-        C.chemora_tune(P.params, P.patch, sp, None, stream)
+    if args.tile:
+        variant = set_tile(C, P, args.tile)
+    else:
+        variant = C.chemora_tile_variant(P.params, P.patch) if args.no_tune else \
+            C.chemora_tune(P.params, P.patch, sp, None, stream)
     tile = tile_name(C, variant)
 
     def step():

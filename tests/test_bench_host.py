@@ -29,14 +29,13 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_traffic_is_null_once_kernel_sources_change(monkeypatch):
     w = "brill-lindquist-128^3-o4-upwind"
-    tile = bench.MEASURED_TRAFFIC[w]["tile"]
-    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: bench.MEASURED_TRAFFIC[w]["sources_sha256"])
-    assert bench.measured_traffic(w, tile) == pytest.approx(
-        (bench.MEASURED_TRAFFIC[w]["fetch_kib"] * 2.0 + bench.MEASURED_TRAFFIC[w]["write_kib"]) * 1024)
-    assert bench.measured_traffic(w, "64x64") is None
-    assert bench.measured_traffic("no-such-workload", tile) is None
-    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "0" * 64)
-    assert bench.measured_traffic(w, tile) is None
+    for tile, m in bench.MEASURED_TRAFFIC[w].items():
+        monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: m["sources_sha256"])
+        assert bench.measured_traffic(w, tile) == pytest.approx((m["fetch_kib"] * 2.0 + m["write_kib"]) * 1024)
+        assert bench.measured_traffic(w, "64x64") is None
+        assert bench.measured_traffic("no-such-workload", tile) is None
+        monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "0" * 64)
+        assert bench.measured_traffic(w, tile) is None
 
 
 def test_profile_summaries_cite_the_recorded_counters():
@@ -44,9 +43,10 @@ def test_profile_summaries_cite_the_recorded_counters():
     that names the same kernel-sources hash and the same counter readings."""
     prof = os.path.join(ROOT, "profiles")
     texts = [open(os.path.join(prof, f)).read() for f in os.listdir(prof) if f.endswith(".md")]
-    for w, m in bench.MEASURED_TRAFFIC.items():
-        hits = [t for t in texts if m["sources_sha256"] in t]
-        assert hits, f"no profile names the hash recorded for {w}"
-        fetch = f"{int(m['fetch_kib'] / 1e3):,}".replace(",", " ")        # thousands of KiB, e.g. "1 164"
-        write = f"{int(m['write_kib'] / 1e3):,}".replace(",", " ")
-        assert any(fetch in t and write in t for t in hits), (w, fetch, write)
+    for w, recs in bench.MEASURED_TRAFFIC.items():
+        for tile, m in recs.items():
+            hits = [t for t in texts if m["sources_sha256"] in t and tile in t]
+            assert hits, f"no profile names the hash recorded for {w} {tile}"
+            fetch = f"{int(m['fetch_kib'] / 1e3):,}".replace(",", " ")        # thousands of KiB, e.g. "1 164"
+            write = f"{int(m['write_kib'] / 1e3):,}".replace(",", " ")
+            assert any(fetch in t and write in t for t in hits), (w, tile, fetch, write)
