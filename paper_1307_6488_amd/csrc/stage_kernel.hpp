@@ -262,6 +262,70 @@ struct CrossLayout {
   }
 };
 
+// Cross layout at order 4 (any tile depth): what the axis stencils of a
+// grid function without mixed derivatives read.  The TZ tile planes whole
+// (rows [-R, TY-1+R], pitch P: the x and y taps, at the full layout's
+// in-plane offsets), padded to whole chunks, then the TZ + 2R planes dz =
+// -R .. TZ-1+R holding only the tile's TX x TY points (pitch TX: the z taps,
+// at zoff(dz) from the column anchor of the work-item's plane).  The tile
+// planes' own points are staged twice, so that every z tap sits at a
+// compile-time offset whatever the wave's plane.
+template <int R, class SH>
+struct CrossLayoutZ {
+  static constexpr int TX = SH::TX, TY = SH::TY, TZ = SH::TZ;
+  static constexpr int P = TX + 2 * R, ROWS = TY + 2 * R, PLANE = P * ROWS;
+  static constexpr int CHUNK = 128;
+  static constexpr int NCHUNK0 = (TZ * PLANE + CHUNK - 1) / CHUNK;   // chunks of the tile planes
+  static constexpr int Z0 = NCHUNK0 * CHUNK;
+  static constexpr int NPL = TZ + 2 * R;
+  static constexpr int CPP = TX * TY / CHUNK;                        // chunks per column plane
+  static constexpr int SIZE = Z0 + NPL * TX * TY;
+  static constexpr int NCHUNK = SIZE / CHUNK;
+  static constexpr int CPW0 = (NCHUNK0 + SH::WPG - 1) / SH::WPG;     // tile-plane chunks per wave (at most)
+  static constexpr int CMIN = NCHUNK / SH::WPG;                      // chunks per wave (at least)
+  static_assert(TX * TY % CHUNK == 0 && SH::WPG % CPP == 0, "a wave's column chunks share one place in their plane");
+  static_assert(P % 2 == 0, "a lane's pair of doubles must not straddle rows");
+  __host__ __device__ static constexpr int anchor(int xr, int yr, int tz) { return tz * PLANE + yr * P + xr; }
+  __host__ __device__ static constexpr int off(int dx, int dy) { return (dy + R) * P + (dx + R); }
+  __host__ __device__ static constexpr int col_anchor(int xr, int yr, int tz) {
+    return Z0 + (tz + R) * TX * TY + yr * TX + xr;
+  }
+  __host__ __device__ static constexpr int zoff(int dz) { return dz * TX * TY; }
+  // the tile-relative point stored at LDS double idx (padding: (0, 0, 0))
+  __host__ __device__ static constexpr void decode(int idx, int& x, int& y, int& dz) {
+    if (idx < Z0) {
+      if (idx >= TZ * PLANE) {
+        x = 0; y = 0; dz = 0;
+        return;
+      }
+      const int q = idx / PLANE, r = idx - q * PLANE, row = r / P;
+      dz = q;
+      y = row - R;
+      x = r - row * P - R;
+      return;
+    }
+    const int r = idx - Z0, j = r / (TX * TY), e = r - j * TX * TY;
+    dz = j - R;
+    y = e / TX;
+    x = e - y * TX;
+  }
+  // the point a staging lane loads for LDS double idx, clamped as in the
+  // full layouts (tile-plane pairs start at odd columns -R + 2m, column
+  // pairs at even ones)
+  __host__ __device__ static constexpr void stage_point(int idx, int i0, int j0, int k0, int nx, int ny, int nz,
+                                                        int& x, int& y, int& dz) {
+    decode(idx, x, y, dz);
+    const int xmax = nx - 1 + R - i0, ymax = ny - 1 + R - j0, zmax = nz - 1 + R - k0;
+    y = y < ymax ? y : ymax;
+    dz = dz < zmax ? dz : zmax;
+    if (idx < Z0) {
+      if (x > xmax) x = xmax - 1;
+    } else {
+      if (x >= xmax) x = xmax - 1;
+    }
+  }
+};
+
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 // the double v of lane src mod 64 of the wave (every lane active)
@@ -329,7 +393,7 @@ __device__ __forceinline__ void wait_staged(int m) {
 // work-item of the work-group must call it (it synchronises); it ends with a
 // barrier, so the buffers may be reused right after.
 template <int ORDER, bool UPWIND, int R, int NB, bool BOUND, bool OFFS_LDS, bool PARK, class SH, typename T,
-          bool KOQ, bool AXIS_GROUPS>
+          bool KOQ, bool AXIS_GROUPS, bool CROSSZ>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* const (&bufs)[NB], unsigned* offs,
                                            double* park) {
   // T: the arithmetic type of stencil combinations and algebra -- double, or
@@ -389,6 +453,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     // slots, so no barrier is involved) and free their registers
     if (OFFS_LDS) offs[q * SH::NT + wave * 64 + lane] = voff[q];
   }
+  // CROSSZ (order 4, FP64 with parked offsets): the 13 grid functions
+  // without mixed derivatives stage CrossLayoutZ; its tile-plane chunks have
+  // offsets of their own, parked after the full layout's
+  using LZ = CrossLayoutZ<R, SH>;
+  if constexpr (CROSSZ) {
+#pragma unroll
+    for (int q = 0; q < LZ::CPW0; ++q) {
+      int x, y, dz;
+      LZ::stage_point((wave_t + SH::WPG * q) * LZ::CHUNK + 2 * lane_t, i0, j0, k0, G.nx, G.ny, G.nz, x, y, dz);
+      offs[(L::CPW + q) * SH::NT + wave * 64 + lane] = (unsigned)(dz * (int)sz + y * (int)sy + x + (int)bias) * 8u;
+    }
+  }
   const unsigned tile_base = ((k0 + gg) * sz + (j0 + gg) * sy + i0 + gg + XB) * 8u - bias * 8u;
   // whether chunk wave + WPG q exists: with q a compile-time constant the
   // wave-uniform test remains only for the last q, so that the loads before
@@ -416,6 +492,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // through the scalar offset.
   constexpr bool CROSS = AXIS_GROUPS && NB == 1 && ORDER == 8 && SH::TZ == 1;
   using LC = std::conditional_t<CROSS, CrossLayout<R, RM, SH>, L>;
+  using XKIND = std::integral_constant<int, CROSSZ ? 2 : (CROSS ? 1 : 0)>;
   auto issue_cross = [&](int f, double* dst) __attribute__((always_inline)) {
     if constexpr (CROSS) {
       const unsigned so = tile_base + f * sf * 8u;
@@ -444,6 +521,46 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
         int dz = (j & 1) ? -(j / 2 + 1) : j / 2 + 1;
         dz = dz < zmax ? dz : zmax;
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr_t)(dst + c * L::CHUNK), 16, vo,
+                                                 so + (unsigned)(dz + R) * sz * 8u, 0, 0);
+      }
+    }
+  };
+
+  // CROSSZ staging of grid function f into dst: the tile-plane chunks with
+  // their parked offsets, then the column chunks, whose per-lane part is the
+  // same in every plane (the plane enters through the scalar offset, as
+  // (dz + R) sz >= 0).  Wave-uniform tests remain only where a range of
+  // chunks ends inside a round of the waves.
+  auto issue_crossz = [&](int f, double* dst) __attribute__((always_inline)) {
+    if constexpr (CROSSZ) {
+      const unsigned so = tile_base + f * sf * 8u;
+      auto in_range = [&](int q, int lo, int hi) __attribute__((always_inline)) {
+        const int c = wave + SH::WPG * q;
+        const bool above = SH::WPG * q >= lo ? true : (SH::WPG * (q + 1) <= lo ? false : c >= lo);
+        const bool below = SH::WPG * (q + 1) <= hi ? true : (SH::WPG * q >= hi ? false : c < hi);
+        return above && below;
+      };
+#pragma unroll
+      for (int q = 0; q < LZ::CPW0; ++q) {
+        if (!in_range(q, 0, LZ::NCHUNK0)) continue;
+        const int c = wave + SH::WPG * q;
+        const unsigned vo = offs[(L::CPW + q) * SH::NT + wave * 64 + lane];
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr_t)(dst + c * LZ::CHUNK), 16, vo, so, 0, 0);
+      }
+      const int pos = ((wave - LZ::NCHUNK0) % LZ::CPP + LZ::CPP) % LZ::CPP;
+      const int e = pos * LZ::CHUNK + 2 * lane;
+      int y = e / SH::TX, x = e - y * SH::TX;
+      const int xmax = G.nx - 1 + R - i0, ymax = G.ny - 1 + R - j0, zmax = G.nz - 1 + R - k0;
+      y = y < ymax ? y : ymax;
+      if (x >= xmax) x = xmax - 1;
+      const unsigned vo = (unsigned)(y * (int)sy + x + R * ((int)sy + 1)) * 8u;
+#pragma unroll
+      for (int q = 0; q < (LZ::NCHUNK + SH::WPG - 1) / SH::WPG; ++q) {
+        if (!in_range(q, LZ::NCHUNK0, LZ::NCHUNK)) continue;
+        const int c = wave + SH::WPG * q;
+        int dz = (c - LZ::NCHUNK0) / LZ::CPP - R;
+        dz = dz < zmax ? dz : zmax;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr_t)(dst + c * LZ::CHUNK), 16, vo,
                                                  so + (unsigned)(dz + R) * sz * 8u, 0, 0);
       }
     }
@@ -485,6 +602,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     asm volatile("" : "+v"(anc));
     return Taps{cur, anc};
   };
+  // the taps of a CROSSZ buffer: its tile planes hold the x and y taps at
+  // the full layout's in-plane offsets, from the work-item's plane
+  auto cross_ops = [&](const double* cur) __attribute__((always_inline)) {
+    if constexpr (!CROSSZ) {
+      return make_ops(cur);
+    } else {
+      int anc = LZ::anchor(xr, yr, tz) - (L::off(0, 0, 0) - LZ::off(0, 0));
+      asm volatile("" : "+v"(anc));
+      return Taps{cur, anc};
+    }
+  };
   // Taps along the three axes through the point serve a phase's first and
   // pure second derivatives, advection and dissipation.  A phase reads all
   // 1 + 6R of them from LDS in one group into registers, so a work-item
@@ -523,6 +651,27 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       r.v[1][R + o - 1] = tap(0, o, 0);
       r.v[2][R - o] = tap(0, 0, -o);
       r.v[2][R + o - 1] = tap(0, 0, o);
+    }
+    keep(r.c);
+    keep(r.v);
+    return r;
+  };
+  // the same from a CROSSZ buffer (z taps from the column planes)
+  auto phase_src_cross = [&](const Taps& t0) __attribute__((always_inline)) {
+    const Taps tap = t0.fresh();
+    int az = LZ::col_anchor(xr, yr, tz);
+    asm volatile("" : "+v"(az));
+    Axes r;
+    r.t = t0;
+    r.c = tap(0, 0, 0);
+#pragma unroll
+    for (int o = 1; o <= R; ++o) {
+      r.v[0][R - o] = tap(-o, 0, 0);
+      r.v[0][R + o - 1] = tap(o, 0, 0);
+      r.v[1][R - o] = tap(0, -o, 0);
+      r.v[1][R + o - 1] = tap(0, o, 0);
+      r.v[2][R - o] = t0.cur[az + LZ::zoff(-o)];
+      r.v[2][R + o - 1] = t0.cur[az + LZ::zoff(o)];
     }
     keep(r.c);
     keep(r.v);
@@ -826,7 +975,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
   // cross: the buffer holds the CrossLayout (CROSS phases): z taps at the
   // column anchor
   auto stencils = [&](auto tag, const Taps& t0, auto d1, auto d2, auto cross) __attribute__((always_inline)) {
-    constexpr bool XC = decltype(cross)::value;
+    // cross: 0 the full layout, 1 CrossLayout (order 8), 2 CrossLayoutZ (order 4)
+    constexpr int XK = int(decltype(cross)::value);
+    constexpr bool XC = XK == 1, XZ = XK == 2;
     // dependent on the call, so that only cross calls name CrossLayout's members
     using LX = std::conditional_t<XC, LC, CrossLayout<R, RM, Shape<32, 4, 1>>>;
     using TC = decltype(tag);
@@ -842,13 +993,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     out.src.t = t0;
     if constexpr (!AXIS_GROUPS) {
       static_assert(!XC, "the cross layout is read axis by axis");
-      const auto src = phase_src(t0);
+      const auto src = [&]() __attribute__((always_inline)) {
+        if constexpr (XZ)
+          return phase_src_cross(t0);
+        else
+          return phase_src(t0);
+      }();
       if constexpr (W1 && W2)
         D12all(tag, src, *d1, *d2);
       else if constexpr (W1)
         D1all(tag, src, *d1);
       out.ad = advdiss(tag, src);
     } else {
+      static_assert(!XZ, "CrossLayoutZ is read in one group");
       TC st[2] = {TC(0.0), TC(0.0)};
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
@@ -974,7 +1131,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
         lds_barrier();
       }
     } else {
-      if (p + NB - 1 < nphase) issue(seq_gf(p + NB - 1), bufs[(p + NB - 1) % NB]);
+      if (p + NB - 1 < nphase) {
+        if (CROSSZ && p + NB - 1 >= 11)
+          issue_crossz(seq_gf(p + NB - 1), bufs[(p + NB - 1) % NB]);
+        else
+          issue(seq_gf(p + NB - 1), bufs[(p + NB - 1) % NB]);
+      }
     }
   };
   auto sync = [&](int p) __attribute__((always_inline)) {
@@ -983,7 +1145,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       if (CROSS && p >= 11) wait_vm<0>();
       if (p >= 0) lds_barrier();
     } else {
-      wait_staged<NB, L::CMIN>(min(p + NB - 1, nphase - 1) - (p + 1));
+      // the phases issued after the next one hold at least C chunks per
+      // wave each: fewer where CROSSZ phases are among them
+      const int m = min(p + NB - 1, nphase - 1) - (p + 1);
+      if (CROSSZ && p + NB - 1 >= 11)
+        wait_staged<NB, (LZ::CMIN < L::CMIN ? LZ::CMIN : L::CMIN)>(m);
+      else
+        wait_staged<NB, L::CMIN>(m);
       lds_barrier();
     }
   };
@@ -1286,7 +1454,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const int p = 11 + c;
     begin(p);
     T dx[3];
-    const auto ps = stencils(T(), make_ops(buf_of(p)), &dx, nullptr, std::bool_constant<CROSS>());
+    const auto ps = stencils(T(), cross_ops(buf_of(p)), &dx, nullptr, XKIND());
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const T d = dx[ax];
@@ -1333,7 +1501,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const Epi ex[3] = {epi_load(gXT), epi_load(gXT + 1), epi_load(gXT + 2)};
     begin(14);
     T dK[3];
-    const auto ps = stencils(T(), make_ops(buf_of(14)), &dK, nullptr, std::bool_constant<CROSS>());
+    const auto ps = stencils(T(), cross_ops(buf_of(14)), &dK, nullptr, XKIND());
     emit(gK, ps.ad.rhs(-chi * trDDa + alpha * (AA + K * K * (T(1.0) / T(3.0)))), e);
     if constexpr (PARK) {
 #pragma unroll
@@ -1366,7 +1534,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
     const int p = 15 + s;
     const Epi e = epi_load(gAT + s);
     begin(p);
-    const auto ps = stencils(T(), make_ops(buf_of(p)), nullptr, nullptr, std::bool_constant<CROSS>());
+    const auto ps = stencils(T(), cross_ops(buf_of(p)), nullptr, nullptr, XKIND());
     const int i = SI(s), jj = SJ(s);
     T la = T(0.0), aa = T(0.0);
 #pragma unroll
@@ -1390,7 +1558,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, int t, double* co
       const Epi e = epi_load(gB + c);
       const T Bc = T(val(gB + c));
       begin(p);
-      const auto ps = stencils(T(), make_ops(buf_of(p)), nullptr, nullptr, std::bool_constant<CROSS>());
+      const auto ps = stencils(T(), cross_ops(buf_of(p)), nullptr, nullptr, XKIND());
       emit(gB + c, ps.ad.rhs(xsrc[c] - gauge.eta * Bc), e);
       sync(p);
     }
@@ -1421,29 +1589,6 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
   using SH = Shape<TX, WPG, TZ>;
   using L = LdsLayout<R, ORDER / 2, SH>;
   static_assert(NB >= 1 && NB <= 5, "staging depth");
-  constexpr int WG_PER_CU = (OCC * 4) / WPG > 1 ? (OCC * 4) / WPG : 1;
-  constexpr int LDS_STAGE = NB * L::SIZEP * 8, LDS_OFFS = L::CPW * SH::NT * 4;
-  // FP64 with two waves per SIMD keeps the per-lane staging offsets in LDS
-  // where they fit (its 256 registers are otherwise exhausted); FP32 algebra
-  // needs ~156
-  constexpr bool OFFS_LDS = OCC == 2 && sizeof(T) == 8 && WG_PER_CU * (LDS_STAGE + LDS_OFFS) <= 160 * 1024;
-  constexpr int LDS_BASE = LDS_STAGE + (OFFS_LDS ? LDS_OFFS : 0);
-  static_assert(WG_PER_CU * LDS_BASE <= 160 * 1024, "LDS");
-  // two waves per SIMD park six accumulators in LDS where they fit (beside
-  // the persistent form's tile slot)
-  constexpr bool PARK = OFFS_LDS && WG_PER_CU * (LDS_BASE + 6 * SH::NT * 8 + (PERSIST ? 16 : 0)) <= 160 * 1024;
-  // separate arrays, so the compiler can tell the buffers' staging loads apart
-  __shared__ double b0[L::SIZEP];
-  __shared__ double b1[NB > 1 ? L::SIZEP : 1];
-  __shared__ double b2[NB > 2 ? L::SIZEP : 1];
-  __shared__ double b3[NB > 3 ? L::SIZEP : 1];
-  __shared__ double b4[NB > 4 ? L::SIZEP : 1];
-  __shared__ unsigned offs[OFFS_LDS ? L::CPW * SH::NT : 1];
-  __shared__ double park[PARK ? 6 * SH::NT : 1];
-  double* const all[5] = {b0, b1, b2, b3, b4};
-  double* bufs[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) bufs[i] = all[i];
   constexpr bool BOUND = ORDER >= 8 || OCC >= 2;
   // order 8 at two waves per SIMD and split precision at three read their
   // axis taps axis by axis (256 and 168 registers per lane)
@@ -1456,6 +1601,39 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
   constexpr bool AXIS_GROUPS = (ORDER >= 8 && OCC >= 2) ||
                                (CHEMORA_SPLIT_AXIS_GROUPS && std::is_same<T, float>::value && OCC >= 3) ||
                                (CHEMORA_O4_AXIS_GROUPS && ORDER == 4);
+  constexpr int WG_PER_CU = (OCC * 4) / WPG > 1 ? (OCC * 4) / WPG : 1;
+  constexpr int LDS_STAGE = NB * L::SIZEP * 8, LDS_OFFS = L::CPW * SH::NT * 4;
+  // FP64 with two waves per SIMD keeps the per-lane staging offsets in LDS
+  // where they fit (its 256 registers are otherwise exhausted); FP32 algebra
+  // needs ~156
+  constexpr bool OFFS_LDS = OCC == 2 && sizeof(T) == 8 && WG_PER_CU * (LDS_STAGE + LDS_OFFS) <= 160 * 1024;
+  constexpr int LDS_BASE = LDS_STAGE + (OFFS_LDS ? LDS_OFFS : 0);
+  static_assert(WG_PER_CU * LDS_BASE <= 160 * 1024, "LDS");
+  // two waves per SIMD park six accumulators in LDS where they fit (beside
+  // the persistent form's tile slot)
+  constexpr bool PARK = OFFS_LDS && WG_PER_CU * (LDS_BASE + 6 * SH::NT * 8 + (PERSIST ? 16 : 0)) <= 160 * 1024;
+  // order 4, FP64 with parked offsets and a staging pipeline: the 13 grid
+  // functions without mixed derivatives stage CrossLayoutZ, whose tile-plane
+  // chunk offsets are parked too, where that still fits
+#ifndef CHEMORA_CROSS_O4
+#define CHEMORA_CROSS_O4 1
+#endif
+  constexpr int LDS_OFFS_Z = CrossLayoutZ<R, SH>::CPW0 * SH::NT * 4;
+  constexpr bool CROSSZ = CHEMORA_CROSS_O4 && ORDER == 4 && OFFS_LDS && PARK && NB >= 2 &&
+                          !AXIS_GROUPS &&
+                          WG_PER_CU * (LDS_BASE + LDS_OFFS_Z + 6 * SH::NT * 8 + (PERSIST ? 16 : 0)) <= 160 * 1024;
+  // separate arrays, so the compiler can tell the buffers' staging loads apart
+  __shared__ double b0[L::SIZEP];
+  __shared__ double b1[NB > 1 ? L::SIZEP : 1];
+  __shared__ double b2[NB > 2 ? L::SIZEP : 1];
+  __shared__ double b3[NB > 3 ? L::SIZEP : 1];
+  __shared__ double b4[NB > 4 ? L::SIZEP : 1];
+  __shared__ unsigned offs[OFFS_LDS ? (L::CPW + (CROSSZ ? CrossLayoutZ<R, SH>::CPW0 : 0)) * SH::NT : 1];
+  __shared__ double park[PARK ? 6 * SH::NT : 1];
+  double* const all[5] = {b0, b1, b2, b3, b4};
+  double* bufs[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) bufs[i] = all[i];
   if constexpr (!PERSIST) {
     int t = xcd_tile(blockIdx.x, gridDim.x);
     StageArgs a = a1;
@@ -1464,7 +1642,7 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
       a = uniform_args(bt.args + p);
       t -= uniform(table_load(bt.tile_start, p));
     }
-    stage_tile<ORDER, UPWIND, R, NB, BOUND, OFFS_LDS, PARK, SH, T, KOQ, AXIS_GROUPS>(a, t, bufs, offs, park);
+    stage_tile<ORDER, UPWIND, R, NB, BOUND, OFFS_LDS, PARK, SH, T, KOQ, AXIS_GROUPS, CROSSZ>(a, t, bufs, offs, park);
   } else {
     // One work-item fetches each tile and hands it over through LDS.  Every
     // work-item reads the slot before stage_tile's first barrier, and the
@@ -1481,7 +1659,7 @@ void stage_kernel(StageArgs a1, BatchTable bt) {
       if (t < 0) break;
       const int p = batch_patch(bt, t);
       const StageArgs a = uniform_args(bt.args + p);
-      stage_tile<ORDER, UPWIND, R, NB, BOUND, OFFS_LDS, PARK, SH, T, KOQ, AXIS_GROUPS>(a, t - uniform(table_load(bt.tile_start, p)), bufs,
+      stage_tile<ORDER, UPWIND, R, NB, BOUND, OFFS_LDS, PARK, SH, T, KOQ, AXIS_GROUPS, CROSSZ>(a, t - uniform(table_load(bt.tile_start, p)), bufs,
                                                                           offs, park);
     }
     // the last work-group to finish leaves the counters zeroed for the next
